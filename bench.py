@@ -1,0 +1,178 @@
+"""Throughput benchmark of the coupled porous cascaded LB step on one MI355X.
+
+Workload: natural convection in a square porous cavity, 4096 x 4096 nodes,
+Ra = 1e6, Da = 1e-4, porosity 0.4, Pr = 1, J = sigma = 1, Ergun F_phi, FP32
+deviation storage (FP16 with --storage f16).  One "step" is one time step
+of the whole path: pull streaming + macroscopic values + boundary
+reconstruction + D2Q9 and D2Q5 collisions + store, with the FP64 residual,
+mass and Nusselt reductions every 100 steps (their cost is inside the timed
+region).  Inputs (populations) are resident in HBM before timing starts.
+
+Prints one JSON line.  The `roofline` object prices the step kernel against
+HBM: algorithmic bytes per node update are 14 populations read + written
+(112 B in FP32, 56 B in FP16).  `cpu_baseline` times the FP64 CPU oracle on
+a few steps of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("coupled CLB MLUPS & %HBM BW; time-to-steady-state (Nu err≤1e-4) plain vs learned")
+HBM_PEAK_GBS = 8000.0
+REDUCE_EVERY = 100
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("paper_2110_05943_amd/csrc/clb_kernels.hip", "paper_2110_05943_amd/csrc/clb_internal.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage, n):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    rec = data.get("%s_%d" % (storage, n))
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(case, steps):
+    """The FP64 oracle (test infrastructure) on `steps` steps of the workload."""
+    import numpy as np
+    from paper_2110_05943_amd import inputs
+    from tests.cases import oracle_lattice
+    n = case["nx"]
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(inputs.cavity_initial_T(n, seed=1))
+    t0 = time.perf_counter()
+    lat.step(steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    assert np.isfinite(lat.f[:9]).all()
+    return {"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d steps of the same %dx%d cavity, FP64, OpenMP, %.1f s" % (steps, n, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--storage", choices=("f32", "f16", "mixed"), default="f32")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="time launch shapes first")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy 10 times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_probe:
+        x = torch.ones(2 ** 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        y.copy_(x)
+        e0.record()
+        for _ in range(10):
+            y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps({"copy_bytes_per_launch": 2 * x.numel() * 4,
+                          "copy_GBps": round(2 * x.numel() * 4 / ms / 1e6, 1)}), flush=True)
+        return
+    from paper_2110_05943_amd import Solver, inputs
+    from tests.cases import cavity
+
+    n = args.n
+    case = cavity(n, Ra=1e6, Da=1e-4, phi=0.4, Pr=1.0, storage=args.storage)
+    s = Solver(case, device="cuda:0")
+    s.set_state(0, inputs.cavity_initial_T(n, seed=1))
+    if args.autotune:
+        s.autotune()
+    shape = s.get_launch()
+    s.step(args.warmup)
+    s.synchronize()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    events = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < K:
+        chunk = min(REDUCE_EVERY, K - done)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(chunk)
+        e1.record(s.stream)
+        events.append((e0, e1, chunk))
+        done += chunk
+        if done % REDUCE_EVERY == 0 or done == K:
+            ru, rT, mass = s.residual(0)
+            nu = s.nusselt(0, 0)
+    s.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    kernel_ms = sum(a.elapsed_time(b) for a, b, _ in events) / K
+    from paper_2110_05943_amd._binding import BYTES_PER_UPDATE
+    bytes_per_lu = BYTES_PER_UPDATE[args.storage]
+    nodes = n * n
+    achieved = bytes_per_lu * nodes / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.storage, n)
+    mlups = nodes * K / wall / 1e6
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / K, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f64 arithmetic, f32 storage", "f16": "f32 arithmetic, f16 storage",
+                  "mixed": "f32 arithmetic, f16 flow / f32 temperature storage"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": "porous cavity natural convection %dx%d, Ra=1e6, Da=1e-4, "
+                               "phi=0.4, Pr=1, %s deviation storage" % (n, n, args.storage),
+                   "grid": [n, n], "storage": args.storage, "launch_shape": list(shape),
+                   "reductions_every": REDUCE_EVERY},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "step_kernel", "kernel_us": round(kernel_ms * 1e3, 2),
+                     "bytes_per_node_update": bytes_per_lu},
+        "state_check": {"res_u": ru, "res_T": rT, "mass": mass, "nu_hot": nu},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

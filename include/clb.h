@@ -1,0 +1,225 @@
+/*
+ * clb.h - C ABI of the MI355X (gfx950) porous-media cascaded lattice
+ * Boltzmann library.
+ *
+ * The library advances one or many independent 2-D domains ("cavities") of
+ * the coupled method of Feng, Liu & He, "Numerical simulations of convection
+ * heat transfer in porous media using a cascaded lattice Boltzmann method"
+ * (arXiv:2110.05943):
+ *   - flow: D2Q9 central-moment collision whose shift matrix carries the
+ *     porosity (Section 2.1, Eqs. 6-23, A1) with the generalized non-Darcy
+ *     (Brinkman-Forchheimer) force of Eq. 4;
+ *   - temperature: D2Q5 central-moment collision whose shift matrix carries the
+ *     heat-capacity ratio sigma (Section 2.2, Eqs. 24-37, A2);
+ *   - streaming (Eqs. 18, 35), boundary nodes by non-equilibrium
+ *     extrapolation, and FP64 reductions for the Nusselt number (Section 3.2),
+ *     residual and mass.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns clb_status; CLB_OK is 0.  No call throws.
+ *   - Out-parameters are left untouched when a call fails.
+ *   - The caller owns all device memory: clb_create receives one device
+ *     workspace of clb_workspace_bytes() bytes and never allocates device
+ *     memory itself.  The caller also owns the HIP stream (a hipStream_t passed
+ *     as void*); all device work is enqueued on it.  The workspace must stay
+ *     allocated until clb_destroy.
+ *   - Host arrays of nodal fields are row-major (ny rows of nx values, x
+ *     fastest, index y*nx + x), in FP64.  Walls lie on the outermost nodes,
+ *     so nx and ny count wall nodes and the characteristic length of a square
+ *     cavity is L = nx - 1.
+ *   - A context may be used by one host thread at a time.  Calls that return
+ *     host values synchronize the stream.
+ */
+#ifndef CLB_H
+#define CLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CLB_OK = 0,
+  CLB_ERR_ARG = 1,        /* invalid argument or parameter set                 */
+  CLB_ERR_HIP = 2,        /* a HIP runtime call failed (launch, copy, fault)   */
+  CLB_ERR_WORKSPACE = 3,  /* workspace too small or misaligned (256 B)         */
+  CLB_ERR_DIVERGED = 4,   /* a non-finite value was found in the fields        */
+  CLB_ERR_STATE = 5       /* call not valid in the current state               */
+} clb_status;
+
+/* Side kinds (index 0..3 = W, E, S, N). */
+enum {
+  CLB_PERIODIC = 0,       /* the axis wraps; both sides of an axis must agree  */
+  CLB_WALL_T = 1,         /* wall, velocity (bc_u, bc_v), temperature bc_T      */
+  CLB_WALL_ADIABATIC = 2, /* wall, velocity (bc_u, bc_v), zero normal gradient  */
+  CLB_INLET = 3,          /* parabolic normal inflow of mean inlet_U, T = bc_T  */
+  CLB_OUTLET = 4          /* rho = 1, velocity and T taken from the inner node  */
+};
+
+enum { CLB_WEST = 0, CLB_EAST = 1, CLB_SOUTH = 2, CLB_NORTH = 3 };
+
+/* Storage of the populations in device memory.  Every mode stores the
+ * deviation of each population from its rest value and rounds stochastically
+ * when narrowing (unbiased rounding; bit-reproducible from the step count).
+ *   CLB_STORE_F32:   14 FP32 planes (112 B per node update), FP64 arithmetic;
+ *   CLB_STORE_F16:   14 FP16 planes (56 B), FP32 arithmetic;
+ *   CLB_STORE_MIXED: 9 FP16 flow planes and 5 FP32 temperature planes (76 B),
+ *                    FP32 arithmetic. */
+enum { CLB_STORE_F32 = 0, CLB_STORE_F16 = 1, CLB_STORE_MIXED = 2 };
+
+/* How the lattice parameters follow from the dimensionless groups. */
+enum {
+  CLB_SCALE_CAVITY = 0,   /* relaxation rates of Eq. 46, u_c = Ma c_s (Section 3.2) */
+  CLB_SCALE_CHANNEL = 1   /* 1/s_v = 1/2 + J H u_ref/(c_s^2 Re), Ra gives g beta (Section 3.1) */
+};
+
+/*
+ * Parameters of one domain.  A field left at 0 takes the paper's default or is
+ * derived (Section 3: J = 1, varpi = 1/4, s0 = s1 = 1, s3 = 1.2,
+ * s4 = 1.8, zeta_T = zeta_e = zeta_nu = 1; Eq. 46 or the channel relation for
+ * s_v and zeta_alpha; Eq. 5 for F_phi).  The bulk rate s_b defaults to 1.5:
+ * the paper's value is garbled, and the reading s_b = s_v makes the collision
+ * linearly unstable for s_v < 1.19.  Call clb_params_default() first.
+ */
+typedef struct clb_params {
+  int32_t nx, ny;            /* nodes including wall nodes; >= 4 on a walled axis    */
+  int32_t bc[4];             /* side kinds W, E, S, N                                */
+  double bc_u[4], bc_v[4];   /* wall velocity per side (lattice units)               */
+  double bc_T[4];            /* Dirichlet temperature per side                       */
+  double inlet_U;            /* mean velocity of a CLB_INLET side                    */
+
+  /* porous medium (Eqs. 4-5) */
+  double phi;                /* uniform porosity in (0, 1], used when eps == NULL    */
+  const double *eps;         /* optional porosity per node (host, ny*nx); then
+                                K = eps^3 dp^2 / (150 (1-eps)^2) and the Ergun F_phi
+                                are evaluated per node (Eq. 5)                        */
+  double dp;                 /* particle diameter for the eps field                  */
+  double Da;                 /* uniform medium: K = Da Lc^2; <= 0 removes the drag   */
+  double F_phi;              /* uniform medium: < 0 Ergun (Eq. 5), 0 none, > 0 value */
+
+  /* dimensionless groups (Eq. 38) and scaling */
+  int32_t scaling;           /* CLB_SCALE_*                                          */
+  double Ra, Pr, Re, J, Gamma, sigma, Ma;
+  double u_ref;              /* channel scaling: velocity in Re = H u_ref / nu       */
+  double dT;                 /* temperature difference; default 1                   */
+  double T0;                 /* Boussinesq reference temperature; default 0.5        */
+  double g_dir[2];           /* unit vector of gravity; default (0, -1)              */
+  double a[2];               /* external acceleration (lattice units)                */
+
+  /* lattice overrides (> 0 replaces the derived value) */
+  double nu;                 /* fluid viscosity in the Darcy term                    */
+  double s_v, s_b, s1, s3, s4, zeta_a, zeta_e, zeta_nu, varpi;
+  double gbeta;              /* g beta per unit temperature                           */
+
+  double T_init;             /* initial uniform temperature; default T0              */
+  int32_t storage;           /* CLB_STORE_*; must agree over all domains of a context */
+} clb_params;
+
+/* Lattice quantities derived from a clb_params (all lattice units). */
+typedef struct clb_derived {
+  double L;                  /* characteristic length: nx-1 (cavity) or ny-1 (channel) */
+  double s_v, s_b, s1, s3, s4, zeta_a, zeta_e, zeta_nu, varpi;
+  double nu_e, nu, alpha_e;  /* nu_e = c_s^2 (1/s_v - 1/2); alpha_e of Eq. 37       */
+  double gbeta;              /* magnitude of g beta                                  */
+  double K, F_phi;           /* uniform medium values (K = inf without drag)          */
+  double sigma, T0, dT;
+} clb_derived;
+
+typedef struct clb_ctx clb_ctx;
+
+/* Fill *p with the defaults above (square cavity scaling, hot W / cold E walls,
+ * adiabatic S / N walls, phi = 1, no drag, FP32 storage, nx = ny = 0). */
+void clb_params_default(clb_params *p);
+
+/* Derive the lattice parameters of one domain (host only, no device work).
+ * Errors: CLB_ERR_ARG for an invalid parameter set (N < 4 on a walled axis,
+ * phi outside (0, 1], sigma <= 0, a relaxation rate outside (0, 2), varpi
+ * outside (0, 1), mismatched periodic sides). */
+clb_status clb_derive(const clb_params *p, clb_derived *out);
+
+/* Device bytes needed for `count` domains.  Pure host function. */
+clb_status clb_workspace_bytes(const clb_params *p, int32_t count, size_t *bytes);
+
+/* Create a context for `count` domains described by p[0..count-1] on the
+ * caller's device workspace (256-byte aligned, >= clb_workspace_bytes) and
+ * stream.  Host arrays referenced by p (eps) are copied during the call.
+ * All domains start at rest with T = T_init at every node.
+ * Errors: CLB_ERR_ARG, CLB_ERR_WORKSPACE, CLB_ERR_HIP. */
+clb_status clb_create(const clb_params *p, int32_t count, void *d_workspace, size_t bytes,
+                      void *hip_stream, clb_ctx **out);
+
+/* Enqueue n time steps of every active domain on the stream (asynchronous).
+ * The last step also records u, v, T for clb_residual.  A kernel fault is
+ * reported here or by the next synchronizing call (CLB_ERR_HIP). */
+clb_status clb_step(clb_ctx *ctx, int64_t n);
+
+/* Macroscopic fields of one domain at the current time (Eqs. 20-23, 36;
+ * boundary nodes report the values used by their collision).  Any pointer may
+ * be NULL.  Synchronizes. */
+clb_status clb_macros(clb_ctx *ctx, int32_t cavity, double *rho, double *u, double *v,
+                      double *T);
+
+/* Mean Nusselt number on one side (CLB_WEST..CLB_NORTH): second-order
+ * one-sided wall gradient, trapezoid mean over the wall nodes, L and dT of the
+ * domain.  nu_local (nullable) receives one value per wall node.  FP64.
+ * Synchronizes. */
+clb_status clb_nusselt(clb_ctx *ctx, int32_t cavity, int32_t side, double *nu_mean,
+                       double *nu_local);
+
+/* Mean Nusselt number on one side for every domain (count values). */
+clb_status clb_nusselt_all(clb_ctx *ctx, int32_t side, double *nu_mean);
+
+/* Relative change between the last two steps, r_u = |u^n - u^(n-1)|_2 / |u^n|_2
+ * over (u, v), r_T likewise on T, and the mass sum(rho), all in FP64.
+ * Returns CLB_ERR_STATE before the first step and CLB_ERR_DIVERGED (with the
+ * out-values set) when a field holds a non-finite value.  Synchronizes. */
+clb_status clb_residual(clb_ctx *ctx, int32_t cavity, double *res_u, double *res_T,
+                        double *mass);
+
+/* Residuals of all domains: arrays of `count` values; status[i] is CLB_OK or
+ * CLB_ERR_DIVERGED per domain (any array may be NULL). */
+clb_status clb_residual_all(clb_ctx *ctx, double *res_u, double *res_T, double *mass,
+                            int32_t *status);
+
+/* Warm start: set every node of one domain to equilibrium, f = f^eq(rho = 1, u)
+ * (Eq. 19) and g = g^eq(T, u) (Eq. 34).  NULL u or v means 0; T must be given.
+ * Asynchronous with respect to the host (the arrays are copied first). */
+clb_status clb_set_state(clb_ctx *ctx, int32_t cavity, const double *u, const double *v,
+                         const double *T);
+
+/* Choose which domains clb_step advances (active[i] != 0).  Synchronizes. */
+clb_status clb_set_active(clb_ctx *ctx, const uint8_t *active);
+
+/* Byte-exact checkpoint of all population planes and the step counter.
+ * clb_state_bytes gives the size of the host buffer.  Synchronizes. */
+clb_status clb_state_bytes(clb_ctx *ctx, size_t *bytes);
+clb_status clb_get_state(clb_ctx *ctx, void *host_buf, size_t bytes);
+clb_status clb_put_state(clb_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Time steps taken so far. */
+clb_status clb_steps_done(clb_ctx *ctx, int64_t *steps);
+
+/* Launch shape of the step kernel: a work tile is tile_x * tile_y nodes run by
+ * one workgroup of tile_x * tile_y threads (tile_x in {64, 128, 256},
+ * tile_x * tile_y in {64, 128, 256, 512}); `blocks` workgroups loop over the
+ * tiles (0: one workgroup per tile).  Re-captures the step graph. */
+clb_status clb_set_launch(clb_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t blocks);
+clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_t *blocks);
+
+/* Time the step kernel over the candidate launch shapes on the live state
+ * (which the timing runs advance) and keep the fastest.  When cache_path is
+ * non-NULL the choice is read from / appended to that text file, keyed by
+ * storage and domain sizes.  Synchronizes. */
+clb_status clb_autotune(clb_ctx *ctx, const char *cache_path);
+
+/* Release the context (not the workspace, which the caller owns). */
+void clb_destroy(clb_ctx *ctx);
+
+const char *clb_strerror(clb_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLB_H */

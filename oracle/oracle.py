@@ -128,13 +128,15 @@ def neq(T, ux, uy, sigma, varpi=0.25):
 class Lattice:
     """An nx x ny lattice advanced by the oracle.
 
-    Arrays are (ny, nx) with x fastest.  `phi`, `K`, `Fphi` are scalars or
+    Arrays are (ny, nx) with x fastest.  s_b defaults to 1.5, the reading of
+    the bulk rate (garbled in the paper) for which the rest-state collision is
+    linearly stable at every s_v; s_b=None means s_b = s_v.  `phi`, `K`, `Fphi` are scalars or
     (ny, nx) arrays; K = inf removes the Darcy drag.  bc is a 4-tuple of kind
     names for W, E, S, N.
     """
 
     def __init__(self, nx, ny, *, bc=("periodic",) * 4, bc_u=(0, 0, 0, 0), bc_v=(0, 0, 0, 0),
-                 bc_T=(0, 0, 0, 0), inlet_U=0.0, nu, s_v, s_b=None, s0=1.0, s1=1.0, s3=1.2,
+                 bc_T=(0, 0, 0, 0), inlet_U=0.0, nu, s_v, s_b=1.5, s0=1.0, s1=1.0, s3=1.2,
                  s4=1.8, za, zT=1.0, ze=1.0, zn=1.0, varpi=0.25, sigma=1.0, T0=0.5,
                  gb=(0.0, 0.0), a=(0.0, 0.0), accel=None, phi=1.0, K=math.inf, Fphi=0.0,
                  nthreads=0):

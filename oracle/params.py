@@ -9,12 +9,14 @@ Eq. 15 and Eq. 37, and the Ergun/Kozeny-Carman closures of Eq. 5.
 """
 import math
 
+import numpy as np
+
 CS2 = 1.0 / 3.0  # D2Q9 c_s^2 with c = 1 (below Eq. 15)
 
 
 def ergun_F(phi):
     """Inertia coefficient of Eq. 5."""
-    return 1.75 / math.sqrt(150.0 * phi ** 3)
+    return 1.75 / np.sqrt(150.0 * np.asarray(phi, dtype=np.float64) ** 3)
 
 
 def kozeny_carman_K(phi, dp):

@@ -1,0 +1,90 @@
+// Internal definitions shared by the host runtime (clb_api.cpp) and the
+// kernels (clb_kernels.hip) of the GPU library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace clb {
+
+// Side kinds, same numbering as the public CLB_* enum.
+enum : int32_t { kPeriodic = 0, kWallT = 1, kWallAdiabatic = 2, kInlet = 3, kOutlet = 4 };
+
+// Number of planes of one population buffer: 9 (D2Q9) + 5 (D2Q5).
+constexpr int kPlanes = 14;
+// Partial sums per tile / results per domain of the residual reduction:
+// |du|^2, |u|^2, dT^2, T^2, sum(rho - 1), non-finite count, nodes, unused.
+constexpr int kRed = 8;
+
+// One work tile: domain index and the origin of a tile of nodes.
+struct Tile {
+  int32_t cav, x0, y0, pad;
+};
+
+// Per-domain constants and addresses read by every kernel (scalar loads).
+// Populations are stored as deviations from their rest values:
+//   df_i = f_i - w_i,   dg_i = g_i - g_i^eq(T0, u = 0),
+// where T0 here is the storage reference temperature (the initial temperature
+// of the domain); the Boussinesq reference enters through the constant part
+// of the body force (ax, ay).
+struct alignas(16) CavDesc {
+  int32_t nx, ny, pitch, plane;   // plane = ny * pitch elements
+  int32_t bc[4];
+  int32_t has_eps, tile0, ntiles, _pad0;
+  char *A;                        // population planes, 14 planes (9 f, 5 g)
+  char *B;                        // second buffer (A/B double buffering)
+  const float *eps;               // porosity plane (pitch layout) or null
+  float *snap;                    // u, v, theta planes for the residual (pitch layout)
+
+  // Constants in FP64; kernels that compute in FP32 round them once.
+  // boundary values; temperatures as theta = T - T0
+  double bc_u[4], bc_v[4], bc_th[4];
+  double inlet_U;
+
+  // uniform medium (ignored when has_eps)
+  double phi, ip;                 // porosity and 1/phi
+  double cd, cf;                  // phi nu / K and phi F_phi / sqrt(K)
+  // eps field: cd = kc_d (1-eps)^2/eps^2, cf = kc_f (1-eps)/eps^2 (Ergun + Kozeny-Carman)
+  double kc_d, kc_f;
+
+  // D2Q9 relaxation (Eq. 15)
+  double s1c, s1f;                // 1 - s1, 1 - s1/2
+  double sp, sm;                  // s+, s-
+  double svc;                     // 1 - s_v
+  double s3c, s3f;                // 1 - s3, (1 - s3/2)/3
+  double s4;
+
+  // D2Q5 relaxation (Eq. 28); varpi; sigma
+  double zac, zec, znc;           // 1 - zeta_a, 1 - zeta_e, 1 - zeta_nu
+  double hv;                      // varpi / 2 = c_sT^2
+  double sig, isig, sig_mv;       // sigma, 1/sigma, sigma - varpi
+  double T0;
+
+  // body force G = gb * theta + a
+  double gbx, gby, ax, ay;
+  double dT;                      // temperature difference of the Nusselt number
+};
+
+struct LaunchShape {
+  int tile_x, tile_y, blocks;
+};
+
+// Kernel launchers (clb_kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
+                       int32_t grid_tiles, int parity, int write_snap, int storage,
+                       LaunchShape shape, hipStream_t s);
+hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int parity,
+                       const float *uvth /* 3 dense planes or null */, float th_uniform,
+                       int storage, hipStream_t s);
+hipError_t launch_residual(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int parity,
+                           double *partials, int storage, LaunchShape shape, hipStream_t s);
+hipError_t launch_residual_finalize(const CavDesc *descs, int32_t count, const double *partials,
+                                    double *results, hipStream_t s);
+hipError_t launch_macros(const CavDesc *descs, const Tile *tiles, int32_t tile0, int32_t ntiles,
+                         int parity, float *out /* 4 dense planes */, int storage,
+                         LaunchShape shape, hipStream_t s);
+hipError_t launch_nusselt(const CavDesc *descs, int32_t cav0, int32_t ncav, int32_t side,
+                          int parity, double *nu_mean, double *nu_local, int storage,
+                          hipStream_t s);
+
+}  // namespace clb

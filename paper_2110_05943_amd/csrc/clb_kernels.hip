@@ -1,0 +1,804 @@
+// HIP kernels (gfx950) of the porous-media cascaded lattice Boltzmann step.
+//
+// Method: Feng, Liu & He, arXiv:2110.05943, Section 2.  One fused kernel per
+// time step pulls the 9 + 5 populations of every node from the A buffer
+// (streaming, Eqs. 18 and 35), computes the macroscopic values (Eqs. 20-23,
+// 36 and the force of Eq. 4), applies the boundary reconstruction at wall
+// nodes, collides both lattices in central-moment space (D2Q9: Eqs. 11-17 with
+// the porous shift of Eq. 14 and its inverse Eq. A1; D2Q5: Eqs. 28-33 with
+// Eq. 31 and Eq. A2) and writes the post-collision populations to the B
+// buffer.  The two lattices are coupled node-locally (G needs T, the D2Q5
+// shift needs u), so both are handled in one pass: 14 loads and 14 stores per
+// node and step.
+//
+// Storage is the deviation of each population from its rest value
+// (df_i = f_i - w_i, dg_i = g_i - g_i^eq(T0, 0)), so every moment below is the
+// small deviation of a moment from its rest value.
+//
+// Precision.  Kernels are templated on a storage policy: FP32 planes are
+// computed in FP64, FP16 planes in FP32, and the mixed policy keeps the D2Q9
+// planes in FP16 and the D2Q5 planes in FP32.  Stores to a narrower type
+// round stochastically.  In a slowly varying field, a deterministic rounding
+// repeats the same error at a node step after step; that bias accumulates
+// through the long thermal memory of the problem (it dominates the error
+// against an FP64 reference after a few thousand steps), while unbiased
+// rounding leaves noise that the dynamics damp.  FP64 lanes run at the FP32
+// rate on gfx950 (packed FP32 is not used), so the FP64 arithmetic rides
+// under the memory traffic.
+#include <hip/hip_runtime.h>
+
+#include "clb_internal.h"
+
+namespace clb {
+
+// ---------------------------------------------------------------- storage
+
+// FP16 planes hold 2^12 times the deviation, which keeps deviations down to
+// ~1e-8 in the normal FP16 range (the largest, ~0.5, stays far below 65504).
+constexpr float kF16Scale = 4096.0f, kF16Unscale = 1.0f / 4096.0f;
+
+template <typename R>
+__device__ __forceinline__ R ldv(const float *p) {
+  return (R)__builtin_nontemporal_load(p);
+}
+template <typename R>
+__device__ __forceinline__ R ldv(const _Float16 *p) {
+  return (R)((float)__builtin_nontemporal_load(p) * kF16Unscale);
+}
+
+// FP64 -> FP32 with stochastic rounding: 16 random bits are added below the
+// FP32 precision of the value (29 bits lie below a normal FP32 significand),
+// which is then truncated toward zero.
+__device__ __forceinline__ void stv(float *p, double v, uint32_t r) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  u += (unsigned long long)(r & 0xFFFFu) << 13;
+  u &= ~((1ull << 29) - 1ull);
+  __builtin_nontemporal_store((float)__longlong_as_double((long long)u), p);
+}
+// FP32 -> FP16 (scaled) with stochastic rounding: 12 random bits below the
+// FP16 precision (13 bits lie below a normal FP16 significand).
+__device__ __forceinline__ void stv(_Float16 *p, float v, uint32_t r) {
+  uint32_t u = __float_as_uint(v * kF16Scale);
+  u += (r & 0xFFFu) << 1;
+  u &= 0xFFFFE000u;
+  __builtin_nontemporal_store((_Float16)__uint_as_float(u), p);
+}
+
+// FP32 -> FP32: no rounding (mixed storage computes the FP32 planes in FP32).
+__device__ __forceinline__ void stv(float *p, float v, uint32_t) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// Storage policy: element types of the 9 D2Q9 planes (F) and the 5 D2Q5
+// planes (G) and the arithmetic type R.  A population buffer holds the F
+// planes, then the G planes, each plane `plane` elements long.
+template <typename SF, typename SG, typename SR>
+struct Store {
+  using F = SF;
+  using G = SG;
+  using R = SR;
+};
+using StoreF32 = Store<float, float, double>;        // FP32 planes, FP64 arithmetic
+using StoreF16 = Store<_Float16, _Float16, float>;   // FP16 planes, FP32 arithmetic
+using StoreMix = Store<_Float16, float, float>;      // FP16 flow, FP32 temperature
+
+template <typename P>
+__device__ __forceinline__ const typename P::F *fplanes(const char *buf) {
+  return reinterpret_cast<const typename P::F *>(buf);
+}
+template <typename P>
+__device__ __forceinline__ const typename P::G *gplanes(const char *buf, int plane) {
+  return reinterpret_cast<const typename P::G *>(buf + (size_t)9 * plane * sizeof(typename P::F));
+}
+
+// Counter-based random bits: an integer hash (xorshift-multiply finaliser)
+// seeds a xorshift32 sequence; a run is reproducible bit for bit.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
+// ------------------------------------------------------------- node state
+
+// Deviations of the raw moments of Eq. 9 (k00 - 1, k10, k01, k20 - 1/3,
+// k02 - 1/3, k11, k21, k12, k22 - 1/9), the D2Q5 raw moments of Eq. 26
+// (k10, k01, k20 - c_sT^2 T0, k02 - c_sT^2 T0 and sigma theta), and the
+// macroscopic values the collision uses.
+template <typename R>
+struct NodeState {
+  R dr, jx, jy, k20, k02, k11, k21, k12, k22;
+  R n1, n2, n3, n4;
+  R sg;                 // sigma theta = sum of the D2Q5 deviations (conserved)
+  R th;                 // theta = T - T0
+  R rho, ux, uy, umag;
+  R phi, ip, cd, cf;    // medium at this node
+};
+
+// Deviation of the equilibrium raw moments of Eq. 19 from their rest values,
+// for rho = 1 + drho.
+template <typename R>
+__device__ __forceinline__ void meq_dev(R drho, R ux, R uy, R ip, R m[9]) {
+  const R rho = R(1) + drho;
+  const R ux2 = ux * ux, uy2 = uy * uy, rip = rho * ip;
+  const R third = R(1) / R(3);
+  m[0] = drho;
+  m[1] = rho * ux;
+  m[2] = rho * uy;
+  m[3] = drho * third + rip * ux2;
+  m[4] = drho * third + rip * uy2;
+  m[5] = rip * ux * uy;
+  m[6] = rho * uy * third + rip * ux2 * uy;
+  m[7] = rho * ux * third + rip * ux * uy2;
+  m[8] = drho * (R(1) / R(9)) + rip * (ux2 + uy2) * third + rip * ip * ux2 * uy2;
+}
+
+__device__ __forceinline__ bool dirichlet_T(int kind) { return kind == kWallT || kind == kInlet; }
+
+// Porosity-dependent drag coefficients at one node.
+template <typename R>
+__device__ __forceinline__ void medium_at(const CavDesc &d, int idx, R &phi, R &ip, R &cd, R &cf) {
+  if (d.has_eps) {
+    // Eq. 5 (Kozeny-Carman K, Ergun F_phi) folded into phi nu / K and
+    // phi F_phi / sqrt(K):  cd = 150 nu (1-phi)^2 / (phi^2 dp^2),
+    // cf = 1.75 (1-phi) / (phi^2 dp).
+    phi = (R)d.eps[idx];
+    ip = R(1) / phi;
+    const R q = (R(1) - phi) * ip;
+    cd = (R)d.kc_d * q * q;
+    cf = (R)d.kc_f * q * ip;
+  } else {
+    phi = (R)d.phi;
+    ip = (R)d.ip;
+    cd = (R)d.cd;
+    cf = (R)d.cf;
+  }
+}
+
+// Pull the post-streaming populations of node (xs, ys) and reduce them to
+// moments and macroscopic values.  (xs, ys) must have all 8 neighbours inside
+// the domain or across a periodic side.
+template <typename P, typename R = typename P::R>
+__device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__restrict__ buf,
+                                               int xs, int ys, NodeState<R> &st) {
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch, plane = d.plane;
+  int xm = xs - 1, xp = xs + 1, ym = ys - 1, yp = ys + 1;
+  if (d.bc[0] == kPeriodic) {
+    xm = xm < 0 ? xm + nx : xm;
+    xp = xp >= nx ? xp - nx : xp;
+  }
+  if (d.bc[2] == kPeriodic) {
+    ym = ym < 0 ? ym + ny : ym;
+    yp = yp >= ny ? yp - ny : yp;
+  }
+  const int r0 = ys * pitch, rm = ym * pitch, rp = yp * pitch;
+  const typename P::F *A = fplanes<P>(buf);
+  const typename P::G *G = gplanes<P>(buf, plane);
+  // f_i(x) = f_i*(x - e_i), velocities of Eq. 6.
+  const R f0 = ldv<R>(A + r0 + xs);
+  const R f1 = ldv<R>(A + plane + r0 + xm);
+  const R f2 = ldv<R>(A + 2 * plane + rm + xs);
+  const R f3 = ldv<R>(A + 3 * plane + r0 + xp);
+  const R f4 = ldv<R>(A + 4 * plane + rp + xs);
+  const R f5 = ldv<R>(A + 5 * plane + rm + xm);
+  const R f6 = ldv<R>(A + 6 * plane + rm + xp);
+  const R f7 = ldv<R>(A + 7 * plane + rp + xp);
+  const R f8 = ldv<R>(A + 8 * plane + rp + xm);
+  const R g0 = ldv<R>(G + r0 + xs);
+  const R g1 = ldv<R>(G + plane + r0 + xm);
+  const R g2 = ldv<R>(G + 2 * plane + rm + xs);
+  const R g3 = ldv<R>(G + 3 * plane + r0 + xp);
+  const R g4 = ldv<R>(G + 4 * plane + rp + xs);
+
+  // raw moments (Eq. 7 on Eq. 6), as deviations
+  const R p13 = f1 + f3, m13 = f1 - f3, p24 = f2 + f4, m24 = f2 - f4;
+  const R a = f5 + f7, b = f6 + f8, c = f5 - f7, e = f6 - f8;
+  st.k22 = a + b;
+  st.k11 = a - b;
+  st.k21 = c + e;
+  st.k12 = c - e;
+  st.jx = m13 + st.k12;
+  st.jy = m24 + st.k21;
+  st.k20 = p13 + st.k22;
+  st.k02 = p24 + st.k22;
+  st.dr = f0 + (p13 + p24 + st.k22);
+  // D2Q5 raw moments (Eq. 24); theta from Eq. 36
+  st.n1 = g1 - g3;
+  st.n2 = g2 - g4;
+  st.n3 = g1 + g3;
+  st.n4 = g2 + g4;
+  st.sg = g0 + (st.n3 + st.n4);
+  st.th = st.sg * (R)d.isig;
+
+  medium_at(d, r0 + xs, st.phi, st.ip, st.cd, st.cf);
+  // Eqs. 20-23: rho, the temporal velocity v and the explicit velocity u.
+  st.rho = R(1) + st.dr;
+  const R irho = R(1) / st.rho;
+  const R Gx = (R)d.gbx * st.th + (R)d.ax, Gy = (R)d.gby * st.th + (R)d.ay;
+  const R hphi = R(0.5) * st.phi;
+  const R vx = st.jx * irho + hphi * Gx;
+  const R vy = st.jy * irho + hphi * Gy;
+  const R vm = sqrt(vx * vx + vy * vy);
+  const R l0 = R(0.5) + R(0.25) * st.cd;
+  const R l1 = R(0.5) * st.cf;
+  const R iD = R(1) / (l0 + sqrt(l0 * l0 + l1 * vm));
+  st.ux = vx * iD;
+  st.uy = vy * iD;
+  st.umag = vm * iD;
+}
+
+// theta at node (xs, ys) from its post-streaming D2Q5 populations.
+template <typename P, typename R = typename P::R>
+__device__ __forceinline__ R gather_theta(const CavDesc &d, const char *__restrict__ buf, int xs,
+                                          int ys) {
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch, plane = d.plane;
+  int xm = xs - 1, xp = xs + 1, ym = ys - 1, yp = ys + 1;
+  if (d.bc[0] == kPeriodic) {
+    xm = xm < 0 ? xm + nx : xm;
+    xp = xp >= nx ? xp - nx : xp;
+  }
+  if (d.bc[2] == kPeriodic) {
+    ym = ym < 0 ? ym + ny : ym;
+    yp = yp >= ny ? yp - ny : yp;
+  }
+  const typename P::G *G = gplanes<P>(buf, plane);
+  const R s = ldv<R>(G + ys * pitch + xs) +
+              ((ldv<R>(G + plane + ys * pitch + xm) + ldv<R>(G + 3 * plane + ys * pitch + xp)) +
+               (ldv<R>(G + 2 * plane + ym * pitch + xs) + ldv<R>(G + 4 * plane + yp * pitch + xs)));
+  return s * (R)d.isig;
+}
+
+// Macroscopic state of node (x, y) ready for the collision.  Boundary nodes
+// (outermost nodes of a non-periodic side) are rebuilt by non-equilibrium
+// extrapolation from their inward neighbour x_f (diagonal at a corner):
+// their raw moments become m(x_f) + m^eq(rho_b, u_b; phi_b) - m^eq(rho_f, u_f;
+// phi_f), which is M applied to f_i^eq(b) + [f_i(x_f) - f_i^eq(x_f)], and
+// likewise for the D2Q5 moments with Eq. 33.  The node then collides with
+// (rho_b, u_b, T_b).  Returns true for boundary nodes.
+template <typename P, typename R = typename P::R>
+__device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restrict__ A, int x,
+                                           int y, NodeState<R> &st) {
+  int sx = -1, sy = -1, dx = 0, dy = 0;
+  if (x == 0 && d.bc[0] != kPeriodic) {
+    sx = 0;
+    dx = 1;
+  } else if (x == d.nx - 1 && d.bc[1] != kPeriodic) {
+    sx = 1;
+    dx = -1;
+  }
+  if (y == 0 && d.bc[2] != kPeriodic) {
+    sy = 2;
+    dy = 1;
+  } else if (y == d.ny - 1 && d.bc[3] != kPeriodic) {
+    sy = 3;
+    dy = -1;
+  }
+  const bool wall = (sx >= 0) || (sy >= 0);
+  gather_moments<P>(d, A, x + dx, y + dy, st);
+  if (wall) {
+    const R drf = st.dr, uxf = st.ux, uyf = st.uy, thf = st.th, ipf = st.ip;
+    const bool corner = (sx >= 0) && (sy >= 0);
+    const int side = sx >= 0 ? sx : sy;
+    const int kind = d.bc[side];
+    bool need_ff;
+    if (corner)
+      need_ff = !dirichlet_T(d.bc[sx]) && !dirichlet_T(d.bc[sy]);
+    else
+      need_ff = kind == kWallAdiabatic;
+    R thff = R(0);
+    if (need_ff) thff = gather_theta<P>(d, A, x + 2 * dx, y + 2 * dy);
+    // second-order zero normal gradient: theta_b = (4 theta_f - theta_ff) / 3
+    const R thx = thf + (thf - thff) * (R(1) / R(3));
+    R drb = drf, ubx = R(0), uby = R(0), thb;
+    if (corner) {
+      thb = dirichlet_T(d.bc[sx]) ? (R)d.bc_th[sx]
+                                  : (dirichlet_T(d.bc[sy]) ? (R)d.bc_th[sy] : thx);
+    } else if (kind == kWallT || kind == kWallAdiabatic) {
+      ubx = (R)d.bc_u[side];
+      uby = (R)d.bc_v[side];
+      thb = kind == kWallT ? (R)d.bc_th[side] : thx;
+    } else if (kind == kInlet) {
+      const R t = side < 2 ? (R)y / (R)(d.ny - 1) : (R)x / (R)(d.nx - 1);
+      const R un = R(6) * (R)d.inlet_U * t * (R(1) - t);
+      ubx = side == 0 ? un : (side == 1 ? -un : R(0));
+      uby = side == 2 ? un : (side == 3 ? -un : R(0));
+      thb = (R)d.bc_th[side];
+    } else {  // outlet
+      drb = R(0);
+      ubx = uxf;
+      uby = uyf;
+      thb = thf;
+    }
+    // the boundary node's own medium
+    medium_at(d, y * d.pitch + x, st.phi, st.ip, st.cd, st.cf);
+    R mb[9], mf[9];
+    meq_dev(drb, ubx, uby, st.ip, mb);
+    meq_dev(drf, uxf, uyf, ipf, mf);
+    st.dr += mb[0] - mf[0];
+    st.jx += mb[1] - mf[1];
+    st.jy += mb[2] - mf[2];
+    st.k20 += mb[3] - mf[3];
+    st.k02 += mb[4] - mf[4];
+    st.k11 += mb[5] - mf[5];
+    st.k21 += mb[6] - mf[6];
+    st.k12 += mb[7] - mf[7];
+    st.k22 += mb[8] - mf[8];
+    const R T0 = (R)d.T0, hv = (R)d.hv;
+    const R Tb = T0 + thb, Tf = T0 + thf;
+    st.n1 += ubx * Tb - uxf * Tf;
+    st.n2 += uby * Tb - uyf * Tf;
+    st.n3 += (hv * thb + ubx * ubx * Tb) - (hv * thf + uxf * uxf * Tf);
+    st.n4 += (hv * thb + uby * uby * Tb) - (hv * thf + uyf * uyf * Tf);
+    st.sg = (R)d.sig * thb;
+    st.th = thb;
+    st.rho = R(1) + st.dr;
+    st.ux = ubx;
+    st.uy = uby;
+    st.umag = sqrt(ubx * ubx + uby * uby);
+  }
+  return wall;
+}
+
+// Collide one node in central-moment space and store the post-collision
+// deviations to the planes of B at element offset idx.
+template <typename P, typename R = typename P::R>
+__device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<R> &st, bool wall,
+                                              char *__restrict__ buf, int idx, uint32_t seed) {
+  const int plane = d.plane;
+  const R rho = st.rho, ux = st.ux, uy = st.uy, ip = st.ip, dr = st.dr;
+  const R jx = st.jx, jy = st.jy;
+  const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+  const R third = R(1) / R(3), two = R(2), half = R(0.5), quarter = R(0.25);
+
+  // force of Eq. 4 with G = gb theta + a
+  const R Gx = (R)d.gbx * st.th + (R)d.ax, Gy = (R)d.gby * st.th + (R)d.ay;
+  const R drag = st.cd + st.cf * st.umag;
+  const R rFx = rho * (st.phi * Gx - drag * ux);
+  const R rFy = rho * (st.phi * Gy - drag * uy);
+
+  // central moments m~ = N m (Eq. 14), as deviations from their rest values
+  const R c1 = jx - ux * rho;
+  const R c2 = jy - uy * rho;
+  const R c3 = st.k20 + ip * ux * (ux * rho - two * jx);
+  const R c4 = st.k02 + ip * uy * (uy * rho - two * jy);
+  const R c5 = st.k11 + ip * (uxy * rho - uy * jx - ux * jy);
+  const R K20 = third + st.k20, K02 = third + st.k02;
+  const R c6 = st.k21 - uy * K20 - two * ux * st.k11 + ip * ux * (two * uy * jx + ux * jy - uxy * rho);
+  const R c7 = st.k12 - ux * K02 - two * uy * st.k11 + ip * uy * (uy * jx + two * ux * jy - uxy * rho);
+  const R c8 = st.k22 +
+               ip * (uy2 * K20 + ux2 * K02 + R(4) * uxy * st.k11 - two * uy * st.k21 -
+                     two * ux * st.k12) +
+               ip * ip * uxy * (uxy * rho - two * uy * jx - two * ux * jy);
+
+  // relaxation with consistent forcing (Eqs. 11, 15-17)
+  const R e3 = c3 - dr * third, e4 = c4 - dr * third;
+  const R sp = (R)d.sp, sm = (R)d.sm, s3c = (R)d.s3c, s3f = (R)d.s3f, s1c = (R)d.s1c,
+          s1f = (R)d.s1f;
+  const R c1s = s1c * c1 + s1f * rFx;
+  const R c2s = s1c * c2 + s1f * rFy;
+  const R c3s = c3 - sp * e3 - sm * e4;
+  const R c4s = c4 - sm * e3 - sp * e4;
+  const R c5s = (R)d.svc * c5;
+  const R c6s = s3c * c6 + s3f * rFy;
+  const R c7s = s3c * c7 + s3f * rFx;
+  const R c8s = c8 - (R)d.s4 * (c8 - dr * (R(1) / R(9)));
+
+  // back to raw moments with N^-1 (Eq. A1).  The first moments are
+  // rho u + c~*_10.  At a fluid node Eq. 21 makes this j + rho F exactly for
+  // any s1; that form is used there because rebuilding it from the rounded u
+  // would inject a momentum error every step.
+  const R K10 = wall ? ux * rho + c1s : jx + rFx;
+  const R K01 = wall ? uy * rho + c2s : jy + rFy;
+  const R Q20 = ip * ux * (ux * rho + two * c1s) + c3s;
+  const R Q02 = ip * uy * (uy * rho + two * c2s) + c4s;
+  const R Q11 = ip * (uxy * rho + uy * c1s + ux * c2s) + c5s;
+  const R Q21 = ip * ux * (uxy * rho + two * uy * c1s + ux * c2s) + uy * (third + c3s) +
+                two * ux * c5s + c6s;
+  const R Q12 = ip * uy * (uxy * rho + uy * c1s + two * ux * c2s) + ux * (third + c4s) +
+                two * uy * c5s + c7s;
+  const R Q22 = ip * ip * uxy * (uxy * rho + two * uy * c1s + two * ux * c2s) +
+                ip * (uy2 * (third + c3s) + ux2 * (third + c4s) + R(4) * uxy * c5s +
+                      two * uy * c6s + two * ux * c7s) +
+                c8s;
+
+  // populations f* = M^-1 m* (deviations; M^-1 maps the rest moments to w_i)
+  const R h20 = half * (Q20 - Q22), h02 = half * (Q02 - Q22);
+  const R f1 = half * (K10 - Q12) + h20;
+  const R f3 = half * (Q12 - K10) + h20;
+  const R f2 = half * (K01 - Q21) + h02;
+  const R f4 = half * (Q21 - K01) + h02;
+  const R pa = quarter * (Q22 + Q21), pb = quarter * (Q11 + Q12);
+  const R pc = quarter * (Q22 - Q21), pd = quarter * (Q11 - Q12);
+  const R f5 = pa + pb;  // (k11 + k21 + k12 + k22)/4
+  const R f6 = pa - pb;  // (-k11 + k21 - k12 + k22)/4
+  const R f7 = pc + pd;  // (k11 - k21 - k12 + k22)/4
+  const R f8 = pc - pd;  // (-k11 - k21 + k12 + k22)/4
+  // rest population from mass conservation (equal to k00 - k20 - k02 + k22)
+  const R f0 = dr - (((f1 + f3) + (f2 + f4)) + ((f5 + f6) + (f7 + f8)));
+
+  // D2Q5 (Eqs. 28-33, A2) in closed form, as deviations
+  const R T = (R)d.T0 + st.th;
+  const R hvth = (R)d.hv * st.th;
+  const R zac = (R)d.zac;
+  const R q1 = zac * (st.n1 - ux * T);
+  const R q2 = zac * (st.n2 - uy * T);
+  const R e3t = (R)d.zec * (ux2 * T - two * ux * st.n1 + st.n3 - hvth);
+  const R e4t = (R)d.znc * (uy2 * T - two * uy * st.n2 + st.n4 - hvth);
+  const R ax_ = ux2 * T + q1 * two * ux + e3t + hvth;
+  const R ay_ = uy2 * T + q2 * two * uy + e4t + hvth;
+  const R bx_ = ux * T + q1, by_ = uy * T + q2;
+  const R g1 = half * (ax_ + bx_);
+  const R g3 = half * (ax_ - bx_);
+  const R g2 = half * (ay_ + by_);
+  const R g4 = half * (ay_ - by_);
+  // rest population from heat conservation (equal to
+  // (sigma - varpi) theta - |u|^2 T - 2 u.q - e3 - e4)
+  const R g0 = st.sg - ((g1 + g3) + (g2 + g4));
+
+  const R out[kPlanes] = {f0, f1, f2, f3, f4, f5, f6, f7, f8, g0, g1, g2, g3, g4};
+  typename P::F *of = const_cast<typename P::F *>(fplanes<P>(buf)) + idx;
+  typename P::G *og = const_cast<typename P::G *>(gplanes<P>(buf, plane)) + idx;
+  // random words for the stochastic rounding: two 16-bit fields per word
+  uint32_t w = mix32((uint32_t)idx + seed);
+#pragma unroll
+  for (int i = 0; i < kPlanes; ++i) {
+    if (i < 9)
+      stv(of + i * plane, out[i], (i & 1) ? (w >> 16) : w);
+    else
+      stv(og + (i - 9) * plane, out[i], (i & 1) ? (w >> 16) : w);
+    if (i & 1) w = xorshift32(w);
+  }
+}
+
+// ------------------------------------------------------------ step kernel
+
+// One time step of every tile in tiles[0 .. counts[0]).  parity selects the
+// source buffer (0: A -> B, 1: B -> A).  write_snap records (u, v, theta) of
+// the collision for the residual.  counts[2 + parity] holds the index of this
+// step; the kernel passes it on in counts[3 - parity] for the next launch, so
+// captured graphs need no baked-in step numbers.
+template <typename P>
+__global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ descs,
+                                                   const Tile *__restrict__ tiles,
+                                                   int32_t *__restrict__ counts, int parity,
+                                                   int write_snap) {
+  using R = typename P::R;
+  const int ntiles = counts[0];
+  const uint32_t step = (uint32_t)counts[2 + parity];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) counts[3 - parity] = (int32_t)(step + 1);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int cav = __builtin_amdgcn_readfirstlane(tiles[t].cav);
+    if (cav < 0) continue;  // padding entry of the XCD-ordered list
+    const int x0 = __builtin_amdgcn_readfirstlane(tiles[t].x0);
+    const int y0 = __builtin_amdgcn_readfirstlane(tiles[t].y0);
+    const CavDesc &d = descs[cav];
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    if (x < d.nx && y < d.ny) {
+      const char *A = parity ? d.B : d.A;
+      char *B = parity ? d.A : d.B;
+      NodeState<R> st;
+      const bool wall = node_state<P>(d, A, x, y, st);
+      const int idx = y * d.pitch + x;
+      const uint32_t seed = mix32(step * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
+      collide_store<P>(d, st, wall, B, idx, seed);
+      if (write_snap) {
+        d.snap[idx] = (float)st.ux;
+        d.snap[d.plane + idx] = (float)st.uy;
+        d.snap[2 * d.plane + idx] = (float)st.th;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ init kernel
+
+// Equilibrium population (deviation) of direction i for rho = 1 and u.
+__device__ __forceinline__ double feq_dev_dir(int i, double ux, double uy, double ip) {
+  double m[9];
+  meq_dev(0.0, ux, uy, ip, m);
+  // M^-1 rows (populations from raw moments)
+  switch (i) {
+    case 0: return m[0] - m[3] - m[4] + m[8];
+    case 1: return 0.5 * (m[1] + m[3] - m[7] - m[8]);
+    case 2: return 0.5 * (m[2] + m[4] - m[6] - m[8]);
+    case 3: return 0.5 * (-m[1] + m[3] + m[7] - m[8]);
+    case 4: return 0.5 * (-m[2] + m[4] + m[6] - m[8]);
+    case 5: return 0.25 * (m[5] + m[6] + m[7] + m[8]);
+    case 6: return 0.25 * (-m[5] + m[6] - m[7] + m[8]);
+    case 7: return 0.25 * (m[5] - m[6] - m[7] + m[8]);
+    default: return 0.25 * (-m[5] - m[6] + m[7] + m[8]);
+  }
+}
+
+// g_i^eq(T, u) - g_i^eq(T0, 0) from Eq. 34.
+__device__ __forceinline__ double geq_dev_dir(const CavDesc &d, int i, double ux, double uy,
+                                              double th) {
+  const double T = d.T0 + th;
+  switch (i) {
+    case 0: return d.sig_mv * th - (ux * ux + uy * uy) * T;
+    case 1: return 0.5 * d.hv * th + 0.5 * (ux + ux * ux) * T;
+    case 2: return 0.5 * d.hv * th + 0.5 * (uy + uy * uy) * T;
+    case 3: return 0.5 * d.hv * th + 0.5 * (ux * ux - ux) * T;
+    default: return 0.5 * d.hv * th + 0.5 * (uy * uy - uy) * T;
+  }
+}
+
+// Fill the current buffer of one domain so that the next pull (streaming)
+// delivers the equilibrium of the given fields at every node: element i of
+// node x holds the equilibrium of node x + e_i (its own when x + e_i lies
+// outside a non-periodic side; boundary nodes rebuild those entries anyway).
+template <typename P>
+__global__ void init_kernel(const CavDesc *__restrict__ descs, int cav, int parity,
+                            const float *__restrict__ uvth, float th_uniform) {
+  using F = typename P::F;
+  using G = typename P::G;
+  const CavDesc &d = descs[cav];
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= d.nx || y >= d.ny) return;
+  const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  char *buf = parity ? d.B : d.A;
+  F *A = const_cast<F *>(fplanes<P>(buf));
+  G *Gp = const_cast<G *>(gplanes<P>(buf, d.plane));
+  const int n = d.nx * d.ny;
+  const double scf = sizeof(F) == 2 ? (double)kF16Scale : 1.0;
+  const double scg = sizeof(G) == 2 ? (double)kF16Scale : 1.0;
+  for (int i = 0; i < 9; ++i) {
+    int xs = x + ex[i], ys = y + ey[i];
+    bool outside = false;
+    if (xs < 0 || xs >= d.nx) {
+      if (d.bc[0] == kPeriodic) xs = (xs + d.nx) % d.nx;
+      else outside = true;
+    }
+    if (ys < 0 || ys >= d.ny) {
+      if (d.bc[2] == kPeriodic) ys = (ys + d.ny) % d.ny;
+      else outside = true;
+    }
+    if (outside) {
+      xs = x;
+      ys = y;
+    }
+    double ux = 0.0, uy = 0.0, th = th_uniform;
+    if (uvth) {
+      const int k = ys * d.nx + xs;
+      ux = uvth[k];
+      uy = uvth[n + k];
+      th = uvth[2 * n + k];
+    }
+    double phi, ip, cd, cf;
+    medium_at(d, ys * d.pitch + xs, phi, ip, cd, cf);
+    const int idx = y * d.pitch + x;
+    A[i * d.plane + idx] = (F)(scf * feq_dev_dir(i, ux, uy, ip));
+    if (i < 5) Gp[i * d.plane + idx] = (G)(scg * geq_dev_dir(d, i, ux, uy, th));
+  }
+}
+
+// ------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum kRed doubles over a block in a fixed order; result valid in thread 0.
+__device__ __forceinline__ void block_sum(double (&v)[kRed], double (*lds)[kRed]) {
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int nthreads = blockDim.x * blockDim.y;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int k = 0; k < kRed; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+    for (int k = 0; k < kRed; ++k) lds[wave][k] = v[k];
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = (nthreads + 63) >> 6;
+    for (int k = 0; k < kRed; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += lds[w][k];
+      v[k] = s;
+    }
+  }
+}
+
+// Residual partial sums of one tile per block.
+template <typename P>
+__global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict__ descs,
+                                                       const Tile *__restrict__ tiles, int parity,
+                                                       double *__restrict__ partials) {
+  using R = typename P::R;
+  __shared__ double lds[8][kRed];
+  const int t = blockIdx.x;
+  const int cav = __builtin_amdgcn_readfirstlane(tiles[t].cav);
+  const CavDesc &d = descs[cav];
+  const int x = tiles[t].x0 + threadIdx.x, y = tiles[t].y0 + threadIdx.y;
+  double v[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (x < d.nx && y < d.ny) {
+    const char *A = parity ? d.B : d.A;
+    NodeState<R> st;
+    node_state<P>(d, A, x, y, st);
+    const int idx = y * d.pitch + x;
+    // the snapshot holds FP32 values: compare like with like
+    const double ux = (double)(float)st.ux, uy = (double)(float)st.uy, th = (double)(float)st.th;
+    const double du = ux - d.snap[idx];
+    const double dv = uy - d.snap[d.plane + idx];
+    const double dth = th - d.snap[2 * d.plane + idx];
+    const double T = d.T0 + (double)st.th;
+    v[0] = du * du + dv * dv;
+    v[1] = (double)st.ux * (double)st.ux + (double)st.uy * (double)st.uy;
+    v[2] = dth * dth;
+    v[3] = T * T;
+    v[4] = (double)st.dr;
+    const bool bad = !isfinite((double)st.ux) || !isfinite((double)st.uy) ||
+                     !isfinite((double)st.th) || !isfinite((double)st.rho);
+    v[5] = bad ? 1.0 : 0.0;
+    v[6] = 1.0;
+  }
+  block_sum(v, lds);
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    for (int k = 0; k < kRed; ++k) partials[(size_t)t * kRed + k] = v[k];
+}
+
+// Per-domain totals of the tile partial sums (fixed order, deterministic).
+__global__ void __launch_bounds__(256) residual_finalize(const CavDesc *__restrict__ descs,
+                                                         const double *__restrict__ partials,
+                                                         double *__restrict__ results) {
+  __shared__ double lds[4][kRed];
+  const CavDesc &d = descs[blockIdx.x];
+  double v[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < d.ntiles; t += blockDim.x)
+    for (int k = 0; k < kRed; ++k) v[k] += partials[(size_t)(d.tile0 + t) * kRed + k];
+  block_sum(v, lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kRed; ++k) results[(size_t)blockIdx.x * kRed + k] = v[k];
+}
+
+// Macroscopic fields of one domain into 4 dense planes: rho - 1, u, v, theta.
+template <typename P>
+__global__ void __launch_bounds__(512) macros_kernel(const CavDesc *__restrict__ descs,
+                                                     const Tile *__restrict__ tiles, int tile0,
+                                                     int parity, float *__restrict__ out) {
+  using R = typename P::R;
+  const int t = tile0 + blockIdx.x;
+  const int cav = __builtin_amdgcn_readfirstlane(tiles[t].cav);
+  const CavDesc &d = descs[cav];
+  const int x = tiles[t].x0 + threadIdx.x, y = tiles[t].y0 + threadIdx.y;
+  if (x >= d.nx || y >= d.ny) return;
+  const char *A = parity ? d.B : d.A;
+  NodeState<R> st;
+  node_state<P>(d, A, x, y, st);
+  const int n = d.nx * d.ny, k = y * d.nx + x;
+  out[k] = (float)st.dr;
+  out[n + k] = (float)st.ux;
+  out[2 * n + k] = (float)st.uy;
+  out[3 * n + k] = (float)st.th;
+}
+
+// Mean Nusselt number of one side per domain (one block per domain):
+// Nu_j = -L dT/dn / dT with the one-sided derivative (-3 T0 + 4 T1 - T2)/2 taken
+// from the wall inward, trapezoid mean over the wall nodes.
+template <typename P>
+__global__ void __launch_bounds__(256) nusselt_kernel(const CavDesc *__restrict__ descs, int cav0,
+                                                      int side, int parity,
+                                                      double *__restrict__ nu_mean,
+                                                      double *__restrict__ nu_local) {
+  using R = typename P::R;
+  __shared__ double lds[4][kRed];
+  const int cav = cav0 + blockIdx.x;
+  const CavDesc &d = descs[cav];
+  const char *A = parity ? d.B : d.A;
+  const bool along_y = side < 2;
+  const int nw = along_y ? d.ny : d.nx;
+  const double L = along_y ? d.nx - 1 : d.ny - 1;
+  const double sign = (side == 0 || side == 2) ? 1.0 : -1.0;
+  double v[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+    double t[3];
+    for (int k = 0; k < 3; ++k) {
+      int x, y;
+      if (along_y) {
+        y = j;
+        x = side == 0 ? k : d.nx - 1 - k;
+      } else {
+        x = j;
+        y = side == 2 ? k : d.ny - 1 - k;
+      }
+      NodeState<R> st;
+      node_state<P>(d, A, x, y, st);
+      t[k] = (double)st.th;  // the gradient does not depend on the reference T0
+    }
+    const double nu = -L * sign * (-3.0 * t[0] + 4.0 * t[1] - t[2]) * 0.5 / d.dT;
+    if (nu_local) nu_local[j] = nu;
+    v[0] += (j == 0 || j == nw - 1) ? 0.5 * nu : nu;
+  }
+  block_sum(v, lds);
+  if (threadIdx.x == 0) nu_mean[cav] = v[0] / (nw - 1);
+}
+
+// --------------------------------------------------------------- launchers
+
+static dim3 block_of(const LaunchShape &s) { return dim3(s.tile_x, s.tile_y, 1); }
+
+// Calls f(StoreX{}) for the storage kind of the context (0 FP32, 1 FP16,
+// 2 FP16 flow + FP32 temperature).
+template <typename Fn>
+static void dispatch(int storage, Fn &&f) {
+  if (storage == 0)
+    f(StoreF32{});
+  else if (storage == 1)
+    f(StoreF16{});
+  else
+    f(StoreMix{});
+}
+
+hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
+                       int32_t grid_tiles, int parity, int write_snap, int storage,
+                       LaunchShape shape, hipStream_t s) {
+  if (grid_tiles <= 0) return hipSuccess;
+  const int blocks = shape.blocks > 0 && shape.blocks < grid_tiles ? shape.blocks : grid_tiles;
+  dispatch(storage, [&](auto p) {
+    using P = decltype(p);
+    hipLaunchKernelGGL(step_kernel<P>, dim3(blocks), block_of(shape), 0, s, descs, tiles, counts,
+                       parity, write_snap);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int parity,
+                       const float *uvth, float th_uniform, int storage, hipStream_t s) {
+  const dim3 blk(64, 4, 1), grd((nx + 63) / 64, (ny + 3) / 4, 1);
+  dispatch(storage, [&](auto p) {
+    using P = decltype(p);
+    hipLaunchKernelGGL(init_kernel<P>, grd, blk, 0, s, descs, cav, parity, uvth, th_uniform);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int parity,
+                           double *partials, int storage, LaunchShape shape, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  dispatch(storage, [&](auto p) {
+    using P = decltype(p);
+    hipLaunchKernelGGL(residual_kernel<P>, dim3(ntiles), block_of(shape), 0, s, descs, tiles,
+                       parity, partials);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_finalize(const CavDesc *descs, int32_t count, const double *partials,
+                                    double *results, hipStream_t s) {
+  hipLaunchKernelGGL(residual_finalize, dim3(count), dim3(256), 0, s, descs, partials, results);
+  return hipGetLastError();
+}
+
+hipError_t launch_macros(const CavDesc *descs, const Tile *tiles, int32_t tile0, int32_t ntiles,
+                         int parity, float *out, int storage, LaunchShape shape, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  dispatch(storage, [&](auto p) {
+    using P = decltype(p);
+    hipLaunchKernelGGL(macros_kernel<P>, dim3(ntiles), block_of(shape), 0, s, descs, tiles, tile0,
+                       parity, out);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_nusselt(const CavDesc *descs, int32_t cav0, int32_t ncav, int32_t side,
+                          int parity, double *nu_mean, double *nu_local, int storage,
+                          hipStream_t s) {
+  dispatch(storage, [&](auto p) {
+    using P = decltype(p);
+    hipLaunchKernelGGL(nusselt_kernel<P>, dim3(ncav), dim3(256), 0, s, descs, cav0, side, parity,
+                       nu_mean, nu_local);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace clb

@@ -1,0 +1,88 @@
+"""Workload descriptions shared by the GPU tests: one dict feeds both the GPU
+library (field names of clb_params) and the oracle, whose lattice values are
+derived independently by oracle.params."""
+import math
+
+import numpy as np
+
+import oracle
+from oracle import params as op
+
+CAVITY_BC = ("wall_T", "wall_T", "wall_adiabatic", "wall_adiabatic")
+CHANNEL_BC = ("periodic", "periodic", "wall_T", "wall_T")
+
+
+def cavity(n, Ra=1e3, Pr=1.0, Da=1e-2, phi=0.6, sigma=1.0, ny=None, **kw):
+    c = dict(nx=n, ny=n if ny is None else ny, bc=CAVITY_BC, bc_T=(1.0, 0.0, 0.0, 0.0), Ra=Ra,
+             Pr=Pr, Da=Da, phi=phi, F_phi=-1.0, sigma=sigma, scaling="cavity")
+    c.update(kw)
+    return c
+
+
+def oracle_values(case):
+    """Lattice values of a workload by the oracle's own derivation."""
+    c = dict(case)
+    nx, ny = c["nx"], c["ny"]
+    scaling = c.get("scaling", "cavity")
+    phi = c.get("phi", 1.0)
+    J, Gamma, sigma = c.get("J", 1.0), c.get("Gamma", 1.0), c.get("sigma", 1.0)
+    varpi = c.get("varpi", 0.25)
+    if scaling == "cavity":
+        L = nx - 1
+        if c.get("s_v", 0) > 0 and c.get("zeta_a", 0) > 0:
+            P = dict(s_v=c["s_v"], za=c["zeta_a"], nu=(1 / c["s_v"] - 0.5) / 3 / J, gbeta_dT=0.0)
+        else:
+            P = op.cavity(nx, Ra=c["Ra"], Pr=c["Pr"], Da=c.get("Da", 1.0), phi=phi, J=J,
+                          Gamma=Gamma, sigma=sigma, Ma=c.get("Ma", 0.1), varpi=varpi)
+    else:
+        L = ny - 1
+        if c.get("s_v", 0) > 0 and c.get("zeta_a", 0) > 0:
+            P = dict(s_v=c["s_v"], za=c["zeta_a"], nu=(1 / c["s_v"] - 0.5) / 3 / J, gbeta_dT=0.0)
+        else:
+            P = op.channel(ny, Re=c["Re"], Ra=c.get("Ra", 0.0), Pr=c["Pr"], Da=c.get("Da", 1.0),
+                           phi=phi, u_ref=c["u_ref"], J=J, Gamma=Gamma, sigma=sigma, varpi=varpi)
+    s_v = c.get("s_v", 0) or P["s_v"]
+    za = c.get("zeta_a", 0) or P["za"]
+    nu = c.get("nu", 0) or P["nu"]
+    dT = c.get("dT", 1.0)
+    gbeta = c.get("gbeta", 0) or P["gbeta_dT"] / dT
+    gdir = c.get("g_dir", (0.0, -1.0))
+    Da = c.get("Da", 0.0)
+    eps = c.get("eps")
+    if eps is not None:
+        eps = np.asarray(eps, dtype=np.float64)
+        K = op.kozeny_carman_K(eps, c["dp"])
+        Fphi = op.ergun_F(eps) if c.get("F_phi", -1.0) != 0 else np.zeros_like(eps)
+        phi_f = eps
+    else:
+        K = Da * L * L if Da > 0 else math.inf
+        Fp = c.get("F_phi", 0.0)
+        Fphi = op.ergun_F(phi) if Fp < 0 else Fp
+        phi_f = phi
+    return dict(
+        bc=c.get("bc", CAVITY_BC), bc_u=c.get("bc_u", (0, 0, 0, 0)),
+        bc_v=c.get("bc_v", (0, 0, 0, 0)), bc_T=c.get("bc_T", (0, 0, 0, 0)),
+        inlet_U=c.get("inlet_U", 0.0), nu=nu, s_v=s_v, s_b=c.get("s_b") or 1.5,
+        s1=c.get("s1") or 1.0, s3=c.get("s3") or 1.2, s4=c.get("s4") or 1.8, za=za,
+        ze=c.get("zeta_e") or 1.0, zn=c.get("zeta_nu") or 1.0, varpi=varpi, sigma=sigma,
+        T0=c.get("T0", 0.5), gb=(-gdir[0] * gbeta, -gdir[1] * gbeta), a=c.get("a", (0.0, 0.0)),
+        phi=phi_f, K=K, Fphi=Fphi)
+
+
+def oracle_lattice(case, nthreads=0):
+    """An oracle Lattice for the same workload (FP64, own derivation)."""
+    return oracle.Lattice(case["nx"], case["ny"], nthreads=nthreads, **oracle_values(case))
+
+
+def rel_l2(a, b):
+    """Eq. 45: |a - b|_2 / |b|_2."""
+    a, b = np.asarray(a), np.asarray(b)
+    den = np.sqrt(np.sum(b * b))
+    return np.sqrt(np.sum((a - b) ** 2)) / den if den > 0 else np.sqrt(np.sum(a * a))
+
+
+def vel_rel_l2(ga, oa):
+    """Eq. 45 on the velocity vector (u, v)."""
+    num = np.sum((ga["ux"] - oa["ux"]) ** 2 + (ga["uy"] - oa["uy"]) ** 2)
+    den = np.sum(oa["ux"] ** 2 + oa["uy"] ** 2)
+    return math.sqrt(num / den)

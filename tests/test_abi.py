@@ -1,0 +1,96 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and its host-side parameter derivation agrees with the oracle's own
+derivation and with the definitions of the dimensionless groups."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from oracle import params as oparams
+from paper_2110_05943_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "clb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(clb_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(B.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_struct_sizes_match_header_layout():
+    # 2 ints + 4 ints + 12 doubles + 1 + (phi, eps*, dp, Da, F) + int + 7 + 3 + 2*2 + 11 + T_init + int
+    p = B.make_params(nx=8, ny=8)
+    assert C.sizeof(p) == C.sizeof(B.Params)
+    assert B.Params.storage.offset > B.Params.T_init.offset > B.Params.gbeta.offset
+
+
+@pytest.mark.parametrize("n,Ra,Pr,Da,phi", [(64, 1e3, 1.0, 1e-2, 0.6), (128, 1e5, 0.71, 1e-4, 0.4),
+                                            (512, 1e7, 7.0, 1e-5, 0.95)])
+def test_cavity_derivation_matches_oracle(n, Ra, Pr, Da, phi):
+    d = B.derive(nx=n, ny=n, Ra=Ra, Pr=Pr, Da=Da, phi=phi, F_phi=-1.0)
+    o = oparams.cavity(n, Ra=Ra, Pr=Pr, Da=Da, phi=phi)
+    assert math.isclose(d["s_v"], o["s_v"], rel_tol=1e-14)
+    assert math.isclose(d["zeta_a"], o["za"], rel_tol=1e-14)
+    assert math.isclose(d["nu"], o["nu"], rel_tol=1e-14)
+    assert math.isclose(d["gbeta"], o["gbeta_dT"], rel_tol=1e-14)
+    assert math.isclose(d["K"], o["K"], rel_tol=1e-14)
+    assert math.isclose(d["F_phi"], o["Fphi"], rel_tol=1e-14)
+    assert d["L"] == n - 1
+    # paper defaults (Section 3)
+    assert (d["s1"], d["s3"], d["s4"], d["zeta_e"], d["zeta_nu"], d["varpi"]) == \
+        (1.0, 1.2, 1.8, 1.0, 1.0, 0.25)
+    assert d["s_b"] == 1.5
+
+
+def test_channel_derivation_matches_oracle():
+    ny, Re, u1 = 33, 5.0, 5.0 / 6.0 / 32
+    d = B.derive(nx=4, ny=ny, bc=("periodic", "periodic", "wall_T", "wall_T"), scaling="channel",
+                 Re=Re, u_ref=u1, Ra=100.0, Pr=1.0, Da=0.01, phi=0.6)
+    o = oparams.channel(ny, Re=Re, Ra=100.0, Pr=1.0, Da=0.01, phi=0.6, u_ref=u1)
+    for a, b in (("s_v", "s_v"), ("zeta_a", "za"), ("nu", "nu"), ("gbeta", "gbeta_dT"),
+                 ("K", "K")):
+        assert math.isclose(d[a], o[b], rel_tol=1e-13), a
+    assert math.isclose(d["s_v"], 1.0, rel_tol=1e-13)
+
+
+@pytest.mark.parametrize("bad", [dict(nx=3), dict(phi=0.0), dict(phi=1.5), dict(s_v=2.5),
+                                 dict(bc=("periodic", "wall_T", "wall_T", "wall_T")),
+                                 dict(Ra=0.0), dict(varpi=1.2), dict(storage=7)])
+def test_invalid_parameters_are_rejected(bad):
+    kw = dict(nx=16, ny=16, Ra=1e3, Pr=1.0, Da=1e-2, phi=0.6)
+    kw.update(bad)
+    with pytest.raises(B.CLBError) as e:
+        B.derive(**kw)
+    assert e.value.status == B.ERR_ARG
+
+
+def test_workspace_bytes():
+    lib = B._lib()
+    arr = (B.Params * 2)(B.make_params(nx=64, ny=64, Ra=1e3, Pr=1.0),
+                         B.make_params(nx=100, ny=30, Ra=1e3, Pr=1.0))
+    n = C.c_size_t()
+    assert lib.clb_workspace_bytes(arr, 2, C.byref(n)) == 0
+    # two population buffers of 14 FP32 planes each per domain, rows padded to 64
+    assert n.value > 2 * 14 * 4 * (64 * 64 + 128 * 30)
+    arr[1].storage = 1
+    assert lib.clb_workspace_bytes(arr, 2, C.byref(n)) == B.ERR_ARG  # storage must agree
+
+
+def test_create_rejects_small_workspace():
+    lib = B._lib()
+    p = B.make_params(nx=64, ny=64, Ra=1e3, Pr=1.0)
+    ctx = C.c_void_p()
+    # a too-small (and null) workspace fails before any device call
+    assert lib.clb_create(C.byref(p), 1, None, 16, None, C.byref(ctx)) == B.ERR_WORKSPACE

