@@ -1,17 +1,23 @@
 """Throughput benchmark of the coupled porous cascaded LB step on one MI355X.
 
-Workload: natural convection in a square porous cavity, 4096 x 4096 nodes,
-Ra = 1e6, Da = 1e-4, porosity 0.4, Pr = 1, J = sigma = 1, Ergun F_phi, FP32
-deviation storage (FP16 with --storage f16).  One "step" is one time step
-of the whole path: pull streaming + macroscopic values + boundary
-reconstruction + D2Q9 and D2Q5 collisions + store, with the FP64 residual,
-mass and Nusselt reductions every 100 steps (their cost is inside the timed
-region).  Inputs (populations) are resident in HBM before timing starts.
+Default workload: natural convection in a square porous cavity, 4096 x 4096
+nodes, Ra = 1e6, Da = 1e-4, porosity 0.4, Pr = 1, J = sigma = 1, Ergun
+F_phi, FP32 deviation storage (--storage f16 / mixed for the narrow modes).
+Other workloads: --workload batch (256 cavities of 64^2..512^2 with drawn
+parameters, one context) and --workload channel (2048^2 mixed-convection
+channel with a random porosity map, inlet and outlet).
+
+One "step" is one time step of the whole path for every domain: pull
+streaming + macroscopic values + boundary reconstruction + D2Q9 and D2Q5
+collisions + store, with the FP64 residual, mass and Nusselt reductions every
+100 steps (their cost is inside the timed region).  Populations are resident
+in HBM before timing starts.
 
 Prints one JSON line.  The `roofline` object prices the step kernel against
-HBM: algorithmic bytes per node update are 14 populations read + written
-(112 B in FP32, 56 B in FP16).  `cpu_baseline` times the FP64 CPU oracle on
-a few steps of the same workload on the host cores.
+HBM: algorithmic bytes per node update are the 14 populations read and
+written (112 B FP32, 56 B FP16, 76 B mixed) plus 4 B for a porosity field.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload on the host cores.
 """
 import argparse
 import hashlib
@@ -35,7 +41,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage, n):
+def measured_traffic(key):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
@@ -43,28 +49,69 @@ def measured_traffic(storage, n):
         data = json.load(open(path))
     except (OSError, ValueError):
         return None
-    rec = data.get("%s_%d" % (storage, n))
+    rec = data.get(key)
     if not rec or rec.get("kernel_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(case, steps):
-    """The FP64 oracle (test infrastructure) on `steps` steps of the workload."""
+def build_workload(args):
+    """(list of domain parameter dicts, workload description, short key)."""
+    from paper_2110_05943_amd import workloads
+    if args.workload == "cavity":
+        n = args.n
+        cases = [workloads.cavity(n, Ra=1e6, Da=1e-4, phi=0.4, Pr=1.0, storage=args.storage)]
+        desc = ("porous cavity natural convection %dx%d, Ra=1e6, Da=1e-4, phi=0.4, Pr=1, "
+                "%s deviation storage" % (n, n, args.storage))
+        return cases, desc, "cavity%d_%s" % (n, args.storage)
+    if args.workload == "batch":
+        cases = workloads.batch(count=args.count, seed=3, storage=args.storage)
+        desc = ("%d porous cavities in one context, N in {64,128,256,512}, Ra 1e3..1e7, "
+                "Da 1e-5..1e-1, phi 0.3..0.95, Pr {0.71,1,7}, sigma 0.8..1.2 (seed 3), "
+                "%s deviation storage" % (args.count, args.storage))
+        return cases, desc, "batch%d_%s" % (args.count, args.storage)
+    n = args.n if args.n != 4096 else 2048
+    cases = [workloads.hetero_channel(n, n, ell=32, seed=4, storage=args.storage)]
+    desc = ("porous mixed-convection channel %dx%d, inlet/outlet, random porosity map "
+            "(l=32, eps 0.3..0.9, mean Da=1e-3), Re=100, Ri=1, Pr=1, %s deviation storage"
+            % (n, n, args.storage))
+    return cases, desc, "channel%d_%s" % (n, args.storage)
+
+
+def initial_state(solver, cases):
+    from paper_2110_05943_amd import inputs
+    for k, c in enumerate(cases):
+        if c["bc"][0] == "wall_T":  # cavity: T = 0.5 + seeded noise
+            solver.set_state(k, inputs.cavity_initial_T(c["nx"], seed=1, ny=c["ny"]))
+
+
+def cpu_baseline(cases, steps):
+    """The FP64 oracle (test infrastructure) on a bounded sample of the
+    workload: `steps` steps of its domains, in order, until about 3e8 node
+    updates are reached."""
     import numpy as np
     from paper_2110_05943_amd import inputs
     from tests.cases import oracle_lattice
-    n = case["nx"]
-    lat = oracle_lattice(case)
-    lat.init_equilibrium(inputs.cavity_initial_T(n, seed=1))
-    t0 = time.perf_counter()
-    lat.step(steps)
-    dt = time.perf_counter() - t0
+    lus, dt, used = 0, 0.0, 0
+    for c in cases:
+        lat = oracle_lattice(c)
+        if c["bc"][0] == "wall_T":
+            lat.init_equilibrium(inputs.cavity_initial_T(c["nx"], seed=1, ny=c["ny"]))
+        else:
+            lat.init_equilibrium(c.get("T_init", 0.5))
+        t0 = time.perf_counter()
+        lat.step(steps)
+        dt += time.perf_counter() - t0
+        assert np.isfinite(lat.f[:9]).all()
+        lus += c["nx"] * c["ny"] * steps
+        used += 1
+        if lus >= 3e8:
+            break
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    assert np.isfinite(lat.f[:9]).all()
-    return {"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+    return {"value": round(lus / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
-            "sample": "%d steps of the same %dx%d cavity, FP64, OpenMP, %.1f s" % (steps, n, n, dt)}
+            "sample": "%d steps of %d of the %d domains (%.3g node updates), FP64, OpenMP, %.1f s"
+                      % (steps, used, len(cases), lus, dt)}
 
 
 def main():
@@ -72,11 +119,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--workload", choices=("cavity", "batch", "channel"), default="cavity")
+    ap.add_argument("--n", type=int, default=4096, help="grid size (cavity; channel: 2048)")
+    ap.add_argument("--count", type=int, default=256, help="domains of the batch workload")
     ap.add_argument("--storage", choices=("f32", "f16", "mixed"), default="f32")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time launch shapes first")
+    ap.add_argument("--launch", type=str, default=None, help="tile_x,tile_y,blocks")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
@@ -100,13 +150,14 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": 2 * x.numel() * 4,
                           "copy_GBps": round(2 * x.numel() * 4 / ms / 1e6, 1)}), flush=True)
         return
-    from paper_2110_05943_amd import Solver, inputs
-    from tests.cases import cavity
+    from paper_2110_05943_amd import WEST, Solver
+    from paper_2110_05943_amd._binding import BYTES_PER_UPDATE
 
-    n = args.n
-    case = cavity(n, Ra=1e6, Da=1e-4, phi=0.4, Pr=1.0, storage=args.storage)
-    s = Solver(case, device="cuda:0")
-    s.set_state(0, inputs.cavity_initial_T(n, seed=1))
+    cases, desc, key = build_workload(args)
+    s = Solver(cases, device="cuda:0")
+    initial_state(s, cases)
+    if args.launch:
+        s.set_launch(*[int(v) for v in args.launch.split(",")])
     if args.autotune:
         s.autotune()
     shape = s.get_launch()
@@ -127,19 +178,17 @@ def main():
         e1.record(s.stream)
         events.append((e0, e1, chunk))
         done += chunk
-        if done % REDUCE_EVERY == 0 or done == K:
-            ru, rT, mass = s.residual(0)
-            nu = s.nusselt(0, 0)
+        ru, rT, mass, status = s.residual_all()
+        nu = s.nusselt_all(WEST) if args.workload != "channel" else s.nusselt_all(2)
     s.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     kernel_ms = sum(a.elapsed_time(b) for a, b, _ in events) / K
-    from paper_2110_05943_amd._binding import BYTES_PER_UPDATE
-    bytes_per_lu = BYTES_PER_UPDATE[args.storage]
-    nodes = n * n
+    nodes = sum(c["nx"] * c["ny"] for c in cases)
+    bytes_per_lu = BYTES_PER_UPDATE[args.storage] + (4 if cases[0].get("eps") is not None else 0)
     achieved = bytes_per_lu * nodes / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.storage, n)
+    traffic = measured_traffic(key)
     mlups = nodes * K / wall / 1e6
     out = {
         "metric": METRIC,
@@ -155,19 +204,20 @@ def main():
         "dtype": {"f32": "f64 arithmetic, f32 storage", "f16": "f32 arithmetic, f16 storage",
                   "mixed": "f32 arithmetic, f16 flow / f32 temperature storage"}[args.storage],
         "data": "synthetic",
-        "config": {"workload": "porous cavity natural convection %dx%d, Ra=1e6, Da=1e-4, "
-                               "phi=0.4, Pr=1, %s deviation storage" % (n, n, args.storage),
-                   "grid": [n, n], "storage": args.storage, "launch_shape": list(shape),
+        "config": {"workload": desc, "domains": len(cases), "nodes": nodes,
+                   "storage": args.storage, "launch_shape": list(shape),
                    "reductions_every": REDUCE_EVERY},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel": "step_kernel", "kernel_us": round(kernel_ms * 1e3, 2),
                      "bytes_per_node_update": bytes_per_lu},
-        "state_check": {"res_u": ru, "res_T": rT, "mass": mass, "nu_hot": nu},
+        "state_check": {"res_u_max": float(max(ru)), "res_T_max": float(max(rT)),
+                        "diverged": int((status != 0).sum()), "mass": float(sum(mass)),
+                        "nu_first": float(nu[0])},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(cases, args.cpu_steps)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

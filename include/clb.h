@@ -46,7 +46,8 @@ typedef enum {
   CLB_ERR_HIP = 2,        /* a HIP runtime call failed (launch, copy, fault)   */
   CLB_ERR_WORKSPACE = 3,  /* workspace too small or misaligned (256 B)         */
   CLB_ERR_DIVERGED = 4,   /* a non-finite value was found in the fields        */
-  CLB_ERR_STATE = 5       /* call not valid in the current state               */
+  CLB_ERR_STATE = 5,      /* call not valid in the current state               */
+  CLB_NOT_CONVERGED = 6   /* per-domain result of clb_run: still unsteady      */
 } clb_status;
 
 /* Side kinds (index 0..3 = W, E, S, N). */
@@ -171,8 +172,10 @@ clb_status clb_nusselt(clb_ctx *ctx, int32_t cavity, int32_t side, double *nu_me
 /* Mean Nusselt number on one side for every domain (count values). */
 clb_status clb_nusselt_all(clb_ctx *ctx, int32_t side, double *nu_mean);
 
-/* Relative change between the last two steps, r_u = |u^n - u^(n-1)|_2 / |u^n|_2
- * over (u, v), r_T likewise on T, and the mass sum(rho), all in FP64.
+/* Relative change per step, r_u = |u^n - u^(n-k)|_2 / (k |u^n|_2) over (u, v),
+ * r_T likewise on T, and the mass sum(rho), all in FP64.  k = 1 after
+ * clb_step (the change between the last two steps); after clb_run, k is the
+ * length of its last round.
  * Returns CLB_ERR_STATE before the first step and CLB_ERR_DIVERGED (with the
  * out-values set) when a field holds a non-finite value.  Synchronizes. */
 clb_status clb_residual(clb_ctx *ctx, int32_t cavity, double *res_u, double *res_T,
@@ -191,6 +194,36 @@ clb_status clb_set_state(clb_ctx *ctx, int32_t cavity, const double *u, const do
 
 /* Choose which domains clb_step advances (active[i] != 0).  Synchronizes. */
 clb_status clb_set_active(clb_ctx *ctx, const uint8_t *active);
+
+/* Run to steady state with retirement (batched stepping of many domains).
+ * Advances the active domains in rounds of `check_every` steps, at most
+ * `max_steps` steps in total.  After each round it evaluates, for every
+ * domain still running, the relative change per step over the round (the
+ * residual of clb_residual with k = the round length); a domain with
+ * max(res_u, res_T) <= tol is retired (made inactive) with status CLB_OK, a
+ * domain holding a non-finite value is retired with CLB_ERR_DIVERGED.  The
+ * paper fixes no steady-state criterion.  Measuring the change over a whole
+ * round rather than one step divides the noise floor that stochastic
+ * rounding leaves in the single-step change (about 1e-7 in u and 1e-8 in T
+ * with FP32 storage) by the round length, while a smooth approach to the
+ * steady state gives nearly the same value either way.
+ *   steps_taken[count]: steps this call advanced each domain;
+ *   status[count]:      CLB_OK (steady), CLB_ERR_DIVERGED, CLB_NOT_CONVERGED
+ *                       (still active after max_steps), or CLB_ERR_STATE for
+ *                       a domain that was inactive at entry (0 steps);
+ *   nu_record:          NULL, or count * max_records values (domain-major):
+ *                       the mean Nusselt number of side `nu_side` after round
+ *                       r (step (r+1) * check_every) for r < max_records, NaN
+ *                       for rounds after the domain retired.  nu_side = -1
+ *                       records nothing; otherwise no domain may have a
+ *                       periodic side there.
+ * Retired domains stay inactive on return (clb_set_active resumes them).
+ * Returns CLB_ERR_ARG for invalid arguments (out-arrays untouched), a HIP
+ * error if a launch or copy fails, CLB_OK otherwise.  Synchronizes after
+ * every round. */
+clb_status clb_run(clb_ctx *ctx, int64_t max_steps, int32_t check_every, double tol,
+                   int32_t nu_side, double *nu_record, int32_t max_records,
+                   int64_t *steps_taken, int32_t *status);
 
 /* Byte-exact checkpoint of all population planes and the step counter.
  * clb_state_bytes gives the size of the host buffer.  Synchronizes. */

@@ -13,7 +13,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libclb.so")
 
-OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_DIVERGED, ERR_STATE = range(6)
+OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_DIVERGED, ERR_STATE, NOT_CONVERGED = range(7)
 PERIODIC, WALL_T, WALL_ADIABATIC, INLET, OUTLET = range(5)
 WEST, EAST, SOUTH, NORTH = range(4)
 STORE_F32, STORE_F16, STORE_MIXED = 0, 1, 2
@@ -63,7 +63,7 @@ class Derived(C.Structure):
 EXPORTS = (
     "clb_params_default", "clb_derive", "clb_workspace_bytes", "clb_create", "clb_step",
     "clb_macros", "clb_nusselt", "clb_nusselt_all", "clb_residual", "clb_residual_all",
-    "clb_set_state", "clb_set_active", "clb_state_bytes", "clb_get_state", "clb_put_state",
+    "clb_set_state", "clb_set_active", "clb_run", "clb_state_bytes", "clb_get_state", "clb_put_state",
     "clb_steps_done", "clb_set_launch", "clb_get_launch", "clb_autotune", "clb_destroy",
     "clb_strerror",
 )
@@ -93,6 +93,8 @@ def _lib():
             "clb_residual_all": (st, [vp, dp, dp, dp, C.POINTER(C.c_int32)]),
             "clb_set_state": (st, [vp, C.c_int32, dp, dp, dp]),
             "clb_set_active": (st, [vp, C.POINTER(C.c_uint8)]),
+            "clb_run": (st, [vp, C.c_int64, C.c_int32, C.c_double, C.c_int32, dp, C.c_int32,
+                             C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
             "clb_state_bytes": (st, [vp, C.POINTER(C.c_size_t)]),
             "clb_get_state": (st, [vp, vp, C.c_size_t]),
             "clb_put_state": (st, [vp, vp, C.c_size_t]),
@@ -267,6 +269,23 @@ class Solver:
         a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8))
         _check(_lib().clb_set_active(self._ctx, a.ctypes.data_as(C.POINTER(C.c_uint8))),
                "clb_set_active")
+
+    def run(self, max_steps, check_every=100, tol=1e-8, nu_side=None, max_records=0):
+        """Run the active domains to steady state (clb_run).
+
+        Returns dict(steps=int64[count], status=int32[count], nu=(count,
+        max_records) array or None)."""
+        steps = np.zeros(self.count, dtype=np.int64)
+        status = np.zeros(self.count, dtype=np.int32)
+        nu = None
+        if nu_side is not None and max_records > 0:
+            nu = np.empty((self.count, max_records), dtype=np.float64)
+        _check(_lib().clb_run(self._ctx, int(max_steps), int(check_every), float(tol),
+                              -1 if nu_side is None else int(nu_side),
+                              _dptr(nu), int(max_records),
+                              steps.ctypes.data_as(C.POINTER(C.c_int64)),
+                              status.ctypes.data_as(C.POINTER(C.c_int32))), "clb_run")
+        return dict(steps=steps, status=status, nu=nu)
 
     def get_state(self):
         n = C.c_size_t()

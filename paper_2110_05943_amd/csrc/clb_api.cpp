@@ -265,6 +265,7 @@ struct clb_ctx {
   int64_t steps = 0;
   int parity = 0;
   bool snap_valid = false;
+  int64_t snap_span = 1;  // steps between the snapshot and the current state
   hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
@@ -339,7 +340,8 @@ void build_tiles(clb_ctx *c) {
   for (int k = 0; k < c->count; ++k) {
     c->tile0[k] = (int32_t)c->tiles_all.size();
     for (int y0 = 0; y0 < c->p[k].ny; y0 += ty)
-      for (int x0 = 0; x0 < c->p[k].nx; x0 += tx) c->tiles_all.push_back(Tile{k, x0, y0, 0});
+      for (int x0 = 0; x0 < c->p[k].nx; x0 += tx)
+        c->tiles_all.push_back(Tile{k, x0, y0, (int32_t)c->tiles_all.size()});
     c->ntiles[k] = (int32_t)c->tiles_all.size() - c->tile0[k];
     c->desc[k].tile0 = c->tile0[k];
     c->desc[k].ntiles = c->ntiles[k];
@@ -521,10 +523,17 @@ extern "C" void clb_destroy(clb_ctx *c) {
   delete c;
 }
 
-extern "C" clb_status clb_step(clb_ctx *c, int64_t n) {
-  if (!c || n < 0) return CLB_ERR_ARG;
-  if (n == 0) return CLB_OK;
-  int64_t rest = n - 1;  // the final step is launched directly and records the snapshot
+namespace {
+// Enqueues n >= 1 steps.  One step, launched directly, records the snapshot of
+// (u, v, theta) for the residual: the last one (residual over one step) or,
+// with snap_first, the first one (residual over all n steps).
+clb_status advance(clb_ctx *c, int64_t n, bool snap_first) {
+  if (snap_first) {
+    const clb_status s = launch_one(c, 1, c->stream);
+    if (s != CLB_OK) return s;
+    c->parity ^= 1;
+  }
+  int64_t rest = n - 1;  // steps besides the one that records the snapshot
   while (rest > 0) {
     if (rest >= kGraphSteps) {
       if (!c->graph[c->parity]) {
@@ -540,12 +549,22 @@ extern "C" clb_status clb_step(clb_ctx *c, int64_t n) {
       --rest;
     }
   }
-  const clb_status s = launch_one(c, 1, c->stream);
-  if (s != CLB_OK) return s;
-  c->parity ^= 1;
+  if (!snap_first) {
+    const clb_status s = launch_one(c, 1, c->stream);
+    if (s != CLB_OK) return s;
+    c->parity ^= 1;
+  }
   c->steps += n;
   c->snap_valid = true;
+  c->snap_span = snap_first ? n : 1;
   return CLB_OK;
+}
+}  // namespace
+
+extern "C" clb_status clb_step(clb_ctx *c, int64_t n) {
+  if (!c || n < 0) return CLB_ERR_ARG;
+  if (n == 0) return CLB_OK;
+  return advance(c, n, false);
 }
 
 extern "C" clb_status clb_macros(clb_ctx *c, int32_t cav, double *rho, double *u, double *v,
@@ -602,10 +621,17 @@ extern "C" clb_status clb_nusselt_all(clb_ctx *c, int32_t side, double *nu_mean)
 }
 
 namespace {
-clb_status residual_sums(clb_ctx *c, std::vector<double> &h) {
+// Residual sums per domain into h (kRed values per domain).  With
+// active_only, only the tiles of active domains are evaluated and the slots
+// of the other domains keep their last values.
+clb_status residual_sums(clb_ctx *c, std::vector<double> &h, bool active_only = false) {
   if (!c->snap_valid) return CLB_ERR_STATE;
-  HIPCHK(clb::launch_residual(c->d_desc, c->d_tiles_all, (int)c->tiles_all.size(), c->parity,
-                              c->d_partials, c->storage, c->shape, c->stream));
+  if (active_only)
+    HIPCHK(clb::launch_residual(c->d_desc, c->d_tiles_active, (int)c->tiles_active.size(),
+                                c->parity, c->d_partials, c->storage, c->shape, c->stream));
+  else
+    HIPCHK(clb::launch_residual(c->d_desc, c->d_tiles_all, (int)c->tiles_all.size(), c->parity,
+                                c->d_partials, c->storage, c->shape, c->stream));
   HIPCHK(clb::launch_residual_finalize(c->d_desc, c->count, c->d_partials, c->d_results,
                                        c->stream));
   h.assign((size_t)clb::kRed * c->count, 0.0);
@@ -615,9 +641,12 @@ clb_status residual_sums(clb_ctx *c, std::vector<double> &h) {
   return CLB_OK;
 }
 
-void residual_values(const double *r, double *ru, double *rT, double *mass, bool *bad) {
-  *ru = r[1] > 0 ? std::sqrt(r[0] / r[1]) : std::numeric_limits<double>::infinity();
-  *rT = r[3] > 0 ? std::sqrt(r[2] / r[3]) : std::numeric_limits<double>::infinity();
+// Relative change per step over the `span` steps since the snapshot.
+void residual_values(const double *r, int64_t span, double *ru, double *rT, double *mass,
+                     bool *bad) {
+  const double inf = std::numeric_limits<double>::infinity();
+  *ru = r[1] > 0 ? std::sqrt(r[0] / r[1]) / (double)span : inf;
+  *rT = r[3] > 0 ? std::sqrt(r[2] / r[3]) / (double)span : inf;
   *mass = r[6] + r[4];
   *bad = r[5] > 0 || !std::isfinite(r[0]) || !std::isfinite(r[2]) || !std::isfinite(r[4]);
 }
@@ -631,7 +660,7 @@ extern "C" clb_status clb_residual(clb_ctx *c, int32_t cav, double *res_u, doubl
   if (s != CLB_OK) return s;
   double ru, rT, m;
   bool bad;
-  residual_values(&h[(size_t)clb::kRed * cav], &ru, &rT, &m, &bad);
+  residual_values(&h[(size_t)clb::kRed * cav], c->snap_span, &ru, &rT, &m, &bad);
   if (res_u) *res_u = ru;
   if (res_T) *res_T = rT;
   if (mass) *mass = m;
@@ -647,7 +676,7 @@ extern "C" clb_status clb_residual_all(clb_ctx *c, double *res_u, double *res_T,
   for (int k = 0; k < c->count; ++k) {
     double ru, rT, m;
     bool bad;
-    residual_values(&h[(size_t)clb::kRed * k], &ru, &rT, &m, &bad);
+    residual_values(&h[(size_t)clb::kRed * k], c->snap_span, &ru, &rT, &m, &bad);
     if (res_u) res_u[k] = ru;
     if (res_T) res_T[k] = rT;
     if (mass) mass[k] = m;
@@ -681,6 +710,72 @@ extern "C" clb_status clb_set_active(clb_ctx *c, const uint8_t *active) {
   if (!c || !active) return CLB_ERR_ARG;
   for (int k = 0; k < c->count; ++k) c->active[k] = active[k] ? 1 : 0;
   return upload_tiles(c);
+}
+
+// ------------------------------------------------------ run to steady state
+
+extern "C" clb_status clb_run(clb_ctx *c, int64_t max_steps, int32_t check_every, double tol,
+                              int32_t nu_side, double *nu_record, int32_t max_records,
+                              int64_t *steps_taken, int32_t *status) {
+  if (!c || max_steps < 0 || check_every < 1 || !(tol >= 0.0) || !steps_taken || !status)
+    return CLB_ERR_ARG;
+  if (nu_side < -1 || nu_side > 3 || (nu_record && (max_records < 1 || nu_side < 0)))
+    return CLB_ERR_ARG;
+  if (nu_side >= 0)
+    for (int k = 0; k < c->count; ++k)
+      if (c->p[k].bc[nu_side] == CLB_PERIODIC) return CLB_ERR_ARG;
+  const int n = c->count;
+  std::vector<uint8_t> live(c->active);
+  std::vector<int64_t> taken(n, 0);
+  std::vector<int32_t> st(n, CLB_ERR_STATE);
+  for (int k = 0; k < n; ++k)
+    if (live[k]) st[k] = CLB_NOT_CONVERGED;
+  std::vector<double> nu(n), h;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  if (nu_record) std::fill(nu_record, nu_record + (size_t)n * max_records, nan);
+  int64_t done = 0;
+  int round = 0;
+  auto any_live = [&] { return std::find(live.begin(), live.end(), 1) != live.end(); };
+  while (done < max_steps && any_live()) {
+    const int64_t m = std::min<int64_t>(check_every, max_steps - done);
+    clb_status s = advance(c, m, true);
+    if (s != CLB_OK) return s;
+    done += m;
+    s = residual_sums(c, h, true);
+    if (s != CLB_OK) return s;
+    if (nu_side >= 0) {
+      HIPCHK(clb::launch_nusselt(c->d_desc, 0, n, nu_side, c->parity, c->d_nu, nullptr,
+                                 c->storage, c->stream));
+      HIPCHK(hipMemcpyAsync(nu.data(), c->d_nu, sizeof(double) * n, hipMemcpyDeviceToHost,
+                            c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    bool retired = false;
+    for (int k = 0; k < n; ++k) {
+      if (!live[k]) continue;
+      taken[k] += m;
+      if (nu_record && round < max_records) nu_record[(size_t)k * max_records + round] = nu[k];
+      double ru, rT, mass;
+      bool bad;
+      residual_values(&h[(size_t)clb::kRed * k], c->snap_span, &ru, &rT, &mass, &bad);
+      if (bad)
+        st[k] = CLB_ERR_DIVERGED;
+      else if (std::max(ru, rT) <= tol)
+        st[k] = CLB_OK;
+      else
+        continue;
+      live[k] = 0;
+      retired = true;
+    }
+    ++round;
+    if (retired) {
+      s = clb_set_active(c, live.data());
+      if (s != CLB_OK) return s;
+    }
+  }
+  std::copy(taken.begin(), taken.end(), steps_taken);
+  std::copy(st.begin(), st.end(), status);
+  return CLB_OK;
 }
 
 // ------------------------------------------------------------- checkpoint
@@ -859,6 +954,7 @@ extern "C" const char *clb_strerror(clb_status s) {
     case CLB_ERR_WORKSPACE: return "workspace too small or misaligned";
     case CLB_ERR_DIVERGED: return "non-finite value in the fields";
     case CLB_ERR_STATE: return "call not valid in the current state";
+    case CLB_NOT_CONVERGED: return "not steady within the step limit";
   }
   return "unknown status";
 }

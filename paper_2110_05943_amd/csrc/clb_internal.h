@@ -16,9 +16,11 @@ constexpr int kPlanes = 14;
 // |du|^2, |u|^2, dT^2, T^2, sum(rho - 1), non-finite count, nodes, unused.
 constexpr int kRed = 8;
 
-// One work tile: domain index and the origin of a tile of nodes.
+// One work tile: domain index (-1: padding entry, skipped), the origin of a
+// tile of nodes, and its index in the list of all tiles (the slot of its
+// residual partial sums).
 struct Tile {
-  int32_t cav, x0, y0, pad;
+  int32_t cav, x0, y0, id;
 };
 
 // Per-domain constants and addresses read by every kernel (scalar loads).
@@ -76,6 +78,8 @@ hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
 hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int parity,
                        const float *uvth /* 3 dense planes or null */, float th_uniform,
                        int storage, hipStream_t s);
+// Partial sums of the tiles in `tiles` (padding entries skipped) go to slot
+// tiles[t].id of `partials`.
 hipError_t launch_residual(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int parity,
                            double *partials, int storage, LaunchShape shape, hipStream_t s);
 hipError_t launch_residual_finalize(const CavDesc *descs, int32_t count, const double *partials,

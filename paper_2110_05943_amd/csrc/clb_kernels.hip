@@ -618,6 +618,7 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
   __shared__ double lds[8][kRed];
   const int t = blockIdx.x;
   const int cav = __builtin_amdgcn_readfirstlane(tiles[t].cav);
+  if (cav < 0) return;  // padding entry of an active list (uniform per block)
   const CavDesc &d = descs[cav];
   const int x = tiles[t].x0 + threadIdx.x, y = tiles[t].y0 + threadIdx.y;
   double v[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -643,8 +644,9 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
     v[6] = 1.0;
   }
   block_sum(v, lds);
+  const size_t slot = (size_t)tiles[t].id * kRed;
   if (threadIdx.x == 0 && threadIdx.y == 0)
-    for (int k = 0; k < kRed; ++k) partials[(size_t)t * kRed + k] = v[k];
+    for (int k = 0; k < kRed; ++k) partials[slot + k] = v[k];
 }
 
 // Per-domain totals of the tile partial sums (fixed order, deterministic).

@@ -8,15 +8,7 @@ import numpy as np
 import oracle
 from oracle import params as op
 
-CAVITY_BC = ("wall_T", "wall_T", "wall_adiabatic", "wall_adiabatic")
-CHANNEL_BC = ("periodic", "periodic", "wall_T", "wall_T")
-
-
-def cavity(n, Ra=1e3, Pr=1.0, Da=1e-2, phi=0.6, sigma=1.0, ny=None, **kw):
-    c = dict(nx=n, ny=n if ny is None else ny, bc=CAVITY_BC, bc_T=(1.0, 0.0, 0.0, 0.0), Ra=Ra,
-             Pr=Pr, Da=Da, phi=phi, F_phi=-1.0, sigma=sigma, scaling="cavity")
-    c.update(kw)
-    return c
+from paper_2110_05943_amd.workloads import CAVITY_BC, CHANNEL_BC, cavity  # noqa: F401
 
 
 def oracle_values(case):

@@ -94,3 +94,13 @@ def test_create_rejects_small_workspace():
     ctx = C.c_void_p()
     # a too-small (and null) workspace fails before any device call
     assert lib.clb_create(C.byref(p), 1, None, 16, None, C.byref(ctx)) == B.ERR_WORKSPACE
+
+
+def test_calls_without_context_are_rejected():
+    lib = B._lib()
+    steps = (C.c_int64 * 1)()
+    status = (C.c_int32 * 1)()
+    assert lib.clb_run(None, 100, 10, 1e-8, -1, None, 0, steps, status) == B.ERR_ARG
+    assert lib.clb_step(None, 1) == B.ERR_ARG
+    assert lib.clb_set_active(None, None) == B.ERR_ARG
+    assert lib.clb_strerror(B.NOT_CONVERGED).decode() == "not steady within the step limit"
