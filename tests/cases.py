@@ -78,3 +78,42 @@ def vel_rel_l2(ga, oa):
     num = np.sum((ga["ux"] - oa["ux"]) ** 2 + (ga["uy"] - oa["uy"]) ** 2)
     den = np.sum(oa["ux"] ** 2 + oa["uy"] ** 2)
     return math.sqrt(num / den)
+
+
+def sampled_oracle(case, vals, fields, x, y, k):
+    """Oracle value at node (x, y) after k steps, from the crop of the initial
+    fields that contains its dependence cone (information moves one node per
+    step; boundary nodes read two nodes inward).  Window sides that are not
+    sides of the domain become walls more than k nodes away.  A window on an
+    inlet side spans the whole inlet, whose profile depends on the position
+    along it.  `vals` are the domain's oracle values; per-node arrays (porosity
+    map) are cropped with the window."""
+    nx, ny = case["nx"], case["ny"]
+    h = k + 3
+    x0, x1 = max(0, x - h), min(nx - 1, x + h)
+    y0, y1 = max(0, y - h), min(ny - 1, y + h)
+    bc = list(vals["bc"])
+    if bc[0] == "inlet" and x0 == 0 or bc[1] == "inlet" and x1 == nx - 1:
+        y0, y1 = 0, ny - 1
+    if bc[2] == "inlet" and y0 == 0 or bc[3] == "inlet" and y1 == ny - 1:
+        x0, x1 = 0, nx - 1
+    if x0 > 0:
+        bc[0] = "wall_T"
+    if x1 < nx - 1:
+        bc[1] = "wall_T"
+    if y0 > 0:
+        bc[2] = "wall_T"
+    if y1 < ny - 1:
+        bc[3] = "wall_T"
+    w = dict(vals)
+    w["bc"] = tuple(bc)
+    for key in ("phi", "K", "Fphi"):
+        if isinstance(w[key], np.ndarray):
+            w[key] = np.ascontiguousarray(w[key][y0:y1 + 1, x0:x1 + 1])
+    win = oracle.Lattice(x1 - x0 + 1, y1 - y0 + 1, nthreads=1, **w)
+    u, v, T = fields
+    win.init_equilibrium(T[y0:y1 + 1, x0:x1 + 1], u[y0:y1 + 1, x0:x1 + 1],
+                         v[y0:y1 + 1, x0:x1 + 1])
+    win.step(k)
+    m = win.macros()
+    return {key: val[y - y0, x - x0] for key, val in m.items()}

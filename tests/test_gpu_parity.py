@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 from paper_2110_05943_amd import inputs
-from tests.cases import CAVITY_BC, cavity, oracle_lattice, rel_l2, vel_rel_l2
+from tests.cases import (CAVITY_BC, cavity, oracle_lattice, rel_l2, sampled_oracle,
+                         vel_rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -256,35 +257,6 @@ def test_checkpoint_roundtrip_and_determinism(Solver):
 
 
 # ------------------------------------------------- full size, sampled nodes
-
-def sampled_oracle(case, vals, fields, x, y, k):
-    """Oracle value at node (x, y) after k steps from the crop of the initial
-    fields that contains its dependence cone; window sides that are not sides
-    of the domain become walls farther than k nodes away.  `vals` are the
-    domain's lattice values (uniform medium)."""
-    from oracle import Lattice
-    nx, ny = case["nx"], case["ny"]
-    h = k + 3
-    x0, x1 = max(0, x - h), min(nx - 1, x + h)
-    y0, y1 = max(0, y - h), min(ny - 1, y + h)
-    bc = list(vals["bc"])
-    if x0 > 0:
-        bc[0] = "wall_T"
-    if x1 < nx - 1:
-        bc[1] = "wall_T"
-    if y0 > 0:
-        bc[2] = "wall_T"
-    if y1 < ny - 1:
-        bc[3] = "wall_T"
-    w = dict(vals)
-    w["bc"] = tuple(bc)
-    win = Lattice(x1 - x0 + 1, y1 - y0 + 1, nthreads=1, **w)
-    u, v, T = fields
-    win.init_equilibrium(T[y0:y1 + 1, x0:x1 + 1], u[y0:y1 + 1, x0:x1 + 1], v[y0:y1 + 1, x0:x1 + 1])
-    win.step(k)
-    m = win.macros()
-    return {key: val[y - y0, x - x0] for key, val in m.items()}
-
 
 @pytest.mark.parametrize("storage,tol", [("f32", 2e-6), ("f16", 2e-3), ("mixed", 2e-3)])
 def test_full_size_4096_sampled(Solver, storage, tol):
