@@ -65,6 +65,7 @@ def build_workload(args):
                 "%s deviation storage" % (n, n, args.storage))
         return cases, desc, "cavity%d_%s" % (n, args.storage)
     if args.workload == "batch":
+        args.count = args.count or 256
         cases = workloads.batch(count=args.count, seed=3, storage=args.storage)
         desc = ("%d porous cavities in one context, N in {64,128,256,512}, Ra 1e3..1e7, "
                 "Da 1e-5..1e-1, phi 0.3..0.95, Pr {0.71,1,7}, sigma 0.8..1.2 (seed 3), "
@@ -114,14 +115,70 @@ def cpu_baseline(cases, steps):
                       % (steps, used, len(cases), lus, dt)}
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2110_05943_amd", "data", "warmstart_unet.npz")
+
+
+def warmstart_bench(args):
+    """Held-out cavities (128^2, random porosity maps and groups, seed 1) run
+    to steady state twice: from rest and from the trained network's
+    prediction.  Reports the time to steady state (hot-wall Nusselt number
+    within 1e-4 of the from-rest final value) of both."""
+    import numpy as np
+    from paper_2110_05943_amd import inputs
+    from paper_2110_05943_amd import warmstart as W
+    from paper_2110_05943_amd.train_warmstart import load_weights
+    if not os.path.exists(WEIGHTS):
+        print("no trained weights at %s (python -m paper_2110_05943_amd.train_warmstart)"
+              % WEIGHTS, file=sys.stderr)
+        sys.exit(2)
+    count = args.count or 500
+    sur = W.Surrogate(n=128)
+    meta = load_weights(WEIGHTS, sur.net)
+    draws = inputs.warmstart_draws(count, seed=1)
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    r = W.evaluate(sur, draws, tol=1e-9, check_every=5000, max_steps=3_000_000, log=log)
+    sp = np.array([x if x is not None else -1 for x in r["settle_plain"]], dtype=float)
+    sw = np.array([x if x is not None else -1 for x in r["settle_warm"]], dtype=float)
+    ok = (sp > 0) & (sw > 0)
+    dnu = np.abs(np.array(r["nu_warm"]) - np.array(r["nu_plain"]))
+    out = {
+        "metric": "time-to-steady-state (Nu err<=1e-4): plain vs learned warm start",
+        "value": round(float(sp[ok].sum() / sw[ok].sum()), 3) if ok.any() else None,
+        "unit": "x fewer steps (sum over held-out cavities)",
+        "higher_is_better": True,
+        "n_gpus": 1, "data": "synthetic", "dtype": "f64 arithmetic, f32 storage; bf16 network",
+        "config": {"workload": "%d held-out porous cavities 128x128, Ra 1e3..1e6, Da 1e-5..1e-1, "
+                               "Pr {0.71,1,7}, sigma 0.8..1.2, random porosity maps (seed 1)"
+                               % count, "tol": 1e-9, "check_every": 5000},
+        "steps_to_steady_median": {"plain": float(np.median(sp[ok])),
+                                   "learned": float(np.median(sw[ok]))},
+        "median_per_case_speedup": float(np.median(sp[ok] / sw[ok])) if ok.any() else None,
+        "cases_compared": int(ok.sum()),
+        "wall_s": {"plain": round(r["wall_plain"], 2),
+                   "learned": round(r["wall_warm"] + r["inference_s"], 2),
+                   "inference": round(r["inference_s"], 3)},
+        "nu_warm_vs_plain": {"max_abs": float(np.nanmax(dnu)),
+                             "within_1e-4": int((dnu <= 1e-4).sum())},
+        "prediction_rel_l2_median": float(np.median(r["pred_rel_l2"])),
+        "training": {k: meta[k] for k in ("train", "epochs", "train_s", "datagen_s")
+                     if k in meta},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", choices=("cavity", "batch", "channel"), default="cavity")
+    ap.add_argument("--workload", choices=("cavity", "batch", "channel", "warmstart"),
+                    default="cavity")
     ap.add_argument("--n", type=int, default=4096, help="grid size (cavity; channel: 2048)")
-    ap.add_argument("--count", type=int, default=256, help="domains of the batch workload")
+    ap.add_argument("--count", type=int, default=None,
+                    help="domains of the batch (256) or warmstart (500) workload")
     ap.add_argument("--storage", choices=("f32", "f16", "mixed"), default="f32")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -150,6 +207,8 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": 2 * x.numel() * 4,
                           "copy_GBps": round(2 * x.numel() * 4 / ms / 1e6, 1)}), flush=True)
         return
+    if args.workload == "warmstart":
+        return warmstart_bench(args)
     from paper_2110_05943_amd import WEST, Solver
     from paper_2110_05943_amd._binding import BYTES_PER_UPDATE
 

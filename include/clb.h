@@ -192,6 +192,17 @@ clb_status clb_residual_all(clb_ctx *ctx, double *res_u, double *res_T, double *
 clb_status clb_set_state(clb_ctx *ctx, int32_t cavity, const double *u, const double *v,
                          const double *T);
 
+/* Warm start from device memory: the same equilibrium initialisation as
+ * clb_set_state, from an FP32 device array holding, for node i = y*nx + x,
+ * u = u_scale d_fields[i*stride], v = u_scale d_fields[i*stride + 1] and
+ * T = T_offset + d_fields[i*stride + 2] (stride >= 3; e.g. a network output
+ * with 16 channels per pixel).  Stream-ordered on the context's stream; no
+ * synchronization: d_fields must be complete in stream order of the
+ * context's stream (e.g. written on that stream) and stay allocated until the
+ * work is done. */
+clb_status clb_set_state_device(clb_ctx *ctx, int32_t cavity, const float *d_fields,
+                                int64_t stride, double u_scale, double T_offset);
+
 /* Choose which domains clb_step advances (active[i] != 0).  Synchronizes. */
 clb_status clb_set_active(clb_ctx *ctx, const uint8_t *active);
 

@@ -63,7 +63,7 @@ class Derived(C.Structure):
 EXPORTS = (
     "clb_params_default", "clb_derive", "clb_workspace_bytes", "clb_create", "clb_step",
     "clb_macros", "clb_nusselt", "clb_nusselt_all", "clb_residual", "clb_residual_all",
-    "clb_set_state", "clb_set_active", "clb_run", "clb_state_bytes", "clb_get_state", "clb_put_state",
+    "clb_set_state", "clb_set_state_device", "clb_set_active", "clb_run", "clb_state_bytes", "clb_get_state", "clb_put_state",
     "clb_steps_done", "clb_set_launch", "clb_get_launch", "clb_autotune", "clb_destroy",
     "clb_strerror",
 )

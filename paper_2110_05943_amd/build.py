@@ -7,7 +7,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libclb.so")
-SOURCES = [os.path.join(CSRC, "clb_kernels.hip"), os.path.join(CSRC, "clb_api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("clb_kernels.hip", "clb_state.hip", "nn_kernels.hip", "clb_api.cpp")]
 ARCH = os.environ.get("CLB_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code.

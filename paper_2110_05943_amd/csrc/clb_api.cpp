@@ -706,6 +706,19 @@ extern "C" clb_status clb_set_state(clb_ctx *c, int32_t cav, const double *u, co
   return CLB_OK;
 }
 
+extern "C" clb_status clb_set_state_device(clb_ctx *c, int32_t cav, const float *d_fields,
+                                           int64_t stride, double u_scale, double T_offset) {
+  if (!c || cav < 0 || cav >= c->count || !d_fields || stride < 3) return CLB_ERR_ARG;
+  const clb_params &p = c->p[cav];
+  const int64_t n = (int64_t)p.nx * p.ny;
+  HIPCHK(clb::launch_uvT_planes(d_fields, stride, n, u_scale, T_offset - p.T_init, c->d_obs,
+                                c->stream));
+  HIPCHK(clb::launch_init(c->d_desc, cav, p.nx, p.ny, c->parity, c->d_obs, 0.0f, c->storage,
+                          c->stream));
+  c->snap_valid = false;
+  return CLB_OK;
+}
+
 extern "C" clb_status clb_set_active(clb_ctx *c, const uint8_t *active) {
   if (!c || !active) return CLB_ERR_ARG;
   for (int k = 0; k < c->count; ++k) c->active[k] = active[k] ? 1 : 0;

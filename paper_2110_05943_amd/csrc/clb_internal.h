@@ -91,4 +91,9 @@ hipError_t launch_nusselt(const CavDesc *descs, int32_t cav0, int32_t ncav, int3
                           int parity, double *nu_mean, double *nu_local, int storage,
                           hipStream_t s);
 
+// (clb_state.hip) planes[0..n) = u_scale src[i*stride], planes[n..2n) =
+// u_scale src[i*stride + 1], planes[2n..3n) = th_offset + src[i*stride + 2].
+hipError_t launch_uvT_planes(const float *src, int64_t stride, int64_t n, double u_scale,
+                             double th_offset, float *planes, hipStream_t s);
+
 }  // namespace clb

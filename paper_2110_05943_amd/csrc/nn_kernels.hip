@@ -1,0 +1,571 @@
+// Kernels of the warm-start network (include/clb_nn.h): implicit-GEMM 3x3
+// convolutions on the gfx950 matrix cores (bf16 MFMA, FP32 accumulation),
+// their weight gradients, and the elementwise layers, loss and optimizer.
+//
+// Matrix-core operand layout (v_mfma_f32_16x16x32_bf16, one wave of 64 lanes):
+//   A (16 x 32):  lane l holds row l % 16, columns 8 (l / 16) .. + 7;
+//   B (32 x 16):  lane l holds column l % 16, rows 8 (l / 16) .. + 7;
+//   D (16 x 16):  lane l holds column l % 16, rows 4 (l / 16) .. + 3.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "clb.h"
+#include "clb_nn.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPixTile = 64;  // pixels per workgroup of the convolution (4 waves x 16)
+constexpr int kCoTile = 64;   // output channels per workgroup (4 MFMA column tiles)
+
+__device__ __forceinline__ f4 mfma16(const bf16x8 &a, const bf16x8 &b, const f4 &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Forward 3x3 convolution as a GEMM: rows = pixels (b, i, j), columns =
+// output channels, reduction index k = t * cin + c (tap-major, channels
+// contiguous).  Each wave computes 16 pixels x up to 64 channels; the
+// reduction runs in steps of 32 (one MFMA per column tile).  cin is a
+// multiple of 16, so a lane's 8 consecutive k lie in one tap and are 16
+// contiguous bytes of x and of the weight row.
+__global__ void __launch_bounds__(256) conv3x3_kernel(
+    const bf16 *__restrict__ x, int B, int H, int W, int cin, const bf16 *__restrict__ wt,
+    const float *__restrict__ bias, int cout, int act, float slope, void *__restrict__ y,
+    int y_fp32) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int M = B * H * W;
+  const int m0 = blockIdx.x * kPixTile + wave * 16;
+  const int co0 = blockIdx.y * kCoTile;
+  const int nt = min(4, (cout - co0) >> 4);
+  const int K = 9 * cin;
+  const int row = lane & 15, kq = 8 * (lane >> 4);
+  const int m = m0 + row;
+  const bool mok = m < M;
+  int n = 0, py = 0, px = 0;
+  if (mok) {
+    n = m / (H * W);
+    const int r = m - n * H * W;
+    py = r / W;
+    px = r - py * W;
+  }
+  f4 acc[4];
+  for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero = {};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int k = k0 + kq;
+    bf16x8 a = zero;
+    if (k < K && mok) {
+      const int tap = k / cin, c = k - tap * cin;
+      const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        a = *reinterpret_cast<const bf16x8 *>(x + ((size_t)(n * H + yy) * W + xx) * cin + c);
+    }
+    for (int t = 0; t < 4; ++t) {
+      if (t >= nt) break;
+      bf16x8 b = zero;
+      if (k < K) b = *reinterpret_cast<const bf16x8 *>(wt + (size_t)(co0 + 16 * t + row) * K + k);
+      acc[t] = mfma16(a, b, acc[t]);
+    }
+  }
+  for (int t = 0; t < 4; ++t) {
+    if (t >= nt) break;
+    const int co = co0 + 16 * t + row;
+    const float bb = bias ? bias[co] : 0.0f;
+    for (int e = 0; e < 4; ++e) {
+      const int mm = m0 + 4 * (lane >> 4) + e;
+      if (mm >= M) continue;
+      float v = acc[t][e] + bb;
+      if (act) v = v > 0.0f ? v : v * slope;
+      if (y_fp32)
+        static_cast<float *>(y)[(size_t)mm * cout + co] = v;
+      else
+        static_cast<bf16 *>(y)[(size_t)mm * cout + co] = (bf16)v;
+    }
+  }
+}
+
+// Weight gradient as a GEMM: rows = output channels, columns = k = t*cin + c,
+// reduction over the pixels of one chunk.  One wave per (16 channels, 16 k,
+// chunk); partial sums per chunk go to `part` (and, for the first k tile, the
+// bias partial sums to `partb`).
+__global__ void __launch_bounds__(64) wgrad_kernel(const bf16 *__restrict__ dy,
+                                                    const bf16 *__restrict__ x, int B, int H,
+                                                    int W, int cin, int cout, int chunk,
+                                                    float *__restrict__ part,
+                                                    float *__restrict__ partb) {
+  const int lane = threadIdx.x;
+  const int M = B * H * W, K = 9 * cin;
+  const int co = blockIdx.x * 16 + (lane & 15);
+  const int kc = blockIdx.y * 16 + (lane & 15);
+  const int tap = kc / cin, c = kc - tap * cin;
+  const int oy = tap / 3 - 1, ox = tap % 3 - 1;
+  const int p0 = blockIdx.z * chunk, p1 = min(M, p0 + chunk);
+  const int q = 8 * (lane >> 4);
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.0f;
+  for (int p = p0; p < p1; p += 32) {
+    bf16x8 a, b;
+    for (int e = 0; e < 8; ++e) {
+      const int mm = p + q + e;
+      bf16 av = (bf16)0.0f, bv = (bf16)0.0f;
+      if (mm < p1) {
+        av = dy[(size_t)mm * cout + co];
+        const int n = mm / (H * W);
+        const int r = mm - n * H * W;
+        const int yy = r / W + oy, xx = r % W + ox;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          bv = x[((size_t)(n * H + yy) * W + xx) * cin + c];
+      }
+      a[e] = av;
+      b[e] = bv;
+      bsum += (float)av;
+    }
+    acc = mfma16(a, b, acc);
+  }
+  const size_t base = (size_t)blockIdx.z * cout * K;
+  for (int e = 0; e < 4; ++e)
+    part[base + (size_t)(blockIdx.x * 16 + 4 * (lane >> 4) + e) * K + blockIdx.y * 16 +
+         (lane & 15)] = acc[e];
+  if (blockIdx.y == 0 && partb) {
+    bsum += __shfl_xor(bsum, 16, 64);
+    bsum += __shfl_xor(bsum, 32, 64);
+    if (lane < 16) partb[(size_t)blockIdx.z * cout + co] = bsum;
+  }
+}
+
+// Sum of `nsplit` partial arrays of length n in split order.
+__global__ void __launch_bounds__(256) sum_parts_kernel(const float *__restrict__ part,
+                                                        int nsplit, size_t n,
+                                                        float *__restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int z = 0; z < nsplit; ++z) s += part[(size_t)z * n + i];
+  out[i] = s;
+}
+
+__global__ void __launch_bounds__(256) weights_kernel(const float *__restrict__ w32, int cout,
+                                                      int cin, bf16 *__restrict__ wf,
+                                                      bf16 *__restrict__ wb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cout * 9 * cin) return;
+  const int o = i / (9 * cin), r = i - o * 9 * cin, t = r / cin, c = r - t * cin;
+  const bf16 v = (bf16)w32[i];
+  wf[i] = v;
+  wb[((size_t)c * 9 + (8 - t)) * cout + o] = v;
+}
+
+__global__ void __launch_bounds__(256) pool2_kernel(const bf16 *__restrict__ x, int B, int H,
+                                                    int W, int C, bf16 *__restrict__ y) {
+  const size_t n = (size_t)B * (H / 2) * (W / 2) * C;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = i % C;
+  size_t r = i / C;
+  const int j = r % (W / 2);
+  r /= (W / 2);
+  const int ii = r % (H / 2);
+  const int b = r / (H / 2);
+  const size_t s = (((size_t)b * H + 2 * ii) * W + 2 * j) * C + c;
+  const float v = (float)x[s] + (float)x[s + C] + (float)x[s + (size_t)W * C] +
+                  (float)x[s + (size_t)W * C + C];
+  y[i] = (bf16)(0.25f * v);
+}
+
+__global__ void __launch_bounds__(256) pool2_grad_kernel(const bf16 *__restrict__ dy, int B,
+                                                         int H, int W, int C,
+                                                         bf16 *__restrict__ dx) {
+  const size_t n = (size_t)B * H * W * C;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = i % C;
+  size_t r = i / C;
+  const int j = r % W;
+  r /= W;
+  const int ii = r % H;
+  const int b = r / H;
+  dx[i] = (bf16)(0.25f * (float)dy[(((size_t)b * (H / 2) + ii / 2) * (W / 2) + j / 2) * C + c]);
+}
+
+__global__ void __launch_bounds__(256) up2_kernel(const bf16 *__restrict__ x, int B, int H, int W,
+                                                  int C, bf16 *__restrict__ y) {
+  const size_t n = (size_t)B * 2 * H * 2 * W * C;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = i % C;
+  size_t r = i / C;
+  const int j = r % (2 * W);
+  r /= (2 * W);
+  const int ii = r % (2 * H);
+  const int b = r / (2 * H);
+  y[i] = x[(((size_t)b * H + ii / 2) * W + j / 2) * C + c];
+}
+
+__global__ void __launch_bounds__(256) up2_grad_kernel(const bf16 *__restrict__ dy, int B, int H,
+                                                       int W, int C, bf16 *__restrict__ dx) {
+  const size_t n = (size_t)B * H * W * C;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = i % C;
+  size_t r = i / C;
+  const int j = r % W;
+  r /= W;
+  const int ii = r % H;
+  const int b = r / H;
+  const size_t s = (((size_t)b * 2 * H + 2 * ii) * 2 * W + 2 * j) * C + c;
+  const size_t row = (size_t)2 * W * C;
+  const float v = (float)dy[s] + (float)dy[s + C] + (float)dy[s + row] + (float)dy[s + row + C];
+  dx[i] = (bf16)v;
+}
+
+__global__ void __launch_bounds__(256) concat_kernel(const bf16 *__restrict__ a, int ca,
+                                                     const bf16 *__restrict__ b, int cb,
+                                                     size_t npix, bf16 *__restrict__ y) {
+  const int C = ca + cb;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix * C) return;
+  const size_t p = i / C;
+  const int c = i - p * C;
+  y[i] = c < ca ? a[p * ca + c] : b[p * cb + (c - ca)];
+}
+
+__global__ void __launch_bounds__(256) split_kernel(const bf16 *__restrict__ y, int ca, int cb,
+                                                    size_t npix, bf16 *__restrict__ a,
+                                                    bf16 *__restrict__ b) {
+  const int C = ca + cb;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix * C) return;
+  const size_t p = i / C;
+  const int c = i - p * C;
+  if (c < ca)
+    a[p * ca + c] = y[i];
+  else
+    b[p * cb + (c - ca)] = y[i];
+}
+
+__global__ void __launch_bounds__(256) act_grad_kernel(const bf16 *__restrict__ g0,
+                                                       const bf16 *__restrict__ g1,
+                                                       const bf16 *__restrict__ out, size_t n,
+                                                       float slope, bf16 *__restrict__ dz) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = (float)g0[i];
+  if (g1) s = (float)(bf16)(s + (float)g1[i]);
+  dz[i] = (bf16)((float)out[i] > 0.0f ? s : slope * s);
+}
+
+constexpr int kMseBlocks = 1024;
+
+__global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ out, int ldo,
+                                                  const float *__restrict__ tgt, int nch,
+                                                  size_t npix, bf16 *__restrict__ dout,
+                                                  double *__restrict__ part) {
+  __shared__ double lds[4];
+  const double scale = 2.0 / ((double)npix * nch);
+  double s = 0.0;
+  const size_t n = npix * ldo;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = i / ldo;
+    const int c = i - p * ldo;
+    float g = 0.0f;
+    if (c < nch) {
+      const float d = out[i] - tgt[p * nch + c];
+      s += (double)d * d;
+      g = (float)(scale * d);
+    }
+    dout[i] = (bf16)g;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+__global__ void __launch_bounds__(256) mse_finalize_kernel(const double *__restrict__ part,
+                                                           int nparts, double count,
+                                                           double *__restrict__ loss) {
+  __shared__ double lds[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *loss = (lds[0] + lds[1] + lds[2] + lds[3]) / count;
+}
+
+__global__ void __launch_bounds__(256) adamw_kernel(float *__restrict__ p,
+                                                    const float *__restrict__ g,
+                                                    float *__restrict__ m, float *__restrict__ v,
+                                                    size_t n, float lr, float b1, float b2,
+                                                    float eps, float wd, float c1, float c2) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / c1, vh = vi / c2;
+  p[i] = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+}
+
+__global__ void __launch_bounds__(256) features_kernel(const float *__restrict__ eps_all,
+                                                       const float *__restrict__ groups,
+                                                       int ngroups, const int32_t *__restrict__ idx,
+                                                       int B, int H, int W, bf16 *__restrict__ x) {
+  const size_t n = (size_t)B * H * W * 16;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = i & 15;
+  size_t r = i >> 4;
+  const int j = r % W;
+  r /= W;
+  const int ii = r % H;
+  const int b = r / H;
+  const int s = idx[b];
+  float v = 0.0f;
+  if (c == 0)
+    v = (eps_all[((size_t)s * H + ii) * W + j] - 0.625f) * 5.0f;
+  else if (c <= ngroups)
+    v = groups[(size_t)s * ngroups + (c - 1)];
+  else if (c == ngroups + 1)
+    v = W > 1 ? 2.0f * j / (W - 1) - 1.0f : 0.0f;
+  else if (c == ngroups + 2)
+    v = H > 1 ? 2.0f * ii / (H - 1) - 1.0f : 0.0f;
+  x[i] = (bf16)v;
+}
+
+__global__ void __launch_bounds__(256) gather_kernel(const float *__restrict__ src, int nch,
+                                                     const int32_t *__restrict__ idx, int B,
+                                                     size_t npix, float *__restrict__ out) {
+  const size_t per = npix * nch;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)B * per) return;
+  const size_t b = i / per, r = i - b * per;
+  out[i] = src[(size_t)idx[b] * per + r];
+}
+
+// ------------------------------------------------------------------ host side
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+clb_status launched() {
+  return hipGetLastError() == hipSuccess ? CLB_OK : CLB_ERR_HIP;
+}
+
+unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
+
+// Split of the pixel reduction of the weight gradient: enough chunks for
+// about 4096 workgroups, each chunk a multiple of 32 pixels and >= 256.
+void wgrad_plan(int64_t M, int64_t tiles, int *nsplit, int *chunk) {
+  int64_t ns = std::max<int64_t>(1, (4096 + tiles - 1) / tiles);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, M / 256));
+  int64_t ch = (M + ns - 1) / ns;
+  ch = (ch + 31) / 32 * 32;
+  *chunk = (int)ch;
+  *nsplit = (int)((M + ch - 1) / ch);
+}
+
+bool dims_ok(int32_t b, int32_t h, int32_t w) {
+  return b > 0 && h > 0 && w > 0 && (int64_t)b * h * w < (1LL << 31);
+}
+
+}  // namespace
+
+extern "C" clb_status clb_nn_conv3x3(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w,
+                                     int32_t cin, const clb_bf16 *weight, const float *bias,
+                                     int32_t cout, int32_t act, float slope, void *y,
+                                     int32_t y_fp32, void *stream) {
+  if (!x || !weight || !y || !dims_ok(batch, h, w) || cin <= 0 || cin % 16 || cout <= 0 ||
+      cout % 16 || (act != 0 && act != 1) || !aligned16(x) || !aligned16(weight))
+    return CLB_ERR_ARG;
+  const int64_t M = (int64_t)batch * h * w;
+  const dim3 grid((unsigned)((M + kPixTile - 1) / kPixTile), (unsigned)((cout + kCoTile - 1) / kCoTile));
+  hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<const bf16 *>(x), batch, h, w, cin,
+                     reinterpret_cast<const bf16 *>(weight), bias, cout, act, slope, y, y_fp32);
+  return launched();
+}
+
+extern "C" clb_status clb_nn_wgrad_workspace_bytes(int32_t batch, int32_t h, int32_t w,
+                                                   int32_t cin, int32_t cout, size_t *bytes) {
+  if (!bytes || !dims_ok(batch, h, w) || cin <= 0 || cin % 16 || cout <= 0 || cout % 16)
+    return CLB_ERR_ARG;
+  int nsplit, chunk;
+  const int64_t K = 9LL * cin;
+  wgrad_plan((int64_t)batch * h * w, (cout / 16) * (K / 16), &nsplit, &chunk);
+  *bytes = sizeof(float) * (size_t)nsplit * (cout * K + cout);
+  return CLB_OK;
+}
+
+extern "C" clb_status clb_nn_conv3x3_wgrad(const clb_bf16 *dy, const clb_bf16 *x, int32_t batch,
+                                           int32_t h, int32_t w, int32_t cin, int32_t cout,
+                                           float *dweight, float *dbias, void *workspace,
+                                           size_t bytes, void *stream) {
+  size_t need = 0;
+  if (clb_nn_wgrad_workspace_bytes(batch, h, w, cin, cout, &need) != CLB_OK || !dy || !x ||
+      !dweight || !workspace || bytes < need)
+    return CLB_ERR_ARG;
+  int nsplit, chunk;
+  const int64_t K = 9LL * cin, M = (int64_t)batch * h * w;
+  wgrad_plan(M, (cout / 16) * (K / 16), &nsplit, &chunk);
+  float *part = static_cast<float *>(workspace);
+  float *partb = part + (size_t)nsplit * cout * K;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(wgrad_kernel, dim3(cout / 16, (unsigned)(K / 16), nsplit), dim3(64), 0, s,
+                     reinterpret_cast<const bf16 *>(dy), reinterpret_cast<const bf16 *>(x), batch,
+                     h, w, cin, cout, chunk, part, partb);
+  const size_t n = (size_t)cout * K;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks_for(n)), dim3(256), 0, s, part, nsplit, n,
+                     dweight);
+  if (dbias)
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks_for(cout)), dim3(256), 0, s, partb, nsplit,
+                       (size_t)cout, dbias);
+  return launched();
+}
+
+extern "C" clb_status clb_nn_weights_bf16(const float *w32, int32_t cout, int32_t cin,
+                                          clb_bf16 *w_fwd, clb_bf16 *w_bwd, void *stream) {
+  if (!w32 || !w_fwd || !w_bwd || cout <= 0 || cin <= 0) return CLB_ERR_ARG;
+  const size_t n = (size_t)cout * 9 * cin;
+  hipLaunchKernelGGL(weights_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), w32, cout, cin,
+                     reinterpret_cast<bf16 *>(w_fwd), reinterpret_cast<bf16 *>(w_bwd));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_pool2(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w,
+                                   int32_t c, clb_bf16 *y, void *stream) {
+  if (!x || !y || !dims_ok(batch, h, w) || h % 2 || w % 2 || c <= 0) return CLB_ERR_ARG;
+  const size_t n = (size_t)batch * (h / 2) * (w / 2) * c;
+  hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(x), batch,
+                     h, w, c, reinterpret_cast<bf16 *>(y));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_pool2_grad(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w,
+                                        int32_t c, clb_bf16 *dx, void *stream) {
+  if (!dy || !dx || !dims_ok(batch, h, w) || h % 2 || w % 2 || c <= 0) return CLB_ERR_ARG;
+  const size_t n = (size_t)batch * h * w * c;
+  hipLaunchKernelGGL(pool2_grad_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(dy), batch,
+                     h, w, c, reinterpret_cast<bf16 *>(dx));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_up2(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w,
+                                 int32_t c, clb_bf16 *y, void *stream) {
+  if (!x || !y || !dims_ok(batch, 2 * h, 2 * w) || c <= 0) return CLB_ERR_ARG;
+  const size_t n = (size_t)batch * 4 * h * w * c;
+  hipLaunchKernelGGL(up2_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(x), batch,
+                     h, w, c, reinterpret_cast<bf16 *>(y));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_up2_grad(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w,
+                                      int32_t c, clb_bf16 *dx, void *stream) {
+  if (!dy || !dx || !dims_ok(batch, 2 * h, 2 * w) || c <= 0) return CLB_ERR_ARG;
+  const size_t n = (size_t)batch * h * w * c;
+  hipLaunchKernelGGL(up2_grad_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(dy), batch,
+                     h, w, c, reinterpret_cast<bf16 *>(dx));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_concat(const clb_bf16 *a, int32_t ca, const clb_bf16 *b, int32_t cb,
+                                    int64_t npix, clb_bf16 *y, void *stream) {
+  if (!a || !b || !y || ca <= 0 || cb <= 0 || npix <= 0) return CLB_ERR_ARG;
+  const size_t n = (size_t)npix * (ca + cb);
+  hipLaunchKernelGGL(concat_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(a), ca,
+                     reinterpret_cast<const bf16 *>(b), cb, (size_t)npix,
+                     reinterpret_cast<bf16 *>(y));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_split(const clb_bf16 *y, int32_t ca, int32_t cb, int64_t npix,
+                                   clb_bf16 *a, clb_bf16 *b, void *stream) {
+  if (!a || !b || !y || ca <= 0 || cb <= 0 || npix <= 0) return CLB_ERR_ARG;
+  const size_t n = (size_t)npix * (ca + cb);
+  hipLaunchKernelGGL(split_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(y), ca, cb,
+                     (size_t)npix, reinterpret_cast<bf16 *>(a), reinterpret_cast<bf16 *>(b));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_act_grad(const clb_bf16 *g0, const clb_bf16 *g1,
+                                      const clb_bf16 *out, int64_t n, float slope, clb_bf16 *dz,
+                                      void *stream) {
+  if (!g0 || !out || !dz || n <= 0) return CLB_ERR_ARG;
+  hipLaunchKernelGGL(act_grad_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(g0),
+                     reinterpret_cast<const bf16 *>(g1), reinterpret_cast<const bf16 *>(out),
+                     (size_t)n, slope, reinterpret_cast<bf16 *>(dz));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_mse_workspace_bytes(int64_t npix, size_t *bytes) {
+  if (!bytes || npix <= 0) return CLB_ERR_ARG;
+  *bytes = sizeof(double) * kMseBlocks;
+  return CLB_OK;
+}
+
+extern "C" clb_status clb_nn_mse(const float *out, int32_t ldo, const float *target, int32_t nch,
+                                 int64_t npix, clb_bf16 *dout, double *d_loss, void *workspace,
+                                 size_t bytes, void *stream) {
+  if (!out || !target || !dout || !d_loss || !workspace || nch <= 0 || ldo < nch || npix <= 0 ||
+      bytes < sizeof(double) * kMseBlocks)
+    return CLB_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned nb = (unsigned)std::min<size_t>(kMseBlocks, blocks_for((size_t)npix * ldo));
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, s, out, ldo, target, nch, (size_t)npix,
+                     reinterpret_cast<bf16 *>(dout), static_cast<double *>(workspace));
+  hipLaunchKernelGGL(mse_finalize_kernel, dim3(1), dim3(256), 0, s,
+                     static_cast<const double *>(workspace), (int)nb, (double)npix * nch, d_loss);
+  return launched();
+}
+
+extern "C" clb_status clb_nn_adamw(float *p, const float *g, float *m, float *v, int64_t n,
+                                   float lr, float b1, float b2, float eps, float wd, int32_t t,
+                                   void *stream) {
+  if (!p || !g || !m || !v || n <= 0 || t < 1) return CLB_ERR_ARG;
+  const float c1 = (float)(1.0 - std::pow((double)b1, t));
+  const float c2 = (float)(1.0 - std::pow((double)b2, t));
+  hipLaunchKernelGGL(adamw_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), p, g, m, v, (size_t)n, lr, b1, b2, eps, wd,
+                     c1, c2);
+  return launched();
+}
+
+extern "C" clb_status clb_nn_features(const float *eps_all, const float *groups_all,
+                                      int32_t ngroups, const int32_t *idx, int32_t batch,
+                                      int32_t h, int32_t w, clb_bf16 *x, void *stream) {
+  if (!eps_all || !idx || !x || ngroups < 0 || ngroups > 13 || (ngroups && !groups_all) ||
+      !dims_ok(batch, h, w))
+    return CLB_ERR_ARG;
+  const size_t n = (size_t)batch * h * w * 16;
+  hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), eps_all, groups_all, ngroups, idx, batch,
+                     h, w, reinterpret_cast<bf16 *>(x));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_gather(const float *fields_all, int32_t nch, const int32_t *idx,
+                                    int32_t batch, int64_t npix, float *out, void *stream) {
+  if (!fields_all || !idx || !out || nch <= 0 || batch <= 0 || npix <= 0) return CLB_ERR_ARG;
+  const size_t n = (size_t)batch * npix * nch;
+  hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), fields_all, nch, idx, batch, (size_t)npix,
+                     out);
+  return launched();
+}

@@ -40,12 +40,13 @@ def random_fields(nx, ny, seed, u_amp=0.02, T_amp=0.3, T0=0.5, smooth=4):
     return out[0], out[1], T0 + out[2]
 
 
-def gaussian_random_field(nx, ny, ell, seed):
+def gaussian_random_field(nx, ny, ell, seed, gen=None):
     """Standardised Gaussian random field with covariance exp(-r^2 / ell^2).
 
-    Periodic FFT filtering of white noise by the square root of the spectrum
-    of that covariance, then shifted and scaled to zero mean, unit variance."""
-    w = rng(seed).standard_normal((ny, nx))
+    Periodic FFT filtering of white noise (from `gen`, else a generator
+    seeded with `seed`) by the square root of the spectrum of that
+    covariance, then shifted and scaled to zero mean, unit variance."""
+    w = (gen if gen is not None else rng(seed)).standard_normal((ny, nx))
     kx = np.fft.fftfreq(nx) * 2 * math.pi
     ky = np.fft.fftfreq(ny) * 2 * math.pi
     k2 = ky[:, None] ** 2 + kx[None, :] ** 2
@@ -94,4 +95,25 @@ def batch_cavities(count=256, seed=3, sizes=(64, 128, 256, 512)):
         Pr = (0.71, 1.0, 7.0)[g.integers(3)]
         sigma = g.uniform(0.8, 1.2)
         out.append(dict(n=n, Ra=Ra, Da=Da, phi=phi, Pr=Pr, sigma=sigma))
+    return out
+
+
+def warmstart_draws(count, seed, n=128, ell=8.0, Ra=(1e3, 1e6), Da=(1e-5, 1e-1),
+                    eps=(0.3, 0.95)):
+    """Cavities of the learned warm start: for sample i, a generator seeded
+    with (seed, i) draws, in this order, Ra log-uniform in Ra, Da log-uniform
+    in Da (the mean Darcy number of the map), Pr uniform over {0.71, 1, 7},
+    sigma uniform [0.8, 1.2], then a porosity map (Gaussian random field of
+    correlation length `ell`, uniform marginal on eps).  Returns dicts with
+    n, Ra, Da, Pr, sigma, eps (n x n)."""
+    out = []
+    for i in range(count):
+        g = np.random.Generator(np.random.PCG64([seed, i]))
+        d = dict(n=n, Ra=10.0 ** g.uniform(np.log10(Ra[0]), np.log10(Ra[1])),
+                 Da=10.0 ** g.uniform(np.log10(Da[0]), np.log10(Da[1])),
+                 Pr=(0.71, 1.0, 7.0)[g.integers(3)], sigma=g.uniform(0.8, 1.2))
+        zf = gaussian_random_field(n, n, ell, None, gen=g)
+        e = eps[0] + (eps[1] - eps[0]) * normal_cdf(zf)
+        d["eps"] = e.astype(np.float32).astype(np.float64)
+        out.append(d)
     return out

@@ -1,0 +1,307 @@
+"""Warm-start network: ctypes binding of the HIP kernels of include/clb_nn.h
+and the encoder-decoder (U-Net) assembled from them.
+
+Argument marshalling and buffer bookkeeping only: every layer, gradient,
+loss and optimizer step runs in the HIP library.  PyTorch provides device
+memory (tensors used as raw buffers) and the stream.
+
+The network maps a 16-channel input (porosity map, normalised dimensionless
+groups, coordinates; clb_nn_features) on an h x w grid to 16 output channels
+of which the first three are the predicted steady u / u_c, v / u_c and T - 1/2
+of a cavity.  Architecture: five levels of widths 16, 32, 64, 128, 256; two
+3x3 convolutions with leaky ReLU (slope 1/8) per level; 2x2 average pooling
+down, nearest 2x upsampling and concatenation with the encoder output of the
+level on the way up; a final 3x3 convolution without activation (FP32
+output).  Mixed precision: bfloat16 activations and gradients, FP32 master
+weights, gradients and AdamW moments.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _binding as B
+
+SLOPE = 0.125
+NN_EXPORTS = (
+    "clb_nn_conv3x3", "clb_nn_wgrad_workspace_bytes", "clb_nn_conv3x3_wgrad",
+    "clb_nn_weights_bf16", "clb_nn_pool2", "clb_nn_pool2_grad", "clb_nn_up2", "clb_nn_up2_grad",
+    "clb_nn_concat", "clb_nn_split", "clb_nn_act_grad", "clb_nn_mse_workspace_bytes",
+    "clb_nn_mse", "clb_nn_adamw", "clb_nn_features", "clb_nn_gather",
+)
+
+_ready = False
+
+
+def lib():
+    global _ready
+    L = B._lib()
+    if not _ready:
+        vp, i32, i64, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+        st, sz = C.c_int, C.POINTER(C.c_size_t)
+        sig = {
+            "clb_nn_conv3x3": [vp, i32, i32, i32, i32, vp, vp, i32, i32, f32, vp, i32, vp],
+            "clb_nn_wgrad_workspace_bytes": [i32, i32, i32, i32, i32, sz],
+            "clb_nn_conv3x3_wgrad": [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, C.c_size_t, vp],
+            "clb_nn_weights_bf16": [vp, i32, i32, vp, vp, vp],
+            "clb_nn_pool2": [vp, i32, i32, i32, i32, vp, vp],
+            "clb_nn_pool2_grad": [vp, i32, i32, i32, i32, vp, vp],
+            "clb_nn_up2": [vp, i32, i32, i32, i32, vp, vp],
+            "clb_nn_up2_grad": [vp, i32, i32, i32, i32, vp, vp],
+            "clb_nn_concat": [vp, i32, vp, i32, i64, vp, vp],
+            "clb_nn_split": [vp, i32, i32, i64, vp, vp, vp],
+            "clb_nn_act_grad": [vp, vp, vp, i64, f32, vp, vp],
+            "clb_nn_mse_workspace_bytes": [i64, sz],
+            "clb_nn_mse": [vp, i32, vp, i32, i64, vp, vp, vp, C.c_size_t, vp],
+            "clb_nn_adamw": [vp, vp, vp, vp, i64, f32, f32, f32, f32, f32, i32, vp],
+            "clb_nn_features": [vp, vp, i32, vp, i32, i32, i32, vp, vp],
+            "clb_nn_gather": [vp, i32, vp, i32, i64, vp, vp],
+            "clb_set_state_device": [vp, i32, vp, i64, f64, f64],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.restype = st
+            fn.argtypes = args
+        _ready = True
+    return L
+
+
+def call(name, *args):
+    B._check(getattr(lib(), name)(*args), name)
+
+
+def ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def graph(levels=5, base=16, cout=16):
+    """Steps of the encoder-decoder; step i writes tensor i + 1 (tensor 0 is
+    the input): dicts with op in {conv, pool, up, cat}, input tensor ids, and
+    for convolutions the index k, the activation flag and the output width."""
+    steps, skips = [], []
+    cur, k = 0, 0
+    for lv in range(levels):
+        if lv:
+            steps.append(dict(op="pool", ins=[cur]))
+            cur = len(steps)
+        for _ in range(2):
+            steps.append(dict(op="conv", ins=[cur], k=k, act=True, out=base << lv))
+            cur, k = len(steps), k + 1
+        skips.append(cur)
+    for lv in range(levels - 2, -1, -1):
+        steps.append(dict(op="up", ins=[cur]))
+        steps.append(dict(op="cat", ins=[len(steps), skips[lv]]))
+        cur = len(steps)
+        for _ in range(2):
+            steps.append(dict(op="conv", ins=[cur], k=k, act=True, out=base << lv))
+            cur, k = len(steps), k + 1
+    steps.append(dict(op="conv", ins=[cur], k=k, act=False, out=cout))
+    return steps
+
+
+class UNet:
+    """The encoder-decoder on one device.  Parameters live in one flat FP32
+    tensor (per convolution: weights (out, 9, in), then bias (out,)), with
+    gradients and AdamW moments of the same layout."""
+
+    def __init__(self, levels=5, base=16, cin=16, cout=16, device="cuda:0", seed=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the warm-start network needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.levels, self.base, self.cin, self.cout = levels, base, cin, cout
+        self.steps = graph(levels, base, cout)
+        # channel count and downsampling level of every tensor
+        self.ch, self.lv = [cin], [0]
+        self.convs = []
+        for st in self.steps:
+            a = st["ins"][0]
+            if st["op"] == "pool":
+                self.ch.append(self.ch[a])
+                self.lv.append(self.lv[a] + 1)
+            elif st["op"] == "up":
+                self.ch.append(self.ch[a])
+                self.lv.append(self.lv[a] - 1)
+            elif st["op"] == "cat":
+                self.ch.append(self.ch[a] + self.ch[st["ins"][1]])
+                self.lv.append(self.lv[a])
+            else:
+                self.convs.append((st["out"], self.ch[a]))
+                self.ch.append(st["out"])
+                self.lv.append(self.lv[a])
+        self.offsets = []
+        n = 0
+        for o, c in self.convs:
+            self.offsets.append((n, n + o * 9 * c))
+            n += o * 9 * c + o
+        self.nparams = n
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.p = torch.zeros(n, **f32)
+        self.g = torch.zeros(n, **f32)
+        self.m = torch.zeros(n, **f32)
+        self.v = torch.zeros(n, **f32)
+        self.wf = [torch.empty(o * 9 * c, dtype=torch.bfloat16, device=self.device)
+                   for o, c in self.convs]
+        self.wb = [torch.empty_like(w) for w in self.wf]
+        self.t = 0
+        self.set_params(self.init_params(seed))
+        self._shape = None
+
+    # ------------------------------------------------------------ parameters
+    def init_params(self, seed):
+        """He-normal weights for the leaky ReLU, zero biases (host, seeded)."""
+        r = np.random.Generator(np.random.PCG64(seed))
+        flat = np.zeros(self.nparams, dtype=np.float32)
+        for (o, c), (w0, b0) in zip(self.convs, self.offsets):
+            std = np.sqrt(2.0 / (1.0 + SLOPE ** 2) / (9 * c))
+            flat[w0:b0] = r.standard_normal(o * 9 * c) * std
+        return flat
+
+    def set_params(self, flat):
+        self.p.copy_(self.torch.from_numpy(np.ascontiguousarray(flat, dtype=np.float32)))
+        self._refresh_bf16()
+
+    def get_params(self):
+        return self.p.cpu().numpy()
+
+    def param_list(self):
+        """[(w (out, 9, in), b (out,))] as FP32 numpy arrays."""
+        flat = self.get_params()
+        out = []
+        for (o, c), (w0, b0) in zip(self.convs, self.offsets):
+            out.append((flat[w0:b0].reshape(o, 9, c).copy(), flat[b0:b0 + o].copy()))
+        return out
+
+    def grad_list(self):
+        flat = self.g.cpu().numpy()
+        return [(flat[w0:b0].reshape(o, 9, c).copy(), flat[b0:b0 + o].copy())
+                for (o, c), (w0, b0) in zip(self.convs, self.offsets)]
+
+    def _refresh_bf16(self):
+        s = C.c_void_p(self.stream.cuda_stream)
+        for k, ((o, c), (w0, _)) in enumerate(zip(self.convs, self.offsets)):
+            call("clb_nn_weights_bf16", C.c_void_p(self.p.data_ptr() + 4 * w0), o, c,
+                 ptr(self.wf[k]), ptr(self.wb[k]), s)
+
+    # --------------------------------------------------------------- buffers
+    def _buffers(self, batch, h, w):
+        if self._shape == (batch, h, w):
+            return
+        torch = self.torch
+        if h % (1 << (self.levels - 1)) or w % (1 << (self.levels - 1)):
+            raise ValueError("image sides must be multiples of %d" % (1 << (self.levels - 1)))
+        bf = dict(dtype=torch.bfloat16, device=self.device)
+        self.vals, self.grads_t, self.gtmp = [], [], []
+        for t, (c, lv) in enumerate(zip(self.ch, self.lv)):
+            n = batch * (h >> lv) * (w >> lv) * c
+            last = t == len(self.ch) - 1
+            self.vals.append(torch.empty(n, dtype=torch.float32, device=self.device)
+                             if last else torch.empty(n, **bf))
+        # gradient storage: per tensor up to two contributions, plus the
+        # gradient through the activation
+        self.gin = [[None, None] for _ in self.ch]
+        self.dz = [None] * len(self.ch)
+        for t, (c, lv) in enumerate(zip(self.ch, self.lv)):
+            n = batch * (h >> lv) * (w >> lv) * c
+            self.gin[t] = [torch.empty(n, **bf), torch.empty(n, **bf)]
+            self.dz[t] = torch.empty(n, **bf)
+        ws = 0
+        for st in self.steps:
+            if st["op"] == "conv":
+                a = st["ins"][0]
+                nb = C.c_size_t()
+                call("clb_nn_wgrad_workspace_bytes", batch, h >> self.lv[a], w >> self.lv[a],
+                     self.ch[a], st["out"], C.byref(nb))
+                ws = max(ws, nb.value)
+        nb = C.c_size_t()
+        call("clb_nn_mse_workspace_bytes", batch * h * w, C.byref(nb))
+        ws = max(ws, nb.value)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self.loss_d = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._shape = (batch, h, w)
+
+    # --------------------------------------------------------------- forward
+    def forward(self, x, batch, h, w):
+        """x: bfloat16 tensor (batch, h, w, cin).  Returns the FP32 output
+        tensor (batch, h, w, cout), owned by the network (overwritten by the
+        next call)."""
+        self._buffers(batch, h, w)
+        s = C.c_void_p(self.stream.cuda_stream)
+        vals = self.vals
+        vals[0] = x
+        for i, st in enumerate(self.steps):
+            t, a = i + 1, st["ins"][0]
+            ha, wa = h >> self.lv[a], w >> self.lv[a]
+            if st["op"] == "conv":
+                k = st["k"]
+                w0, b0 = self.offsets[k]
+                call("clb_nn_conv3x3", ptr(vals[a]), batch, ha, wa, self.ch[a], ptr(self.wf[k]),
+                     C.c_void_p(self.p.data_ptr() + 4 * b0), st["out"], 1 if st["act"] else 0,
+                     SLOPE, ptr(vals[t]), 0 if st["act"] else 1, s)
+            elif st["op"] == "pool":
+                call("clb_nn_pool2", ptr(vals[a]), batch, ha, wa, self.ch[a], ptr(vals[t]), s)
+            elif st["op"] == "up":
+                call("clb_nn_up2", ptr(vals[a]), batch, ha, wa, self.ch[a], ptr(vals[t]), s)
+            else:
+                b_ = st["ins"][1]
+                call("clb_nn_concat", ptr(vals[a]), self.ch[a], ptr(vals[b_]), self.ch[b_],
+                     batch * ha * wa, ptr(vals[t]), s)
+        return vals[-1]
+
+    # -------------------------------------------------------------- backward
+    def backward(self, target, nch, batch, h, w):
+        """Mean-squared error of the first nch output channels against target
+        (FP32 tensor (batch, h, w, nch)) after forward(); fills the gradient
+        tensor self.g and returns the loss as a device FP64 tensor."""
+        s = C.c_void_p(self.stream.cuda_stream)
+        vals, T = self.vals, len(self.ch) - 1
+        ncontrib = [0] * len(self.ch)
+        call("clb_nn_mse", ptr(vals[T]), self.ch[T], ptr(target), nch, batch * h * w,
+             ptr(self.gin[T][0]), ptr(self.loss_d), ptr(self.ws), self.ws.numel(), s)
+        ncontrib[T] = 1
+
+        def contrib(t):
+            buf = self.gin[t][ncontrib[t]]
+            ncontrib[t] += 1
+            return buf
+
+        for i in range(len(self.steps) - 1, -1, -1):
+            st = self.steps[i]
+            t, a = i + 1, st["ins"][0]
+            if ncontrib[t] == 0:
+                continue
+            g0 = self.gin[t][0]
+            g1 = self.gin[t][1] if ncontrib[t] == 2 else None
+            ht, wt = h >> self.lv[t], w >> self.lv[t]
+            ha, wa = h >> self.lv[a], w >> self.lv[a]
+            if st["op"] == "conv":
+                k = st["k"]
+                if st["act"]:
+                    call("clb_nn_act_grad", ptr(g0), ptr(g1), ptr(vals[t]),
+                         batch * ht * wt * self.ch[t], SLOPE, ptr(self.dz[t]), s)
+                    dz = self.dz[t]
+                else:
+                    dz = g0
+                w0, b0 = self.offsets[k]
+                call("clb_nn_conv3x3_wgrad", ptr(dz), ptr(vals[a]), batch, ha, wa, self.ch[a],
+                     st["out"], C.c_void_p(self.g.data_ptr() + 4 * w0),
+                     C.c_void_p(self.g.data_ptr() + 4 * b0), ptr(self.ws), self.ws.numel(), s)
+                if a > 0:
+                    call("clb_nn_conv3x3", ptr(dz), batch, ha, wa, st["out"], ptr(self.wb[k]),
+                         None, self.ch[a], 0, 0.0, ptr(contrib(a)), 0, s)
+            elif st["op"] == "pool":
+                call("clb_nn_pool2_grad", ptr(g0), batch, ha, wa, self.ch[a], ptr(contrib(a)), s)
+            elif st["op"] == "up":
+                call("clb_nn_up2_grad", ptr(g0), batch, ha, wa, self.ch[a], ptr(contrib(a)), s)
+            else:
+                b_ = st["ins"][1]
+                call("clb_nn_split", ptr(g0), self.ch[a], self.ch[b_], batch * ha * wa,
+                     ptr(contrib(a)), ptr(contrib(b_)), s)
+        return self.loss_d
+
+    def adamw(self, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+        self.t += 1
+        call("clb_nn_adamw", ptr(self.p), ptr(self.g), ptr(self.m), ptr(self.v), self.nparams,
+             lr, b1, b2, eps, wd, self.t, C.c_void_p(self.stream.cuda_stream))
+        self._refresh_bf16()

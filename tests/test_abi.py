@@ -14,19 +14,22 @@ from paper_2110_05943_amd import _binding as B
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    text = open(os.path.join(ROOT, "include", "clb.h")).read()
+def declared_functions(header="clb.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(clb_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(clb_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
+    from paper_2110_05943_amd import nn
     lib = C.CDLL(B.LIB_PATH)
-    names = declared_functions()
-    assert len(names) >= 20
-    for n in names:
+    names = declared_functions("clb.h")
+    nn_names = declared_functions("clb_nn.h")
+    assert len(names) >= 20 and len(nn_names) >= 16
+    for n in names + nn_names:
         assert hasattr(lib, n), n
     assert set(names) == set(B.EXPORTS)
+    assert set(nn_names) == set(nn.NN_EXPORTS)
 
 
 def test_struct_sizes_match_header_layout():
@@ -104,3 +107,26 @@ def test_calls_without_context_are_rejected():
     assert lib.clb_step(None, 1) == B.ERR_ARG
     assert lib.clb_set_active(None, None) == B.ERR_ARG
     assert lib.clb_strerror(B.NOT_CONVERGED).decode() == "not steady within the step limit"
+
+
+def test_network_calls_validate_arguments_on_the_host():
+    """Invalid sizes, pointers or alignment are rejected before any launch."""
+    from paper_2110_05943_amd import nn
+    lib = nn.lib()
+    vp = C.c_void_p
+    a16 = vp(4096)  # aligned, never dereferenced: the call fails validation first
+    bad = vp(4098)
+    # channel counts must be multiples of 16; pointers 16-byte aligned
+    assert lib.clb_nn_conv3x3(a16, 1, 4, 4, 8, a16, None, 16, 0, 0.0, a16, 1, None) == B.ERR_ARG
+    assert lib.clb_nn_conv3x3(a16, 1, 4, 4, 16, a16, None, 24, 0, 0.0, a16, 1, None) == B.ERR_ARG
+    assert lib.clb_nn_conv3x3(bad, 1, 4, 4, 16, a16, None, 16, 0, 0.0, a16, 1, None) == B.ERR_ARG
+    assert lib.clb_nn_conv3x3(a16, 0, 4, 4, 16, a16, None, 16, 0, 0.0, a16, 1, None) == B.ERR_ARG
+    assert lib.clb_nn_pool2(a16, 1, 5, 4, 16, a16, None) == B.ERR_ARG  # odd height
+    assert lib.clb_nn_adamw(a16, a16, a16, a16, 10, 1e-3, 0.9, 0.999, 1e-8, 0.0, 0, None) \
+        == B.ERR_ARG  # step t must be >= 1
+    n = C.c_size_t()
+    assert lib.clb_nn_wgrad_workspace_bytes(2, 16, 16, 16, 32, C.byref(n)) == B.OK
+    assert n.value > 32 * 144 * 4
+    assert lib.clb_nn_conv3x3_wgrad(a16, a16, 2, 16, 16, 16, 32, a16, None, a16, n.value - 4,
+                                    None) == B.ERR_ARG  # workspace too small
+    assert lib.clb_set_state_device(None, 0, a16, 16, 1.0, 0.0) == B.ERR_ARG

@@ -158,3 +158,30 @@ def test_table1_steady_nusselt_128(B):
         tail = nu[3 * i:3 * i + 3, -50:]
         assert np.all(np.abs(tail - final[3 * i:3 * i + 3, None]) <= 1e-4)
     s.close()
+
+
+def test_set_state_device_matches_host_warm_start(B):
+    """clb_set_state_device (fields in device memory with a row stride, as a
+    network writes them) gives the same populations as clb_set_state."""
+    import torch
+    from paper_2110_05943_amd import nn
+    case = cavity(40, ny=24, Ra=1e4, sigma=1.1, T_init=0.25)
+    u, v, T = inputs.random_fields(40, 24, seed=5, u_amp=0.02, T_amp=0.3)
+    # values representable in FP32, so both paths see the same numbers
+    u, v, T = (a.astype(np.float32).astype(np.float64) for a in (u, v, T))
+    uc, T_off = 0.0625, 0.0  # scalings that keep every value exact in FP32
+    a = B.Solver([cavity(8, Ra=1e3), case])
+    a.set_state(1, T, u, v)
+    fields = np.zeros((24 * 40, 16), dtype=np.float32)
+    fields[:, 0] = (u / uc).ravel()
+    fields[:, 1] = (v / uc).ravel()
+    fields[:, 2] = (T - T_off).ravel()
+    d = torch.tensor(fields).cuda()
+    torch.cuda.synchronize()  # the copy ran on torch's stream, the solver has its own
+    b = B.Solver([cavity(8, Ra=1e3), case])
+    nn.call("clb_set_state_device", b._ctx, 1, nn.ptr(d), 16, uc, T_off)
+    b.synchronize()
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.step(50)
+    b.step(50)
+    assert np.array_equal(a.get_state(), b.get_state())

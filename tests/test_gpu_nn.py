@@ -1,0 +1,267 @@
+"""GPU parity of the warm-start network kernels (include/clb_nn.h) against the
+FP64 oracle (oracle/nn_oracle.py) on seeded inputs.
+
+bfloat16 inputs are exact in both; FP32 results (convolution outputs, weight
+gradients) agree to FP32 summation order, bound 1e-5 relative to the sum of
+|terms|; bfloat16 results are compared with the oracle's value rounded the
+same way (at most one bfloat16 step apart, rarely)."""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import nn_oracle as N
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nn():
+    import torch
+    assert torch.cuda.is_available(), "needs the MI355X"
+    from paper_2110_05943_amd import nn as m
+    m.lib()
+    return m
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def dev_bf16(a):
+    import torch
+    t = torch.tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16)
+    assert np.array_equal(t.float().numpy(), np.asarray(a, dtype=np.float32))  # exact
+    return t.cuda()
+
+
+def dev_f32(a):
+    import torch
+    return torch.tensor(np.asarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def empty(n, dtype="bf16"):
+    import torch
+    return torch.zeros(n, dtype=torch.bfloat16 if dtype == "bf16" else torch.float32,
+                       device="cuda")
+
+
+def bf16_steps(a, b):
+    """Distance in bfloat16 steps between two bfloat16-representable arrays."""
+    ua = np.asarray(a, dtype=np.float32).view(np.int32) >> 16
+    ub = np.asarray(b, dtype=np.float32).view(np.int32) >> 16
+    return np.abs(ua.astype(np.int64) - ub.astype(np.int64))
+
+
+def check_bf16(got, ref, what, frac=1e-3):
+    d = bf16_steps(got, N.round_bf16(ref))
+    log("%s: %d of %d values one bfloat16 step off, max %d" % (what, int((d > 0).sum()), d.size,
+                                                               int(d.max())))
+    assert d.max() <= 1 and (d > 0).mean() <= frac
+
+
+CONV_SHAPES = [(2, 9, 13, 16, 16), (1, 5, 7, 48, 80), (2, 8, 8, 384, 128), (3, 16, 16, 16, 32)]
+
+
+@pytest.mark.parametrize("shape", CONV_SHAPES)
+def test_conv3x3_forward_fp32_and_bf16(nn, shape):
+    Bn, H, W, ci, co = shape
+    r = rng(sum(shape))
+    x = N.round_bf16(r.standard_normal((Bn, H, W, ci)))
+    w = N.round_bf16(r.standard_normal((co, 9, ci)) / np.sqrt(9 * ci))
+    b = r.standard_normal(co).astype(np.float32).astype(np.float64)
+    ref = N.conv3x3(x, w, b)
+    bound = N.conv3x3(np.abs(x), np.abs(w), np.abs(b)) * 1e-5 + 1e-30
+    dx, dw, db = dev_bf16(x), dev_bf16(w), dev_f32(b)
+    y32 = empty(ref.size, "f32")
+    nn.call("clb_nn_conv3x3", nn.ptr(dx), Bn, H, W, ci, nn.ptr(dw), nn.ptr(db), co, 0, 0.0,
+            nn.ptr(y32), 1, None)
+    got = host(y32).reshape(ref.shape)
+    err = np.abs(got - ref)
+    log("conv %s fp32 max err / bound %.3f" % (shape, (err / bound).max()))
+    assert np.all(err <= bound)
+    y16 = empty(ref.size)
+    nn.call("clb_nn_conv3x3", nn.ptr(dx), Bn, H, W, ci, nn.ptr(dw), nn.ptr(db), co, 1,
+            nn.SLOPE, nn.ptr(y16), 0, None)
+    check_bf16(host(y16).reshape(ref.shape), N.leaky(ref, nn.SLOPE), "conv %s bf16" % (shape,))
+
+
+@pytest.mark.parametrize("shape", CONV_SHAPES)
+def test_conv3x3_input_and_weight_gradients(nn, shape):
+    Bn, H, W, ci, co = shape
+    r = rng(7 + sum(shape))
+    x = N.round_bf16(r.standard_normal((Bn, H, W, ci)))
+    w32 = (r.standard_normal((co, 9, ci)) / np.sqrt(9 * ci)).astype(np.float32)
+    dy = N.round_bf16(r.standard_normal((Bn, H, W, co)))
+    wf, wb = empty(w32.size), empty(w32.size)
+    tw = dev_f32(w32)
+    nn.call("clb_nn_weights_bf16", nn.ptr(tw), co, ci, nn.ptr(wf), nn.ptr(wb), None)
+    w = N.round_bf16(w32)
+    assert np.array_equal(host(wf).reshape(co, 9, ci), w)
+    assert np.array_equal(host(wb).reshape(ci, 9, co), w[:, ::-1, :].transpose(2, 1, 0))
+    # input gradient: the forward kernel with the reversed-tap weights
+    ddy = dev_bf16(dy)
+    gx = empty(x.size, "f32")
+    nn.call("clb_nn_conv3x3", nn.ptr(ddy), Bn, H, W, co, nn.ptr(wb), None, ci, 0, 0.0,
+            nn.ptr(gx), 1, None)
+    ref = N.conv3x3_grad_input(dy, w)
+    bound = N.conv3x3_grad_input(np.abs(dy), np.abs(w)) * 1e-5 + 1e-30
+    assert np.all(np.abs(host(gx).reshape(ref.shape) - ref) <= bound)
+    # weight and bias gradients
+    nb = C.c_size_t()
+    nn.call("clb_nn_wgrad_workspace_bytes", Bn, H, W, ci, co, C.byref(nb))
+    import torch
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    gw, gb = empty(w.size, "f32"), empty(co, "f32")
+    tx = dev_bf16(x)
+    nn.call("clb_nn_conv3x3_wgrad", nn.ptr(ddy), nn.ptr(tx), Bn, H, W, ci, co,
+            nn.ptr(gw), nn.ptr(gb), nn.ptr(ws), nb.value, None)
+    rw, rb = N.conv3x3_grad_weight(dy, x)
+    bw = N.conv3x3_grad_weight(np.abs(dy), np.abs(x))[0] * 1e-5 + 1e-30
+    ew = np.abs(host(gw).reshape(rw.shape) - rw)
+    log("wgrad %s max err / bound %.3f" % (shape, (ew / bw).max()))
+    assert np.all(ew <= bw)
+    assert np.allclose(host(gb), rb, rtol=1e-5, atol=1e-5 * np.abs(dy).sum(axis=(0, 1, 2)).max())
+    # deterministic: a second call gives identical bits
+    gw2 = empty(w.size, "f32")
+    nn.call("clb_nn_conv3x3_wgrad", nn.ptr(ddy), nn.ptr(tx), Bn, H, W, ci, co,
+            nn.ptr(gw2), None, nn.ptr(ws), nb.value, None)
+    assert torch.equal(gw, gw2)
+
+
+def test_elementwise_layers(nn):
+    r = rng(11)
+    Bn, H, W, Cc = 2, 6, 10, 16
+    x = N.round_bf16(r.standard_normal((Bn, H, W, Cc)))
+    dx = dev_bf16(x)
+    y = empty(x.size // 4)
+    nn.call("clb_nn_pool2", nn.ptr(dx), Bn, H, W, Cc, nn.ptr(y), None)
+    check_bf16(host(y).reshape(Bn, H // 2, W // 2, Cc), N.pool2(x), "pool2", frac=1e-2)
+    dy = N.round_bf16(r.standard_normal((Bn, H // 2, W // 2, Cc)))
+    g = empty(x.size)
+    tdy = dev_bf16(dy)
+    nn.call("clb_nn_pool2_grad", nn.ptr(tdy), Bn, H, W, Cc, nn.ptr(g), None)
+    assert np.array_equal(host(g).reshape(x.shape), N.pool2_grad(dy))
+    u = empty(x.size * 4)
+    nn.call("clb_nn_up2", nn.ptr(dx), Bn, H, W, Cc, nn.ptr(u), None)
+    assert np.array_equal(host(u).reshape(Bn, 2 * H, 2 * W, Cc), N.up2(x))
+    du = N.round_bf16(r.standard_normal((Bn, 2 * H, 2 * W, Cc)))
+    tdu = dev_bf16(du)
+    nn.call("clb_nn_up2_grad", nn.ptr(tdu), Bn, H, W, Cc, nn.ptr(g), None)
+    check_bf16(host(g).reshape(x.shape), N.up2_grad(du), "up2_grad", frac=1e-2)
+    b2 = N.round_bf16(r.standard_normal((Bn, H, W, 32)))
+    cat = empty(x.size * 3)
+    tb2 = dev_bf16(b2)
+    nn.call("clb_nn_concat", nn.ptr(dx), 16, nn.ptr(tb2), 32, Bn * H * W, nn.ptr(cat), None)
+    ref = np.concatenate([x, b2], axis=3)
+    assert np.array_equal(host(cat).reshape(ref.shape), ref)
+    sa, sb = empty(x.size), empty(b2.size)
+    nn.call("clb_nn_split", nn.ptr(cat), 16, 32, Bn * H * W, nn.ptr(sa), nn.ptr(sb), None)
+    assert np.array_equal(host(sa), x.ravel()) and np.array_equal(host(sb), b2.ravel())
+    # activation gradient with one and with two contributions
+    out = N.round_bf16(N.leaky(r.standard_normal(x.size), nn.SLOPE))
+    g0 = N.round_bf16(r.standard_normal(x.size))
+    g1 = N.round_bf16(r.standard_normal(x.size) * 1e-2)
+    dz = empty(x.size)
+    t0, t1, to = dev_bf16(g0), dev_bf16(g1), dev_bf16(out)
+    nn.call("clb_nn_act_grad", nn.ptr(t0), None, nn.ptr(to), x.size, nn.SLOPE, nn.ptr(dz), None)
+    assert np.array_equal(host(dz), N.round_bf16(N.leaky_grad(g0, out, nn.SLOPE)))
+    nn.call("clb_nn_act_grad", nn.ptr(t0), nn.ptr(t1), nn.ptr(to), x.size, nn.SLOPE, nn.ptr(dz),
+            None)
+    assert np.array_equal(host(dz), N.round_bf16(N.leaky_grad(N.round_bf16(g0 + g1), out,
+                                                              nn.SLOPE)))
+
+
+def test_mse_adamw_features_gather(nn):
+    import torch
+    r = rng(12)
+    npix, ldo, nch = 1000, 16, 3
+    out = r.standard_normal((npix, ldo)).astype(np.float32).astype(np.float64)
+    tgt = r.standard_normal((npix, nch)).astype(np.float32).astype(np.float64)
+    nb = C.c_size_t()
+    nn.call("clb_nn_mse_workspace_bytes", npix, C.byref(nb))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    dout = empty(npix * ldo)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tout, ttgt = dev_f32(out), dev_f32(tgt)
+    nn.call("clb_nn_mse", nn.ptr(tout), ldo, nn.ptr(ttgt), nch, npix, nn.ptr(dout), nn.ptr(loss),
+            nn.ptr(ws), nb.value, None)
+    rl, rg = N.mse(out[:, :nch], tgt)
+    assert abs(loss.item() - rl) <= 1e-6 * rl
+    g = host(dout).reshape(npix, ldo)
+    assert np.all(g[:, nch:] == 0)
+    check_bf16(g[:, :nch], rg, "mse grad")
+    # AdamW over a few steps
+    n = 5000
+    p0 = r.standard_normal(n).astype(np.float32)
+    p, m, v = dev_f32(p0), empty(n, "f32"), empty(n, "f32")
+    rp, rm, rv = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in range(1, 4):
+        gr = r.standard_normal(n).astype(np.float32)
+        tg = dev_f32(gr)
+        nn.call("clb_nn_adamw", nn.ptr(p), nn.ptr(tg), nn.ptr(m), nn.ptr(v), n, 1e-2,
+                0.9, 0.999, 1e-8, 1e-2, t, None)
+        torch.cuda.synchronize()
+        rp, rm, rv = N.adamw_step(rp, gr.astype(np.float64), rm, rv, t, 1e-2, wd=1e-2)
+    assert np.allclose(host(p), rp, rtol=0, atol=1e-6)
+    # features and gather
+    S, H, W, ng = 5, 8, 16, 4
+    eps = r.uniform(0.3, 0.95, (S, H, W)).astype(np.float32)
+    groups = r.standard_normal((S, ng)).astype(np.float32)
+    idx = np.array([3, 0, 3], dtype=np.int32)
+    xf = empty(3 * H * W * 16)
+    te, tgr, ti = dev_f32(eps), dev_f32(groups), torch.tensor(idx).cuda()
+    nn.call("clb_nn_features", nn.ptr(te), nn.ptr(tgr), ng, nn.ptr(ti), 3, H, W, nn.ptr(xf), None)
+    f = host(xf).reshape(3, H, W, 16)
+    assert np.array_equal(f[..., 0], N.round_bf16((eps[idx].astype(np.float64) - 0.625) * 5))
+    assert np.array_equal(f[1, 2, 3, 1:1 + ng], N.round_bf16(groups[0]))
+    assert f[0, 0, 0, ng + 1] == -1.0 and f[0, 0, W - 1, ng + 1] == 1.0
+    assert f[0, H - 1, 0, ng + 2] == 1.0 and np.all(f[..., ng + 3:] == 0)
+    fields = r.standard_normal((S, H * W, 3)).astype(np.float32)
+    tg = empty(3 * H * W * 3, "f32")
+    tf = dev_f32(fields)
+    nn.call("clb_nn_gather", nn.ptr(tf), 3, nn.ptr(ti), 3, H * W, nn.ptr(tg), None)
+    assert np.array_equal(host(tg).reshape(3, H * W, 3), fields[idx])
+
+
+def test_unet_loss_and_gradients_match_oracle(nn):
+    """Three-level network (widths 16, 32, 64) on a batch of two 16 x 16
+    inputs: output, loss and every parameter gradient against the oracle's
+    reverse pass with the same bfloat16 storage points."""
+    import torch
+    net = nn.UNet(levels=3, base=16, cin=16, cout=16, seed=3)
+    r = rng(13)
+    Bn, H, W = 2, 16, 16
+    x = N.round_bf16(r.standard_normal((Bn, H, W, 16)))
+    tgt = r.standard_normal((Bn, H, W, 3)).astype(np.float32).astype(np.float64)
+    params = [(w.astype(np.float64), b.astype(np.float64)) for w, b in net.param_list()]
+    tx = dev_bf16(x)
+    out = net.forward(tx, Bn, H, W)
+    ro = N.unet_forward(params, x, levels=3, base=16, slope=nn.SLOPE)
+    eo = np.linalg.norm(host(out).reshape(ro.shape) - ro) / np.linalg.norm(ro)
+    ttgt = dev_f32(tgt)
+    loss = net.backward(ttgt, 3, Bn, H, W)
+    rl, rg = N.unet_loss_grads(params, x, tgt, levels=3, base=16, slope=nn.SLOPE)
+    gl = net.grad_list()
+    errs = []
+    for (gw, gb), (rw, rb) in zip(gl, rg):
+        errs.append(max(np.linalg.norm(gw - rw) / np.linalg.norm(rw),
+                        np.linalg.norm(gb - rb) / max(np.linalg.norm(rb), 1e-30)))
+    log("unet output rel-L2 %.2e, loss gpu %.9f oracle %.9f, worst grad rel-L2 %.2e"
+        % (eo, loss.item(), rl, max(errs)))
+    assert eo <= 1e-3
+    assert abs(loss.item() - rl) <= 1e-3 * rl
+    assert max(errs) <= 1e-2
+    torch.cuda.synchronize()
