@@ -245,10 +245,14 @@ clb_status clb_put_state(clb_ctx *ctx, const void *host_buf, size_t bytes);
 /* Time steps taken so far. */
 clb_status clb_steps_done(clb_ctx *ctx, int64_t *steps);
 
-/* Launch shape of the step kernel: a work tile is tile_x * tile_y nodes run by
- * one workgroup of tile_x * tile_y threads (tile_x in {64, 128, 256},
- * tile_x * tile_y in {64, 128, 256, 512}); `blocks` workgroups loop over the
- * tiles (0: one workgroup per tile).  Re-captures the step graph. */
+/* Launch shape of the node kernels.  tile_x = tile_y = 0 (the default)
+ * chooses per domain a tile width of 64, 128 or 256 nodes (the fewest idle
+ * lanes per row, the wider on a tie) and stacks rows to 256 threads; otherwise
+ * every work tile is tile_x * tile_y nodes (tile_x in {64, 128, 256},
+ * tile_x * tile_y in {64, 128, 256, 512}).  One workgroup runs one tile at a
+ * time, one thread per node; `blocks` workgroups loop over the tiles (0: one
+ * workgroup per tile).  Results do not depend on the shape.  Re-captures the
+ * step graph. */
 clb_status clb_set_launch(clb_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t blocks);
 clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_t *blocks);
 

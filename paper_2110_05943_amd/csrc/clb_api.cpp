@@ -261,7 +261,7 @@ struct clb_ctx {
   std::vector<Tile> tiles_all, tiles_active;
   std::vector<int32_t> tile0, ntiles;
   std::vector<uint8_t> active;
-  LaunchShape shape{256, 1, 0};
+  LaunchShape shape{0, 0, 0};
   int64_t steps = 0;
   int parity = 0;
   bool snap_valid = false;
@@ -331,13 +331,36 @@ void fill_desc(const clb_params &p, const clb_derived &d, CavDesc &k) {
   k.dT = d.dT;
 }
 
+// Tile width for a row of nx nodes when the shape is chosen per domain: the
+// fewest idle lanes per row, the wider width on a tie.
+int auto_width(int nx) {
+  int best = 64;
+  long best_idle = -1;
+  for (int w : {64, 128, 256}) {
+    const long idle = (long)((nx + w - 1) / w) * w - nx;
+    if (best_idle < 0 || idle <= best_idle) {
+      best = w;
+      best_idle = idle;
+    }
+  }
+  return best;
+}
+
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
 // All tiles of every domain in domain order.
 void build_tiles(clb_ctx *c) {
   c->tiles_all.clear();
   c->tile0.assign(c->count, 0);
   c->ntiles.assign(c->count, 0);
-  const int tx = c->shape.tile_x, ty = c->shape.tile_y;
   for (int k = 0; k < c->count; ++k) {
+    const int tx = c->shape.tile_x ? c->shape.tile_x : auto_width(c->p[k].nx);
+    const int ty = c->shape.tile_x ? c->shape.tile_y : 256 / tx;
+    c->desc[k].tw_log2 = log2i(tx);
     c->tile0[k] = (int32_t)c->tiles_all.size();
     for (int y0 = 0; y0 < c->p[k].ny; y0 += ty)
       for (int x0 = 0; x0 < c->p[k].nx; x0 += tx)
@@ -389,6 +412,7 @@ clb_status upload_tiles(clb_ctx *c) {
 }
 
 bool shape_ok(int tx, int ty) {
+  if (tx == 0 && ty == 0) return true;  // width chosen per domain
   if (tx != 64 && tx != 128 && tx != 256) return false;
   const int n = tx * ty;
   return ty >= 1 && (n == 64 || n == 128 || n == 256 || n == 512);
@@ -909,7 +933,7 @@ extern "C" clb_status clb_autotune(clb_ctx *c, const char *cache_path) {
     }
     if (found.blocks >= 0) return clb_set_launch(c, found.tile_x, found.tile_y, found.blocks);
   }
-  const int shapes[][2] = {{64, 1},  {64, 2},  {64, 4},  {64, 8},  {128, 1},
+  const int shapes[][2] = {{0, 0},   {64, 1},  {64, 2},  {64, 4},  {64, 8}, {128, 1},
                            {128, 2}, {128, 4}, {256, 1}, {256, 2}};
   size_t nodes = 0;
   for (const auto &p : c->p) nodes += (size_t)p.nx * p.ny;

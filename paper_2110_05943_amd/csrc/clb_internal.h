@@ -32,7 +32,8 @@ struct Tile {
 struct alignas(16) CavDesc {
   int32_t nx, ny, pitch, plane;   // plane = ny * pitch elements
   int32_t bc[4];
-  int32_t has_eps, tile0, ntiles, _pad0;
+  int32_t has_eps, tile0, ntiles;
+  int32_t tw_log2;                // tiles of this domain are (1 << tw_log2) nodes wide
   char *A;                        // population planes, 14 planes (9 f, 5 g)
   char *B;                        // second buffer (A/B double buffering)
   const float *eps;               // porosity plane (pitch layout) or null
@@ -67,8 +68,14 @@ struct alignas(16) CavDesc {
   double dT;                      // temperature difference of the Nusselt number
 };
 
+// Tile shape of the node kernels.  tile_x = 0 chooses the width per domain
+// (the smallest of 64, 128, 256 that covers a row with the fewest idle
+// lanes, rows stacked to 256 threads); otherwise every domain uses
+// tile_x x tile_y.  Work-groups are flat: thread t of a tile handles node
+// (x0 + t % width, y0 + t / width).  blocks = 0: one work-group per tile.
 struct LaunchShape {
   int tile_x, tile_y, blocks;
+  int threads() const { return tile_x ? tile_x * tile_y : 256; }
 };
 
 // Kernel launchers (clb_kernels.hip).  All return hipSuccess or the launch error.

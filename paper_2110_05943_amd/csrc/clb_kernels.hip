@@ -474,14 +474,15 @@ __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ d
   using R = typename P::R;
   const int ntiles = counts[0];
   const uint32_t step = (uint32_t)counts[2 + parity];
-  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) counts[3 - parity] = (int32_t)(step + 1);
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[3 - parity] = (int32_t)(step + 1);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int cav = __builtin_amdgcn_readfirstlane(tiles[t].cav);
     if (cav < 0) continue;  // padding entry of the XCD-ordered list
     const int x0 = __builtin_amdgcn_readfirstlane(tiles[t].x0);
     const int y0 = __builtin_amdgcn_readfirstlane(tiles[t].y0);
     const CavDesc &d = descs[cav];
-    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    const int lw = d.tw_log2;
+    const int x = x0 + (int)(threadIdx.x & ((1u << lw) - 1u)), y = y0 + (int)(threadIdx.x >> lw);
     if (x < d.nx && y < d.ny) {
       const char *A = parity ? d.B : d.A;
       char *B = parity ? d.A : d.B;
@@ -592,8 +593,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Sum kRed doubles over a block in a fixed order; result valid in thread 0.
 __device__ __forceinline__ void block_sum(double (&v)[kRed], double (*lds)[kRed]) {
-  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-  const int nthreads = blockDim.x * blockDim.y;
+  const int tid = threadIdx.x;
+  const int nthreads = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63;
   for (int k = 0; k < kRed; ++k) v[k] = wave_sum(v[k]);
   if (lane == 0)
@@ -620,7 +621,9 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
   const int cav = __builtin_amdgcn_readfirstlane(tiles[t].cav);
   if (cav < 0) return;  // padding entry of an active list (uniform per block)
   const CavDesc &d = descs[cav];
-  const int x = tiles[t].x0 + threadIdx.x, y = tiles[t].y0 + threadIdx.y;
+  const int lw = d.tw_log2;
+  const int x = tiles[t].x0 + (int)(threadIdx.x & ((1u << lw) - 1u));
+  const int y = tiles[t].y0 + (int)(threadIdx.x >> lw);
   double v[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (x < d.nx && y < d.ny) {
     const char *A = parity ? d.B : d.A;
@@ -645,7 +648,7 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
   }
   block_sum(v, lds);
   const size_t slot = (size_t)tiles[t].id * kRed;
-  if (threadIdx.x == 0 && threadIdx.y == 0)
+  if (threadIdx.x == 0)
     for (int k = 0; k < kRed; ++k) partials[slot + k] = v[k];
 }
 
@@ -672,7 +675,9 @@ __global__ void __launch_bounds__(512) macros_kernel(const CavDesc *__restrict__
   const int t = tile0 + blockIdx.x;
   const int cav = __builtin_amdgcn_readfirstlane(tiles[t].cav);
   const CavDesc &d = descs[cav];
-  const int x = tiles[t].x0 + threadIdx.x, y = tiles[t].y0 + threadIdx.y;
+  const int lw = d.tw_log2;
+  const int x = tiles[t].x0 + (int)(threadIdx.x & ((1u << lw) - 1u));
+  const int y = tiles[t].y0 + (int)(threadIdx.x >> lw);
   if (x >= d.nx || y >= d.ny) return;
   const char *A = parity ? d.B : d.A;
   NodeState<R> st;
@@ -727,7 +732,7 @@ __global__ void __launch_bounds__(256) nusselt_kernel(const CavDesc *__restrict_
 
 // --------------------------------------------------------------- launchers
 
-static dim3 block_of(const LaunchShape &s) { return dim3(s.tile_x, s.tile_y, 1); }
+static dim3 block_of(const LaunchShape &s) { return dim3(s.threads(), 1, 1); }
 
 // Calls f(StoreX{}) for the storage kind of the context (0 FP32, 1 FP16,
 // 2 FP16 flow + FP32 temperature).
