@@ -108,6 +108,29 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
   return x;
 }
 
+// ------------------------------------------------------- fast FP64 helpers
+
+// 1/x and sqrt(x) in FP64 from the hardware FP32 estimates refined by two
+// Newton steps (each doubles the number of correct bits: 23 -> 46 -> 92), a
+// fraction of the instructions of the IEEE FP64 division and square-root
+// sequences.  rcp64 is used for values of order one (rho, the porosity, the
+// velocity denominator of Eq. 23); sqrt64 takes the IEEE path for arguments below
+// 1e-30, whose FP32 image would be zero or subnormal.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = (double)__builtin_amdgcn_rcpf((float)x);
+  r = r * (2.0 - x * r);
+  return r * (2.0 - x * r);
+}
+__device__ __forceinline__ float rcp64(float x) { return 1.0f / x; }
+__device__ __forceinline__ double sqrt64(double x) {
+  if (!(x > 1e-30)) return sqrt(x);
+  double y = (double)__builtin_amdgcn_rsqf((float)x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return x * y;
+}
+__device__ __forceinline__ float sqrt64(float x) { return sqrtf(x); }
+
 // ------------------------------------------------------------- node state
 
 // Deviations of the raw moments of Eq. 9 (k00 - 1, k10, k01, k20 - 1/3,
@@ -152,7 +175,7 @@ __device__ __forceinline__ void medium_at(const CavDesc &d, int idx, R &phi, R &
     // phi F_phi / sqrt(K):  cd = 150 nu (1-phi)^2 / (phi^2 dp^2),
     // cf = 1.75 (1-phi) / (phi^2 dp).
     phi = (R)d.eps[idx];
-    ip = R(1) / phi;
+    ip = rcp64(phi);
     const R q = (R(1) - phi) * ip;
     cd = (R)d.kc_d * q * q;
     cf = (R)d.kc_f * q * ip;
@@ -222,15 +245,15 @@ __device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__r
   medium_at(d, r0 + xs, st.phi, st.ip, st.cd, st.cf);
   // Eqs. 20-23: rho, the temporal velocity v and the explicit velocity u.
   st.rho = R(1) + st.dr;
-  const R irho = R(1) / st.rho;
+  const R irho = rcp64(st.rho);
   const R Gx = (R)d.gbx * st.th + (R)d.ax, Gy = (R)d.gby * st.th + (R)d.ay;
   const R hphi = R(0.5) * st.phi;
   const R vx = st.jx * irho + hphi * Gx;
   const R vy = st.jy * irho + hphi * Gy;
-  const R vm = sqrt(vx * vx + vy * vy);
+  const R vm = sqrt64(vx * vx + vy * vy);
   const R l0 = R(0.5) + R(0.25) * st.cd;
   const R l1 = R(0.5) * st.cf;
-  const R iD = R(1) / (l0 + sqrt(l0 * l0 + l1 * vm));
+  const R iD = rcp64(l0 + sqrt64(l0 * l0 + l1 * vm));
   st.ux = vx * iD;
   st.uy = vy * iD;
   st.umag = vm * iD;
