@@ -92,19 +92,16 @@ __device__ __forceinline__ const typename P::G *gplanes(const char *buf, int pla
 }
 
 // Counter-based random bits: an integer hash (xorshift-multiply finaliser)
-// seeds a xorshift32 sequence; a run is reproducible bit for bit.
+// of (node, step, domain) gives each node one random word; further words of
+// the node follow by golden-ratio (Weyl) increments.  Each rounding only
+// needs bits that are uniform over the steps at its own node; a run is
+// reproducible bit for bit.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
   x ^= x >> 15;
   x *= 0x846ca68bu;
   x ^= x >> 16;
-  return x;
-}
-__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
-  x ^= x << 13;
-  x ^= x >> 17;
-  x ^= x << 5;
   return x;
 }
 
@@ -478,7 +475,7 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
       stv(of + i * plane, out[i], (i & 1) ? (w >> 16) : w);
     else
       stv(og + (i - 9) * plane, out[i], (i & 1) ? (w >> 16) : w);
-    if (i & 1) w = xorshift32(w);
+    if (i & 1) w += 0x9E3779B9u;
   }
 }
 
