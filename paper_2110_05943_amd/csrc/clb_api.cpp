@@ -179,10 +179,12 @@ extern "C" clb_status clb_derive(const clb_params *pp, clb_derived *out) {
 namespace {
 
 struct Layout {
-  size_t desc, tiles_all, tiles_active, counts, partials, results, nu, nu_local, obs;
+  size_t desc, tiles_all, tiles_active, counts, partials, gpart, results, nu, nu_local, nu_part,
+      obs;
   std::vector<size_t> A, B, eps, snap;
   size_t total;
   size_t max_tiles, obs_elems, max_wall;
+  int32_t max_chunks;
 };
 
 size_t max_tiles_of(const clb_params &p) {
@@ -211,9 +213,12 @@ Layout make_layout(const clb_params *p, int count) {
   L.tiles_active = take(sizeof(Tile) * (L.max_tiles + 8));
   L.counts = take(sizeof(int32_t) * 4);
   L.partials = take(sizeof(double) * clb::kRed * L.max_tiles);
+  L.gpart = take(sizeof(double) * clb::kRed * L.max_tiles);
   L.results = take(sizeof(double) * clb::kRed * count);
   L.nu = take(sizeof(double) * count);
   L.nu_local = take(sizeof(double) * L.max_wall);
+  L.max_chunks = (int32_t)((L.max_wall + 255) / 256);
+  L.nu_part = take(sizeof(double) * (size_t)L.max_chunks * count);
   L.obs = take(sizeof(float) * 4 * L.obs_elems);
   for (int c = 0; c < count; ++c) {
     const size_t plane = (size_t)p[c].ny * pitch_of(p[c]);
@@ -256,7 +261,8 @@ struct clb_ctx {
   CavDesc *d_desc = nullptr;
   Tile *d_tiles_all = nullptr, *d_tiles_active = nullptr;
   int32_t *d_counts = nullptr;
-  double *d_partials = nullptr, *d_results = nullptr, *d_nu = nullptr, *d_nu_local = nullptr;
+  double *d_partials = nullptr, *d_gpart = nullptr, *d_results = nullptr, *d_nu = nullptr,
+         *d_nu_local = nullptr, *d_nu_part = nullptr;
   float *d_obs = nullptr;
   std::vector<Tile> tiles_all, tiles_active;
   std::vector<int32_t> tile0, ntiles;
@@ -479,6 +485,8 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->d_tiles_active = reinterpret_cast<Tile *>(c->ws + lay.tiles_active);
   c->d_counts = reinterpret_cast<int32_t *>(c->ws + lay.counts);
   c->d_partials = reinterpret_cast<double *>(c->ws + lay.partials);
+  c->d_gpart = reinterpret_cast<double *>(c->ws + lay.gpart);
+  c->d_nu_part = reinterpret_cast<double *>(c->ws + lay.nu_part);
   c->d_results = reinterpret_cast<double *>(c->ws + lay.results);
   c->d_nu = reinterpret_cast<double *>(c->ws + lay.nu);
   c->d_nu_local = reinterpret_cast<double *>(c->ws + lay.nu_local);
@@ -619,7 +627,8 @@ extern "C" clb_status clb_nusselt(clb_ctx *c, int32_t cav, int32_t side, double 
   if (p.bc[side] == CLB_PERIODIC) return CLB_ERR_ARG;
   const int nw = side < 2 ? p.ny : p.nx;
   HIPCHK(clb::launch_nusselt(c->d_desc, cav, 1, side, c->parity, c->d_nu,
-                             nu_local ? c->d_nu_local : nullptr, c->storage, c->stream));
+                             nu_local ? c->d_nu_local : nullptr, c->d_nu_part, c->lay.max_chunks,
+                             c->storage, c->stream));
   double m = 0.0;
   HIPCHK(hipMemcpyAsync(&m, c->d_nu + cav, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (nu_local)
@@ -634,8 +643,8 @@ extern "C" clb_status clb_nusselt_all(clb_ctx *c, int32_t side, double *nu_mean)
   if (!c || side < 0 || side > 3 || !nu_mean) return CLB_ERR_ARG;
   for (int k = 0; k < c->count; ++k)
     if (c->p[k].bc[side] == CLB_PERIODIC) return CLB_ERR_ARG;
-  HIPCHK(clb::launch_nusselt(c->d_desc, 0, c->count, side, c->parity, c->d_nu, nullptr, c->storage,
-                             c->stream));
+  HIPCHK(clb::launch_nusselt(c->d_desc, 0, c->count, side, c->parity, c->d_nu, nullptr,
+                             c->d_nu_part, c->lay.max_chunks, c->storage, c->stream));
   std::vector<double> h(c->count);
   HIPCHK(hipMemcpyAsync(h.data(), c->d_nu, sizeof(double) * c->count, hipMemcpyDeviceToHost,
                         c->stream));
@@ -645,6 +654,13 @@ extern "C" clb_status clb_nusselt_all(clb_ctx *c, int32_t side, double *nu_mean)
 }
 
 namespace {
+// Groups of 256 tile partial sums in the largest domain.
+int32_t max_groups(const clb_ctx *c) {
+  int32_t m = 1;
+  for (int k = 0; k < c->count; ++k) m = std::max(m, (c->ntiles[k] + 255) / 256);
+  return m;
+}
+
 // Residual sums per domain into h (kRed values per domain).  With
 // active_only, only the tiles of active domains are evaluated and the slots
 // of the other domains keep their last values.
@@ -656,8 +672,8 @@ clb_status residual_sums(clb_ctx *c, std::vector<double> &h, bool active_only = 
   else
     HIPCHK(clb::launch_residual(c->d_desc, c->d_tiles_all, (int)c->tiles_all.size(), c->parity,
                                 c->d_partials, c->storage, c->shape, c->stream));
-  HIPCHK(clb::launch_residual_finalize(c->d_desc, c->count, c->d_partials, c->d_results,
-                                       c->stream));
+  HIPCHK(clb::launch_residual_finalize(c->d_desc, c->count, max_groups(c), c->d_partials,
+                                       c->d_gpart, c->d_results, c->stream));
   h.assign((size_t)clb::kRed * c->count, 0.0);
   HIPCHK(hipMemcpyAsync(h.data(), c->d_results, sizeof(double) * h.size(), hipMemcpyDeviceToHost,
                         c->stream));
@@ -782,7 +798,7 @@ extern "C" clb_status clb_run(clb_ctx *c, int64_t max_steps, int32_t check_every
     if (s != CLB_OK) return s;
     if (nu_side >= 0) {
       HIPCHK(clb::launch_nusselt(c->d_desc, 0, n, nu_side, c->parity, c->d_nu, nullptr,
-                                 c->storage, c->stream));
+                                 c->d_nu_part, c->lay.max_chunks, c->storage, c->stream));
       HIPCHK(hipMemcpyAsync(nu.data(), c->d_nu, sizeof(double) * n, hipMemcpyDeviceToHost,
                             c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));

@@ -89,14 +89,19 @@ hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int pa
 // tiles[t].id of `partials`.
 hipError_t launch_residual(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int parity,
                            double *partials, int storage, LaunchShape shape, hipStream_t s);
-hipError_t launch_residual_finalize(const CavDesc *descs, int32_t count, const double *partials,
-                                    double *results, hipStream_t s);
+// Per-domain totals of the partial sums (two fixed-order passes through
+// gpart, max_groups >= ceil(ntiles / 256) of every domain).
+hipError_t launch_residual_finalize(const CavDesc *descs, int32_t count, int32_t max_groups,
+                                    const double *partials, double *gpart, double *results,
+                                    hipStream_t s);
 hipError_t launch_macros(const CavDesc *descs, const Tile *tiles, int32_t tile0, int32_t ntiles,
                          int parity, float *out /* 4 dense planes */, int storage,
                          LaunchShape shape, hipStream_t s);
+// Mean Nusselt number of domains cav0 .. cav0 + ncav - 1 on one side; chunks
+// of 256 wall nodes go through nu_part (max_chunks per domain).
 hipError_t launch_nusselt(const CavDesc *descs, int32_t cav0, int32_t ncav, int32_t side,
-                          int parity, double *nu_mean, double *nu_local, int storage,
-                          hipStream_t s);
+                          int parity, double *nu_mean, double *nu_local, double *nu_part,
+                          int32_t max_chunks, int storage, hipStream_t s);
 
 // (clb_state.hip) planes[0..n) = u_scale src[i*stride], planes[n..2n) =
 // u_scale src[i*stride + 1], planes[2n..3n) = th_offset + src[i*stride + 2].

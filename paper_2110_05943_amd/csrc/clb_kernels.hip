@@ -92,16 +92,26 @@ __device__ __forceinline__ const typename P::G *gplanes(const char *buf, int pla
 }
 
 // Counter-based random bits: an integer hash (xorshift-multiply finaliser)
-// of (node, step, domain) gives each node one random word; further words of
-// the node follow by golden-ratio (Weyl) increments.  Each rounding only
-// needs bits that are uniform over the steps at its own node; a run is
-// reproducible bit for bit.
+// of (node, step, domain) gives each node one random word; a run is
+// reproducible bit for bit.  Further words of the node: for FP32 storage
+// (rounding noise ~1e-8) golden-ratio (Weyl) increments, the cheapest
+// sequence; for FP16 storage, whose rounding noise (~1e-4) reaches the wall
+// gradient of the Nusselt number, a xorshift32 step, so that the roundings of
+// the populations of one node stay uncorrelated.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
   x ^= x >> 15;
   x *= 0x846ca68bu;
   x ^= x >> 16;
+  return x;
+}
+template <typename R>
+__device__ __forceinline__ uint32_t next_bits(uint32_t x) {
+  if (sizeof(R) == 8) return x + 0x9E3779B9u;
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
   return x;
 }
 
@@ -475,7 +485,7 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
       stv(of + i * plane, out[i], (i & 1) ? (w >> 16) : w);
     else
       stv(og + (i - 9) * plane, out[i], (i & 1) ? (w >> 16) : w);
-    if (i & 1) w += 0x9E3779B9u;
+    if (i & 1) w = next_bits<R>(w);
   }
 }
 
@@ -672,15 +682,37 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
     for (int k = 0; k < kRed; ++k) partials[slot + k] = v[k];
 }
 
-// Per-domain totals of the tile partial sums (fixed order, deterministic).
+// Per-domain totals of the tile partial sums in two fixed-order passes
+// (deterministic): block (g, cav) adds the partial sums of tiles
+// [256 g, 256 g + 256) of the domain into gpart slot tile0 + g; one block per
+// domain then adds its group sums.
+constexpr int kGroup = 256;
+
+__global__ void __launch_bounds__(256) residual_groups(const CavDesc *__restrict__ descs,
+                                                       const double *__restrict__ partials,
+                                                       double *__restrict__ gpart) {
+  __shared__ double lds[4][kRed];
+  const CavDesc &d = descs[blockIdx.y];
+  const int g = blockIdx.x;
+  if (g * kGroup >= d.ntiles) return;  // uniform per block
+  double v[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int t = g * kGroup + threadIdx.x;
+  if (t < d.ntiles)
+    for (int k = 0; k < kRed; ++k) v[k] = partials[(size_t)(d.tile0 + t) * kRed + k];
+  block_sum(v, lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kRed; ++k) gpart[(size_t)(d.tile0 + g) * kRed + k] = v[k];
+}
+
 __global__ void __launch_bounds__(256) residual_finalize(const CavDesc *__restrict__ descs,
-                                                         const double *__restrict__ partials,
+                                                         const double *__restrict__ gpart,
                                                          double *__restrict__ results) {
   __shared__ double lds[4][kRed];
   const CavDesc &d = descs[blockIdx.x];
+  const int ng = (d.ntiles + kGroup - 1) / kGroup;
   double v[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int t = threadIdx.x; t < d.ntiles; t += blockDim.x)
-    for (int k = 0; k < kRed; ++k) v[k] += partials[(size_t)(d.tile0 + t) * kRed + k];
+  for (int g = threadIdx.x; g < ng; g += blockDim.x)
+    for (int k = 0; k < kRed; ++k) v[k] += gpart[(size_t)(d.tile0 + g) * kRed + k];
   block_sum(v, lds);
   if (threadIdx.x == 0)
     for (int k = 0; k < kRed; ++k) results[(size_t)blockIdx.x * kRed + k] = v[k];
@@ -715,19 +747,22 @@ __global__ void __launch_bounds__(512) macros_kernel(const CavDesc *__restrict__
 template <typename P>
 __global__ void __launch_bounds__(256) nusselt_kernel(const CavDesc *__restrict__ descs, int cav0,
                                                       int side, int parity,
-                                                      double *__restrict__ nu_mean,
+                                                      double *__restrict__ nu_part,
+                                                      int max_chunks,
                                                       double *__restrict__ nu_local) {
   using R = typename P::R;
   __shared__ double lds[4][kRed];
-  const int cav = cav0 + blockIdx.x;
+  const int cav = cav0 + blockIdx.y;
   const CavDesc &d = descs[cav];
   const char *A = parity ? d.B : d.A;
   const bool along_y = side < 2;
   const int nw = along_y ? d.ny : d.nx;
+  if ((int)blockIdx.x * 256 >= nw) return;  // uniform per block
   const double L = along_y ? d.nx - 1 : d.ny - 1;
   const double sign = (side == 0 || side == 2) ? 1.0 : -1.0;
   double v[kRed] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < nw) {
     double t[3];
     for (int k = 0; k < 3; ++k) {
       int x, y;
@@ -744,10 +779,25 @@ __global__ void __launch_bounds__(256) nusselt_kernel(const CavDesc *__restrict_
     }
     const double nu = -L * sign * (-3.0 * t[0] + 4.0 * t[1] - t[2]) * 0.5 / d.dT;
     if (nu_local) nu_local[j] = nu;
-    v[0] += (j == 0 || j == nw - 1) ? 0.5 * nu : nu;
+    v[0] = (j == 0 || j == nw - 1) ? 0.5 * nu : nu;  // trapezoid weights
   }
   block_sum(v, lds);
-  if (threadIdx.x == 0) nu_mean[cav] = v[0] / (nw - 1);
+  if (threadIdx.x == 0) nu_part[(size_t)cav * max_chunks + blockIdx.x] = v[0];
+}
+
+// Mean Nusselt number of each domain from its chunk sums (fixed order).
+__global__ void __launch_bounds__(64) nusselt_finalize(const CavDesc *__restrict__ descs,
+                                                       int cav0, int side,
+                                                       const double *__restrict__ nu_part,
+                                                       int max_chunks,
+                                                       double *__restrict__ nu_mean) {
+  const int cav = cav0 + blockIdx.x;
+  const CavDesc &d = descs[cav];
+  const int nw = side < 2 ? d.ny : d.nx;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int c = 0; c * 256 < nw; ++c) s += nu_part[(size_t)cav * max_chunks + c];
+  nu_mean[cav] = s / (nw - 1);
 }
 
 // --------------------------------------------------------------- launchers
@@ -800,9 +850,12 @@ hipError_t launch_residual(const CavDesc *descs, const Tile *tiles, int32_t ntil
   return hipGetLastError();
 }
 
-hipError_t launch_residual_finalize(const CavDesc *descs, int32_t count, const double *partials,
-                                    double *results, hipStream_t s) {
-  hipLaunchKernelGGL(residual_finalize, dim3(count), dim3(256), 0, s, descs, partials, results);
+hipError_t launch_residual_finalize(const CavDesc *descs, int32_t count, int32_t max_groups,
+                                    const double *partials, double *gpart, double *results,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(residual_groups, dim3(max_groups, count), dim3(kGroup), 0, s, descs, partials,
+                     gpart);
+  hipLaunchKernelGGL(residual_finalize, dim3(count), dim3(256), 0, s, descs, gpart, results);
   return hipGetLastError();
 }
 
@@ -818,13 +871,15 @@ hipError_t launch_macros(const CavDesc *descs, const Tile *tiles, int32_t tile0,
 }
 
 hipError_t launch_nusselt(const CavDesc *descs, int32_t cav0, int32_t ncav, int32_t side,
-                          int parity, double *nu_mean, double *nu_local, int storage,
-                          hipStream_t s) {
+                          int parity, double *nu_mean, double *nu_local, double *nu_part,
+                          int32_t max_chunks, int storage, hipStream_t s) {
   dispatch(storage, [&](auto p) {
     using P = decltype(p);
-    hipLaunchKernelGGL(nusselt_kernel<P>, dim3(ncav), dim3(256), 0, s, descs, cav0, side, parity,
-                       nu_mean, nu_local);
+    hipLaunchKernelGGL(nusselt_kernel<P>, dim3(max_chunks, ncav), dim3(256), 0, s, descs, cav0,
+                       side, parity, nu_part, max_chunks, nu_local);
   });
+  hipLaunchKernelGGL(nusselt_finalize, dim3(ncav), dim3(64), 0, s, descs, cav0, side, nu_part,
+                     max_chunks, nu_mean);
   return hipGetLastError();
 }
 
