@@ -169,12 +169,72 @@ def warmstart_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def table1_bench(args):
+    """Table 1 of the paper: steady hot-wall Nusselt numbers of the porous
+    cavity for Da = 1e-2, 1e-4, 1e-6 (grids 128^2, 192^2, 256^2 as in Section
+    3.2), three Ra each and porosity 0.4, 0.6, 0.9, Pr = 1: 27 cavities in
+    one context, run from rest until the change per step over 5000-step
+    rounds is <= 1e-9 (or 1e7 steps)."""
+    import numpy as np
+    from paper_2110_05943_amd import WEST, Solver, inputs, workloads
+    from paper_2110_05943_amd._binding import NOT_CONVERGED, OK
+    grid = {1e-2: 128, 1e-4: 192, 1e-6: 256}
+    ref = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "table1_present.txt")):
+        if line.strip() and not line.startswith("#"):
+            v = [float(x) for x in line.split()]
+            for phi, nu in zip((0.4, 0.6, 0.9), v[2:]):
+                ref.append((v[0], v[1], phi, nu))
+    cases = [workloads.cavity(grid[Da], Ra=Ra, Da=Da, phi=phi, Pr=1.0, storage=args.storage)
+             for Da, Ra, phi, _ in ref]
+    s = Solver(cases)
+    for k, c in enumerate(cases):
+        s.set_state(k, inputs.cavity_initial_T(c["nx"], seed=1))
+    every, chunk, cap, tol = 5000, 500_000, 10_000_000, 1e-9
+    steps = np.zeros(len(cases), dtype=np.int64)
+    status = np.full(len(cases), NOT_CONVERGED)
+    nu_last = np.full(len(cases), np.nan)
+    done = 0
+    t0 = time.perf_counter()
+    while done < cap and np.any(status == NOT_CONVERGED):
+        r = s.run(chunk, check_every=every, tol=tol, nu_side=WEST, max_records=chunk // every)
+        live = status == NOT_CONVERGED
+        steps[live] += r["steps"][live]
+        fin = live & (r["status"] != NOT_CONVERGED)
+        status[fin] = r["status"][fin]
+        for k in np.nonzero(live)[0]:
+            rec = r["nu"][k][np.isfinite(r["nu"][k])]
+            if rec.size:
+                nu_last[k] = rec[-1]
+        done += chunk
+        print("  %d steps, %d of %d steady, %.1f s" % (done, int((status == OK).sum()), len(cases),
+                                                      time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    rows = []
+    for k, (Da, Ra, phi, nu_p) in enumerate(ref):
+        rows.append({"Da": Da, "Ra": Ra, "phi": phi, "grid": grid[Da], "nu": round(float(nu_last[k]), 5),
+                     "nu_paper": nu_p, "dev_pct": round(100 * (nu_last[k] - nu_p) / nu_p, 3),
+                     "steps": int(steps[k]), "status": {0: "steady", 4: "diverged",
+                                                        6: "not steady"}.get(int(status[k]), "?")})
+    dev = np.array([abs(r["dev_pct"]) for r in rows if r["status"] == "steady"])
+    out = {"metric": "Table 1 steady mean Nusselt number, deviation from the paper's values",
+           "value": round(float(np.median(dev)), 3) if dev.size else None,
+           "unit": "% (median |deviation| over steady cases)", "higher_is_better": False,
+           "n_gpus": 1, "data": "synthetic", "dtype": "f64 arithmetic, %s storage" % args.storage,
+           "config": {"workload": "27 porous cavities of Table 1 in one context", "tol": tol,
+                      "check_every": every, "max_steps": cap},
+           "wall_s": round(wall, 1), "steady": int((status == OK).sum()),
+           "max_abs_dev_pct": round(float(dev.max()), 3) if dev.size else None, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", choices=("cavity", "batch", "channel", "warmstart"),
+    ap.add_argument("--workload", choices=("cavity", "batch", "channel", "warmstart", "table1"),
                     default="cavity")
     ap.add_argument("--n", type=int, default=4096, help="grid size (cavity; channel: 2048)")
     ap.add_argument("--count", type=int, default=None,
@@ -209,6 +269,8 @@ def main():
         return
     if args.workload == "warmstart":
         return warmstart_bench(args)
+    if args.workload == "table1":
+        return table1_bench(args)
     from paper_2110_05943_amd import WEST, Solver
     from paper_2110_05943_amd._binding import BYTES_PER_UPDATE
 
