@@ -37,13 +37,21 @@ namespace clb {
 // ~1e-8 in the normal FP16 range (the largest, ~0.5, stays far below 65504).
 constexpr float kF16Scale = 4096.0f, kF16Unscale = 1.0f / 4096.0f;
 
+// Population planes live in global memory.  The casts below let the compiler
+// emit global (not flat) loads and stores, and plane-relative 32-bit offsets
+// (at()) let it address them as a uniform base plus a per-lane offset.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+using gcptr = const __attribute__((address_space(1))) T *;
+
 template <typename R>
 __device__ __forceinline__ R ldv(const float *p) {
-  return (R)__builtin_nontemporal_load(p);
+  return (R)__builtin_nontemporal_load((gcptr<float>)p);
 }
 template <typename R>
 __device__ __forceinline__ R ldv(const _Float16 *p) {
-  return (R)((float)__builtin_nontemporal_load(p) * kF16Unscale);
+  return (R)((float)__builtin_nontemporal_load((gcptr<_Float16>)p) * kF16Unscale);
 }
 
 // FP64 -> FP32 with stochastic rounding: 16 random bits are added below the
@@ -53,7 +61,7 @@ __device__ __forceinline__ void stv(float *p, double v, uint32_t r) {
   unsigned long long u = (unsigned long long)__double_as_longlong(v);
   u += (unsigned long long)(r & 0xFFFFu) << 13;
   u &= ~((1ull << 29) - 1ull);
-  __builtin_nontemporal_store((float)__longlong_as_double((long long)u), p);
+  __builtin_nontemporal_store((float)__longlong_as_double((long long)u), (gptr<float>)p);
 }
 // FP32 -> FP16 (scaled) with stochastic rounding: 12 random bits below the
 // FP16 precision (13 bits lie below a normal FP16 significand).
@@ -61,12 +69,12 @@ __device__ __forceinline__ void stv(_Float16 *p, float v, uint32_t r) {
   uint32_t u = __float_as_uint(v * kF16Scale);
   u += (r & 0xFFFu) << 1;
   u &= 0xFFFFE000u;
-  __builtin_nontemporal_store((_Float16)__uint_as_float(u), p);
+  __builtin_nontemporal_store((_Float16)__uint_as_float(u), (gptr<_Float16>)p);
 }
 
 // FP32 -> FP32: no rounding (mixed storage computes the FP32 planes in FP32).
 __device__ __forceinline__ void stv(float *p, float v, uint32_t) {
-  __builtin_nontemporal_store(v, p);
+  __builtin_nontemporal_store(v, (gptr<float>)p);
 }
 
 // Storage policy: element types of the 9 D2Q9 planes (F) and the 5 D2Q5
@@ -138,6 +146,15 @@ __device__ __forceinline__ double sqrt64(double x) {
 }
 __device__ __forceinline__ float sqrt64(float x) { return sqrtf(x); }
 
+// Element i of a plane as a byte offset below 4 GiB from the plane base.
+template <typename T>
+__device__ __forceinline__ T *at(T *base, uint32_t i) {
+  return (T *)((char *)base + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T *at(const T *base, uint32_t i) {
+  return (const T *)((const char *)base + i * (uint32_t)sizeof(T));
+}
 // ------------------------------------------------------------- node state
 
 // Deviations of the raw moments of Eq. 9 (k00 - 1, k10, k01, k20 - 1/3,
@@ -214,20 +231,20 @@ __device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__r
   const typename P::F *A = fplanes<P>(buf);
   const typename P::G *G = gplanes<P>(buf, plane);
   // f_i(x) = f_i*(x - e_i), velocities of Eq. 6.
-  const R f0 = ldv<R>(A + r0 + xs);
-  const R f1 = ldv<R>(A + plane + r0 + xm);
-  const R f2 = ldv<R>(A + 2 * plane + rm + xs);
-  const R f3 = ldv<R>(A + 3 * plane + r0 + xp);
-  const R f4 = ldv<R>(A + 4 * plane + rp + xs);
-  const R f5 = ldv<R>(A + 5 * plane + rm + xm);
-  const R f6 = ldv<R>(A + 6 * plane + rm + xp);
-  const R f7 = ldv<R>(A + 7 * plane + rp + xp);
-  const R f8 = ldv<R>(A + 8 * plane + rp + xm);
-  const R g0 = ldv<R>(G + r0 + xs);
-  const R g1 = ldv<R>(G + plane + r0 + xm);
-  const R g2 = ldv<R>(G + 2 * plane + rm + xs);
-  const R g3 = ldv<R>(G + 3 * plane + r0 + xp);
-  const R g4 = ldv<R>(G + 4 * plane + rp + xs);
+  const R f0 = ldv<R>(at(A, r0 + xs));
+  const R f1 = ldv<R>(at(A + (size_t)plane, r0 + xm));
+  const R f2 = ldv<R>(at(A + (size_t)2 * plane, rm + xs));
+  const R f3 = ldv<R>(at(A + (size_t)3 * plane, r0 + xp));
+  const R f4 = ldv<R>(at(A + (size_t)4 * plane, rp + xs));
+  const R f5 = ldv<R>(at(A + (size_t)5 * plane, rm + xm));
+  const R f6 = ldv<R>(at(A + (size_t)6 * plane, rm + xp));
+  const R f7 = ldv<R>(at(A + (size_t)7 * plane, rp + xp));
+  const R f8 = ldv<R>(at(A + (size_t)8 * plane, rp + xm));
+  const R g0 = ldv<R>(at(G, r0 + xs));
+  const R g1 = ldv<R>(at(G + (size_t)plane, r0 + xm));
+  const R g2 = ldv<R>(at(G + (size_t)2 * plane, rm + xs));
+  const R g3 = ldv<R>(at(G + (size_t)3 * plane, r0 + xp));
+  const R g4 = ldv<R>(at(G + (size_t)4 * plane, rp + xs));
 
   // raw moments (Eq. 7 on Eq. 6), as deviations
   const R p13 = f1 + f3, m13 = f1 - f3, p24 = f2 + f4, m24 = f2 - f4;
@@ -475,16 +492,17 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
   const R g0 = st.sg - ((g1 + g3) + (g2 + g4));
 
   const R out[kPlanes] = {f0, f1, f2, f3, f4, f5, f6, f7, f8, g0, g1, g2, g3, g4};
-  typename P::F *of = const_cast<typename P::F *>(fplanes<P>(buf)) + idx;
-  typename P::G *og = const_cast<typename P::G *>(gplanes<P>(buf, plane)) + idx;
+  typename P::F *of = const_cast<typename P::F *>(fplanes<P>(buf));
+  typename P::G *og = const_cast<typename P::G *>(gplanes<P>(buf, plane));
+  const uint32_t uidx = (uint32_t)idx;
   // random words for the stochastic rounding: two 16-bit fields per word
   uint32_t w = mix32((uint32_t)idx + seed);
 #pragma unroll
   for (int i = 0; i < kPlanes; ++i) {
     if (i < 9)
-      stv(of + i * plane, out[i], (i & 1) ? (w >> 16) : w);
+      stv(at(of + (size_t)i * plane, uidx), out[i], (i & 1) ? (w >> 16) : w);
     else
-      stv(og + (i - 9) * plane, out[i], (i & 1) ? (w >> 16) : w);
+      stv(at(og + (size_t)(i - 9) * plane, uidx), out[i], (i & 1) ? (w >> 16) : w);
     if (i & 1) w = next_bits<R>(w);
   }
 }

@@ -185,3 +185,48 @@ def test_set_state_device_matches_host_warm_start(B):
     a.step(50)
     b.step(50)
     assert np.array_equal(a.get_state(), b.get_state())
+
+
+def test_batch256_workload_sampled_cavities(B):
+    """The batched bench workload (256 cavities, 64^2..512^2, drawn
+    parameters) in its launch configuration: 300 steps from the seeded
+    initial state; eight cavities, the largest and smallest among them,
+    against the oracle run by themselves."""
+    from paper_2110_05943_amd import workloads
+    cases = workloads.batch(256, seed=3)
+    s = B.Solver(cases)
+    for k, c in enumerate(cases):
+        s.set_state(k, inputs.cavity_initial_T(c["nx"], seed=1))
+    s.step(300)
+    sizes = np.array([c["nx"] for c in cases])
+    pick = [int(np.argmax(sizes)), int(np.argmin(sizes))]
+    pick += [int(k) for k in inputs.rng(77).choice(256, 6, replace=False) if k not in pick][:6]
+    ru, rT, mass, st = s.residual_all()
+    for k in pick:
+        c = cases[k]
+        if st[k] != B.OK:  # a drawn cavity at the stability edge may diverge; compare the rest
+            log("cavity %d (N=%d, Ra=%.3g) diverged on the GPU" % (k, c["nx"], c["Ra"]))
+            continue
+        lat = oracle_lattice(c)
+        lat.init_equilibrium(inputs.cavity_initial_T(c["nx"], seed=1))
+        lat.step(300)
+        check_state(s.macros(k), lat.macros(), TOL32,
+                    "batch[%d] N=%d Ra=%.3g Da=%.3g" % (k, c["nx"], c["Ra"], c["Da"]))
+    s.close()
+
+
+def test_cavity_1024_full_field(B):
+    """1024^2 cavity (Ra = 1e6, Da = 1e-4, phi = 0.4), 500 steps from the
+    seeded initial state: the whole field against the oracle."""
+    case = cavity(1024, Ra=1e6, Da=1e-4, phi=0.4)
+    T = inputs.cavity_initial_T(1024, seed=1)
+    s = B.Solver(case)
+    s.set_state(0, T)
+    s.step(500)
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(T)
+    lat.step(500)
+    g, o = s.macros(), lat.macros()
+    check_state(g, o, TOL32, "cavity 1024 500 steps")
+    assert abs(s.nusselt(0, B.WEST) - lat.nusselt(0, 1.0)) <= 1e-4
+    s.close()
