@@ -229,13 +229,137 @@ def table1_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_steady_bench(args):
+    """The 256-cavity batch run from rest to steady state with retirement
+    (clb_run): per-cavity steps to steady state, the aggregate update rate
+    over the whole run, and the final hot-wall Nusselt numbers."""
+    import numpy as np
+    from paper_2110_05943_amd import WEST, Solver, inputs, workloads
+    from paper_2110_05943_amd._binding import ERR_DIVERGED, NOT_CONVERGED, OK
+    cases = workloads.batch(count=args.count or 256, seed=3, storage=args.storage)
+    s = Solver(cases)
+    for k, c in enumerate(cases):
+        s.set_state(k, inputs.cavity_initial_T(c["nx"], seed=1))
+    sizes = np.array([c["nx"] * c["ny"] for c in cases])
+    every, chunk, cap = 5000, 100_000, 2_000_000
+    steps = np.zeros(len(cases), dtype=np.int64)
+    status = np.full(len(cases), NOT_CONVERGED)
+    t0 = time.perf_counter()
+    done = 0
+    while done < cap and np.any(status == NOT_CONVERGED):
+        r = s.run(chunk, check_every=every, tol=args.tol)
+        live = status == NOT_CONVERGED
+        steps[live] += r["steps"][live]
+        fin = live & (r["status"] != NOT_CONVERGED)
+        status[fin] = r["status"][fin]
+        done += chunk
+        print("  %d steps, %d steady, %d diverged, %.1f s" % (done, int((status == OK).sum()),
+              int((status == ERR_DIVERGED).sum()), time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    s.synchronize()
+    wall = time.perf_counter() - t0
+    s.set_active(np.ones(len(cases), dtype=np.uint8))
+    nu = s.nusselt_all(WEST)
+    ok = status == OK
+    lu = float((steps * sizes).sum())
+    by_n = {}
+    for n in sorted(set(c["nx"] for c in cases)):
+        m = ok & (np.array([c["nx"] for c in cases]) == n)
+        if m.any():
+            by_n[str(n)] = {"steady": int(m.sum()), "median_steps": float(np.median(steps[m])),
+                            "max_steps": int(steps[m].max())}
+    out = {"metric": "batched run to steady state with retirement",
+           "value": round(lu / wall / 1e6, 1), "unit": "MLUPS (aggregate over the run)",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "dtype": {"f32": "f64 arithmetic, f32 storage", "f16": "f32 arithmetic, f16 storage",
+                     "mixed": "f32 arithmetic, f16 flow / f32 temperature storage"}[args.storage],
+           "config": {"workload": "256 porous cavities (seed 3), from rest", "tol": args.tol,
+                      "check_every": every, "max_steps": cap},
+           "wall_s": round(wall, 1), "node_updates": lu, "steady": int(ok.sum()),
+           "diverged": int((status == ERR_DIVERGED).sum()),
+           "not_steady": int((status == NOT_CONVERGED).sum()), "by_size": by_n,
+           "steps": steps.tolist(), "status": status.tolist(),
+           "nu_hot": [round(float(v), 6) for v in nu]}
+    print(json.dumps(out), flush=True)
+
+
+def cavity_sweep_bench(args):
+    """Throughput of the single-cavity step over the parameter sets Ra in
+    {1e4, 1e6} x Da in {1e-2, 1e-4} x porosity in {0.4, 0.9} at 1024^2 and
+    4096^2 (Pr = J = sigma = 1)."""
+    import torch
+    from paper_2110_05943_amd import Solver, inputs, workloads
+    from paper_2110_05943_amd._binding import BYTES_PER_UPDATE
+    rows = []
+    for n in (1024, 4096):
+        for Ra in (1e4, 1e6):
+            for Da in (1e-2, 1e-4):
+                for phi in (0.4, 0.9):
+                    c = workloads.cavity(n, Ra=Ra, Da=Da, phi=phi, storage=args.storage)
+                    s = Solver(c)
+                    s.set_state(0, inputs.cavity_initial_T(n, seed=1))
+                    s.step(50)
+                    s.synchronize()
+                    K = 400 if n == 4096 else 2000
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(s.stream)
+                    s.step(K)
+                    e1.record(s.stream)
+                    e1.synchronize()
+                    us = e0.elapsed_time(e1) * 1e3 / K
+                    rows.append({"n": n, "Ra": Ra, "Da": Da, "phi": phi, "us_per_step": round(us, 2),
+                                 "MLUPS": round(n * n / us, 1),
+                                 "GBps": round(BYTES_PER_UPDATE[args.storage] * n * n / us / 1e3, 1)})
+                    s.close()
+                    print(rows[-1], file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "step throughput over parameter sets", "storage": args.storage,
+                      "rows": rows}), flush=True)
+
+
+def oracle_timing():
+    """The FP64 CPU oracle's own speed on this host: one thread and all
+    threads, 64^2 / 256^2 / 1024^2 cavities at fixed step counts."""
+    import numpy as np
+    from paper_2110_05943_amd import inputs, workloads
+    from tests.cases import oracle_lattice
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    rows = []
+    for n, steps in ((64, 5000), (256, 2000), (1024, 200)):
+        c = workloads.cavity(n, Ra=1e5, Da=1e-2, phi=0.6)
+        for threads in (1, cores):
+            k = steps if threads > 1 or n == 64 else steps // 5
+            lat = oracle_lattice(c, nthreads=threads)
+            lat.init_equilibrium(inputs.cavity_initial_T(n, seed=1))
+            t0 = time.perf_counter()
+            lat.step(k)
+            dt = time.perf_counter() - t0
+            assert np.isfinite(lat.f[:9]).all()
+            rows.append({"n": n, "steps": k, "threads": threads, "s": round(dt, 2),
+                         "MLUPS": round(n * n * k / dt / 1e6, 3)})
+            print(rows[-1], file=sys.stderr, flush=True)
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    print(json.dumps({"metric": "FP64 CPU oracle speed", "cpu": cpu, "cores": cores,
+                      "rows": rows, "paper_clb_mlups_context": 3.5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", choices=("cavity", "batch", "channel", "warmstart", "table1"),
+    ap.add_argument("--workload", choices=("cavity", "batch", "channel", "warmstart", "table1",
+                                           "batch-steady", "cavity-sweep", "oracle-timing"),
                     default="cavity")
+    ap.add_argument("--tol", type=float, default=1e-9,
+                    help="batch-steady: change per step over 5000-step rounds")
     ap.add_argument("--n", type=int, default=4096, help="grid size (cavity; channel: 2048)")
     ap.add_argument("--count", type=int, default=None,
                     help="domains of the batch (256) or warmstart (500) workload")
@@ -247,6 +371,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
+    if args.workload == "oracle-timing":
+        return oracle_timing()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -271,6 +397,10 @@ def main():
         return warmstart_bench(args)
     if args.workload == "table1":
         return table1_bench(args)
+    if args.workload == "batch-steady":
+        return batch_steady_bench(args)
+    if args.workload == "cavity-sweep":
+        return cavity_sweep_bench(args)
     from paper_2110_05943_amd import WEST, Solver
     from paper_2110_05943_amd._binding import BYTES_PER_UPDATE
 
