@@ -321,10 +321,17 @@ void orc_collide_f(const orc_params *p, const double f[9], double rho, double ux
   double m[9], mt[9], N[81], Ninv[81], L[81], eq[9], St[9], diff[9], ms[9], mr[9];
   ensure_inverses();
   matvec(9, &MMAT[0][0], f, m);
-  orc_matrix_N(ux, uy, phi, N);
-  matvec(9, N, m, mt);
-  orc_mteq(rho, eq);
-  orc_St(rho, Fx, Fy, St);
+  if (p->model == 1) {
+    /* MRT: N = I, so the moments, equilibria and forcing are the raw ones */
+    memcpy(mt, m, sizeof(mt));
+    orc_meq(rho, ux, uy, phi, eq);
+    orc_Sraw(rho, ux, uy, Fx, Fy, phi, St);
+  } else {
+    orc_matrix_N(ux, uy, phi, N);
+    matvec(9, N, m, mt);
+    orc_mteq(rho, eq);
+    orc_St(rho, Fx, Fy, St);
+  }
   orc_matrix_Lambda(p, L);
   for (int i = 0; i < 9; ++i) diff[i] = mt[i] - eq[i];
   for (int r = 0; r < 9; ++r) {
@@ -335,8 +342,12 @@ void orc_collide_f(const orc_params *p, const double f[9], double rho, double ux
     }
     ms[r] = mt[r] - relax + src;
   }
-  orc_matrix_Ninv(ux, uy, phi, Ninv);
-  matvec(9, Ninv, ms, mr);
+  if (p->model == 1) {
+    memcpy(mr, ms, sizeof(mr));
+  } else {
+    orc_matrix_Ninv(ux, uy, phi, Ninv);
+    matvec(9, Ninv, ms, mr);
+  }
   matvec(9, &MINV[0][0], mr, out);
 }
 
@@ -348,17 +359,27 @@ void orc_collide_g(const orc_params *p, const double g[5], double T, double ux,
   const double cT2 = 0.5 * p->varpi;
   ensure_inverses();
   matvec(5, &MTMAT[0][0], g, n);
-  orc_matrix_NT(ux, uy, p->sigma, N);
-  matvec(5, N, n, nt);
-  /* Eq. 32 */
-  eq[0] = p->sigma * T;
-  eq[1] = 0.0;
-  eq[2] = 0.0;
-  eq[3] = cT2 * T;
-  eq[4] = cT2 * T;
+  if (p->model == 1) {
+    /* MRT: N_T = I, raw equilibria of Eq. 33 */
+    memcpy(nt, n, sizeof(nt));
+    orc_neq(T, ux, uy, p->sigma, p->varpi, eq);
+  } else {
+    orc_matrix_NT(ux, uy, p->sigma, N);
+    matvec(5, N, n, nt);
+    /* Eq. 32 */
+    eq[0] = p->sigma * T;
+    eq[1] = 0.0;
+    eq[2] = 0.0;
+    eq[3] = cT2 * T;
+    eq[4] = cT2 * T;
+  }
   for (int i = 0; i < 5; ++i) ns[i] = nt[i] - q[i] * (nt[i] - eq[i]);
-  orc_matrix_NTinv(ux, uy, p->sigma, Ninv);
-  matvec(5, Ninv, ns, nr);
+  if (p->model == 1) {
+    memcpy(nr, ns, sizeof(nr));
+  } else {
+    orc_matrix_NTinv(ux, uy, p->sigma, Ninv);
+    matvec(5, Ninv, ns, nr);
+  }
   matvec(5, &MTINV[0][0], nr, out);
 }
 

@@ -46,6 +46,12 @@ typedef struct {
   const double *K;         /* permeability per node (INFINITY: no Darcy drag)         */
   const double *Fphi;      /* Forchheimer coefficient per node                        */
   int32_t nthreads;        /* OpenMP threads, <= 0: runtime default                   */
+  int32_t model;           /* 0: cascaded (shift matrices N, N_T of Eqs. 14, 31);
+                              1: raw-moment MRT, N = N_T = I (end of Section 2 and
+                              Table 2): relax M f toward the raw equilibria and
+                              forcing moments of Eq. 19, M_T g toward Eq. 33.
+                              The single-rate (BGK) case is model 1 with equal
+                              rates, chosen by the caller.                          */
 } orc_params;
 
 #ifdef __cplusplus

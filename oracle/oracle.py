@@ -64,7 +64,7 @@ class _Params(C.Structure):
         ("gb", C.c_double * 2), ("a", C.c_double * 2),
         ("accel", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double)),
         ("K", C.POINTER(C.c_double)), ("Fphi", C.POINTER(C.c_double)),
-        ("nthreads", C.c_int32),
+        ("nthreads", C.c_int32), ("model", C.c_int32),
     ]
 
 
@@ -139,7 +139,7 @@ class Lattice:
                  bc_T=(0, 0, 0, 0), inlet_U=0.0, nu, s_v, s_b=1.5, s0=1.0, s1=1.0, s3=1.2,
                  s4=1.8, za, zT=1.0, ze=1.0, zn=1.0, varpi=0.25, sigma=1.0, T0=0.5,
                  gb=(0.0, 0.0), a=(0.0, 0.0), accel=None, phi=1.0, K=math.inf, Fphi=0.0,
-                 nthreads=0):
+                 nthreads=0, model=0):
         self.nx, self.ny = int(nx), int(ny)
         n = self.nx * self.ny
 
@@ -170,6 +170,7 @@ class Lattice:
         p.accel = _ptr(self.accel)
         p.phi, p.K, p.Fphi = _ptr(self.phi), _ptr(self.K), _ptr(self.Fphi)
         p.nthreads = nthreads
+        p.model = {"clb": 0, "mrt": 1, "bgk": 1}.get(model, model)
         self.p = p
         self.f = _vec(9 * n)
         self.g = _vec(5 * n)

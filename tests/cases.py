@@ -51,14 +51,17 @@ def oracle_values(case):
         Fp = c.get("F_phi", 0.0)
         Fphi = op.ergun_F(phi) if Fp < 0 else Fp
         phi_f = phi
+    model = c.get("model", "clb")
+    rates = dict(s_b=c.get("s_b") or 1.5, s1=c.get("s1") or 1.0, s3=c.get("s3") or 1.2,
+                 s4=c.get("s4") or 1.8, ze=c.get("zeta_e") or 1.0, zn=c.get("zeta_nu") or 1.0)
+    if model == "bgk":  # single relaxation time: every rate equals s_v (D2Q9), zeta_a (D2Q5)
+        rates = dict(s_b=s_v, s1=s_v, s3=s_v, s4=s_v, ze=za, zn=za)
     return dict(
-        bc=c.get("bc", CAVITY_BC), bc_u=c.get("bc_u", (0, 0, 0, 0)),
+        model=model, bc=c.get("bc", CAVITY_BC), bc_u=c.get("bc_u", (0, 0, 0, 0)),
         bc_v=c.get("bc_v", (0, 0, 0, 0)), bc_T=c.get("bc_T", (0, 0, 0, 0)),
-        inlet_U=c.get("inlet_U", 0.0), nu=nu, s_v=s_v, s_b=c.get("s_b") or 1.5,
-        s1=c.get("s1") or 1.0, s3=c.get("s3") or 1.2, s4=c.get("s4") or 1.8, za=za,
-        ze=c.get("zeta_e") or 1.0, zn=c.get("zeta_nu") or 1.0, varpi=varpi, sigma=sigma,
+        inlet_U=c.get("inlet_U", 0.0), nu=nu, s_v=s_v, za=za, varpi=varpi, sigma=sigma,
         T0=c.get("T0", 0.5), gb=(-gdir[0] * gbeta, -gdir[1] * gbeta), a=c.get("a", (0.0, 0.0)),
-        phi=phi_f, K=K, Fphi=Fphi)
+        phi=phi_f, K=K, Fphi=Fphi, **rates)
 
 
 def oracle_lattice(case, nthreads=0):
