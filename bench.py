@@ -317,6 +317,65 @@ def cavity_sweep_bench(args):
                       "rows": rows}), flush=True)
 
 
+def models_bench(args):
+    """The cascaded method against its MRT (N = N_T = I) and single-rate
+    (BGK) variants on the GPU: step time on the Table 2 case (Ra = 1e7,
+    Da = 1e-4, phi = 0.6, 192^2) and on a 4096^2 grid, and how long each
+    stays finite on cavities with relaxation times close to 1/2."""
+    import numpy as np
+    import torch
+    from paper_2110_05943_amd import Solver, inputs, workloads
+    from paper_2110_05943_amd._binding import ERR_DIVERGED
+    out = {"metric": "collision models: step time and stability", "storage": args.storage,
+           "cost": [], "stability": []}
+    for n, K in ((192, 20000), (4096, 400)):
+        base = None
+        for model in ("bgk", "mrt", "clb"):
+            c = workloads.cavity(n, Ra=1e7, Da=1e-4, phi=0.6, model=model, storage=args.storage)
+            s = Solver(c)
+            s.set_state(0, inputs.cavity_initial_T(n, seed=1))
+            s.step(100)
+            s.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.step(K)
+            e1.record(s.stream)
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / K
+            base = base or us
+            out["cost"].append({"n": n, "model": model, "us_per_step": round(us, 3),
+                                "ratio_to_bgk": round(us / base, 3)})
+            print(out["cost"][-1], file=sys.stderr, flush=True)
+            s.close()
+    configs = [(256, 1e9, 1e-6, 0.6), (256, 1e8, 1e-6, 0.6), (192, 1e7, 1e-4, 0.6),
+               (128, 1e8, 1e-2, 0.9), (128, 1e9, 1e-4, 0.9)]
+    steps, every = 1_000_000, 5000
+    for model in ("clb", "mrt", "bgk"):
+        cases = [workloads.cavity(n, Ra=Ra, Da=Da, phi=phi, model=model, storage=args.storage)
+                 for n, Ra, Da, phi in configs]
+        s = Solver(cases)
+        for k, c in enumerate(cases):
+            s.set_state(k, inputs.cavity_initial_T(c["nx"], seed=1))
+        r = s.run(steps, check_every=every, tol=0.0)
+        for k, (n, Ra, Da, phi) in enumerate(configs):
+            tau = 1.0 / s_v_of(cases[k])
+            out["stability"].append({"model": model, "n": n, "Ra": Ra, "Da": Da, "phi": phi,
+                                     "tau_v": round(tau, 6),
+                                     "diverged_after": int(r["steps"][k])
+                                     if r["status"][k] == ERR_DIVERGED else None,
+                                     "steps": int(r["steps"][k])})
+            print(out["stability"][-1], file=sys.stderr, flush=True)
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
+def s_v_of(case):
+    from paper_2110_05943_amd import derive
+    kw = {k: v for k, v in case.items() if k != "storage"}
+    return derive(**kw)["s_v"]
+
+
 def oracle_timing():
     """The FP64 CPU oracle's own speed on this host: one thread and all
     threads, 64^2 / 256^2 / 1024^2 cavities at fixed step counts."""
@@ -356,7 +415,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", choices=("cavity", "batch", "channel", "warmstart", "table1",
-                                           "batch-steady", "cavity-sweep", "oracle-timing"),
+                                           "batch-steady", "cavity-sweep", "oracle-timing",
+                                           "models"),
                     default="cavity")
     ap.add_argument("--tol", type=float, default=1e-9,
                     help="batch-steady: change per step over 5000-step rounds")
@@ -401,6 +461,8 @@ def main():
         return batch_steady_bench(args)
     if args.workload == "cavity-sweep":
         return cavity_sweep_bench(args)
+    if args.workload == "models":
+        return models_bench(args)
     from paper_2110_05943_amd import WEST, Solver
     from paper_2110_05943_amd._binding import BYTES_PER_UPDATE
 

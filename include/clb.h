@@ -70,6 +70,18 @@ enum { CLB_WEST = 0, CLB_EAST = 1, CLB_SOUTH = 2, CLB_NORTH = 3 };
  *                    FP32 arithmetic. */
 enum { CLB_STORE_F32 = 0, CLB_STORE_F16 = 1, CLB_STORE_MIXED = 2 };
 
+/* Collision operator of a domain.
+ *   CLB_MODEL_CASCADED: the paper's method, moments shifted by N(u, phi) and
+ *                       N_T(u, sigma) (Eqs. 11-17, 28-33);
+ *   CLB_MODEL_MRT:      the same with N = N_T = I, i.e. relaxation of the raw
+ *                       moments toward the raw equilibria and forcing of
+ *                       Eq. 19 and Eq. 33 (the MRT method of Section 2 and
+ *                       Table 2);
+ *   CLB_MODEL_BGK:      CLB_MODEL_MRT with every D2Q9 rate equal to s_v and
+ *                       every D2Q5 rate equal to zeta_alpha (single relaxation
+ *                       time; rate overrides are ignored). */
+enum { CLB_MODEL_CASCADED = 0, CLB_MODEL_MRT = 1, CLB_MODEL_BGK = 2 };
+
 /* How the lattice parameters follow from the dimensionless groups. */
 enum {
   CLB_SCALE_CAVITY = 0,   /* relaxation rates of Eq. 46, u_c = Ma c_s (Section 3.2) */
@@ -116,6 +128,8 @@ typedef struct clb_params {
 
   double T_init;             /* initial uniform temperature; default T0              */
   int32_t storage;           /* CLB_STORE_*; must agree over all domains of a context */
+  int32_t model;             /* CLB_MODEL_*: collision operator; default cascaded;
+                                must agree over all domains of a context         */
 } clb_params;
 
 /* Lattice quantities derived from a clb_params (all lattice units). */
@@ -188,7 +202,7 @@ clb_status clb_residual_all(clb_ctx *ctx, double *res_u, double *res_T, double *
 
 /* Warm start: set every node of one domain to equilibrium, f = f^eq(rho = 1, u)
  * (Eq. 19) and g = g^eq(T, u) (Eq. 34).  NULL u or v means 0; T must be given.
- * Asynchronous with respect to the host (the arrays are copied first). */
+ * The fields pass through FP32.  Synchronizes. */
 clb_status clb_set_state(clb_ctx *ctx, int32_t cavity, const double *u, const double *v,
                          const double *T);
 

@@ -21,6 +21,7 @@ SCALE_CAVITY, SCALE_CHANNEL = 0, 1
 KIND = {"periodic": PERIODIC, "wall_T": WALL_T, "wall_adiabatic": WALL_ADIABATIC,
         "inlet": INLET, "outlet": OUTLET}
 STORAGE = {"f32": STORE_F32, "f16": STORE_F16, "mixed": STORE_MIXED}
+MODEL = {"clb": 0, "mrt": 1, "bgk": 2}
 # bytes moved per node update (14 populations read and written)
 BYTES_PER_UPDATE = {"f32": 112, "f16": 56, "mixed": 76}
 
@@ -50,7 +51,7 @@ class Params(C.Structure):
         ("nu", C.c_double), ("s_v", C.c_double), ("s_b", C.c_double), ("s1", C.c_double),
         ("s3", C.c_double), ("s4", C.c_double), ("zeta_a", C.c_double), ("zeta_e", C.c_double),
         ("zeta_nu", C.c_double), ("varpi", C.c_double), ("gbeta", C.c_double),
-        ("T_init", C.c_double), ("storage", C.c_int32),
+        ("T_init", C.c_double), ("storage", C.c_int32), ("model", C.c_int32),
     ]
 
 
@@ -151,6 +152,8 @@ def make_params(**kw):
                 p.eps = _dptr(arr)
         elif k == "storage":
             p.storage = STORAGE[v] if isinstance(v, str) else int(v)
+        elif k == "model":
+            p.model = MODEL[v] if isinstance(v, str) else int(v)
         elif k == "scaling":
             p.scaling = {"cavity": SCALE_CAVITY, "channel": SCALE_CHANNEL}.get(v, v)
         else:

@@ -105,6 +105,7 @@ extern "C" clb_status clb_derive(const clb_params *pp, clb_derived *out) {
   if ((p.bc[2] == CLB_PERIODIC) != (p.bc[3] == CLB_PERIODIC)) return CLB_ERR_ARG;
   if (walled_x(p) && p.nx < 4) return CLB_ERR_ARG;
   if (walled_y(p) && p.ny < 4) return CLB_ERR_ARG;
+  if (p.model < CLB_MODEL_CASCADED || p.model > CLB_MODEL_BGK) return CLB_ERR_ARG;
   if (p.storage != CLB_STORE_F32 && p.storage != CLB_STORE_F16 && p.storage != CLB_STORE_MIXED)
     return CLB_ERR_ARG;
   if (p.scaling != CLB_SCALE_CAVITY && p.scaling != CLB_SCALE_CHANNEL) return CLB_ERR_ARG;
@@ -161,6 +162,10 @@ extern "C" clb_status clb_derive(const clb_params *pp, clb_derived *out) {
   d.s4 = p.s4 > 0 ? p.s4 : 1.8;
   d.zeta_e = p.zeta_e > 0 ? p.zeta_e : 1.0;
   d.zeta_nu = p.zeta_nu > 0 ? p.zeta_nu : 1.0;
+  if (p.model == CLB_MODEL_BGK) {  // single relaxation time
+    d.s_b = d.s1 = d.s3 = d.s4 = d.s_v;
+    d.zeta_e = d.zeta_nu = d.zeta_a;
+  }
   if (!rate_ok(d.s_v) || !rate_ok(d.s_b) || !rate_ok(d.s1) || !rate_ok(d.s3) || !rate_ok(d.s4) ||
       !rate_ok(d.zeta_a) || !rate_ok(d.zeta_e) || !rate_ok(d.zeta_nu))
     return CLB_ERR_ARG;
@@ -251,6 +256,7 @@ extern "C" clb_status clb_workspace_bytes(const clb_params *p, int32_t count, si
 struct clb_ctx {
   int count = 0;
   int storage = 0;
+  int raw = 0;  // raw-moment (MRT / BGK) collision
   std::vector<clb_params> p;
   std::vector<clb_derived> der;
   std::vector<CavDesc> desc;
@@ -432,7 +438,7 @@ int grid_tiles(const clb_ctx *c) {
 
 clb_status launch_one(clb_ctx *c, int write_snap, hipStream_t s) {
   const hipError_t e = clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c),
-                                        c->parity, write_snap, c->storage, c->shape, s);
+                                        c->parity, write_snap, c->storage, c->raw, c->shape, s);
   if (e != hipSuccess) return hip_fail(e, "step kernel launch");
   return CLB_OK;
 }
@@ -443,7 +449,7 @@ clb_status capture_graph(clb_ctx *c, int p0) {
   hipError_t err = hipSuccess;
   for (int k = 0; k < kGraphSteps && err == hipSuccess; ++k)
     err = clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c), (p0 + k) & 1,
-                           0, c->storage, c->shape, c->cap_stream);
+                           0, c->storage, c->raw, c->shape, c->cap_stream);
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (err != hipSuccess) return hip_fail(err, "graph capture launch");
   if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
@@ -465,7 +471,7 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   for (int k = 0; k < count; ++k) {
     const clb_status s = clb_derive(&p[k], &der[k]);
     if (s != CLB_OK) return s;
-    if (p[k].storage != p[0].storage) return CLB_ERR_ARG;
+    if (p[k].storage != p[0].storage || p[k].model != p[0].model) return CLB_ERR_ARG;
   }
   Layout lay = make_layout(p, count);
   if (!d_workspace || bytes < lay.total || ((uintptr_t)d_workspace % kAlign) != 0)
@@ -474,6 +480,7 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   clb_ctx *c = new clb_ctx();
   c->count = count;
   c->storage = p[0].storage;
+  c->raw = p[0].model != CLB_MODEL_CASCADED;
   c->p.assign(p, p + count);
   for (auto &q : c->p) q.eps = nullptr;  // host arrays are not kept
   c->der = der;

@@ -79,8 +79,9 @@ struct LaunchShape {
 };
 
 // Kernel launchers (clb_kernels.hip).  All return hipSuccess or the launch error.
+// raw != 0: the raw-moment (MRT) collision instead of the cascaded one.
 hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
-                       int32_t grid_tiles, int parity, int write_snap, int storage,
+                       int32_t grid_tiles, int parity, int write_snap, int storage, int raw,
                        LaunchShape shape, hipStream_t s);
 hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int parity,
                        const float *uvth /* 3 dense planes or null */, float th_uniform,

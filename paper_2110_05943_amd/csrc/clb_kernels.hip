@@ -395,9 +395,10 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restr
   return wall;
 }
 
-// Collide one node in central-moment space and store the post-collision
-// deviations to the planes of B at element offset idx.
-template <typename P, typename R = typename P::R>
+// Collide one node in central-moment space (RAW: in raw-moment space, the
+// MRT form with N = N_T = I) and store the post-collision deviations to the
+// planes of B at element offset idx.
+template <typename P, bool RAW, typename R = typename P::R>
 __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<R> &st, bool wall,
                                               char *__restrict__ buf, int idx, uint32_t seed) {
   const int plane = d.plane;
@@ -412,50 +413,79 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
   const R rFx = rho * (st.phi * Gx - drag * ux);
   const R rFy = rho * (st.phi * Gy - drag * uy);
 
-  // central moments m~ = N m (Eq. 14), as deviations from their rest values
-  const R c1 = jx - ux * rho;
-  const R c2 = jy - uy * rho;
-  const R c3 = st.k20 + ip * ux * (ux * rho - two * jx);
-  const R c4 = st.k02 + ip * uy * (uy * rho - two * jy);
-  const R c5 = st.k11 + ip * (uxy * rho - uy * jx - ux * jy);
-  const R K20 = third + st.k20, K02 = third + st.k02;
-  const R c6 = st.k21 - uy * K20 - two * ux * st.k11 + ip * ux * (two * uy * jx + ux * jy - uxy * rho);
-  const R c7 = st.k12 - ux * K02 - two * uy * st.k11 + ip * uy * (uy * jx + two * ux * jy - uxy * rho);
-  const R c8 = st.k22 +
-               ip * (uy2 * K20 + ux2 * K02 + R(4) * uxy * st.k11 - two * uy * st.k21 -
-                     two * ux * st.k12) +
-               ip * ip * uxy * (uxy * rho - two * uy * jx - two * ux * jy);
+  // post-collision raw moments (deviations from their rest values)
+  R K10, K01, Q20, Q02, Q11, Q21, Q12, Q22;
+  if constexpr (!RAW) {
+    // central moments m~ = N m (Eq. 14), as deviations from their rest values
+    const R c1 = jx - ux * rho;
+    const R c2 = jy - uy * rho;
+    const R c3 = st.k20 + ip * ux * (ux * rho - two * jx);
+    const R c4 = st.k02 + ip * uy * (uy * rho - two * jy);
+    const R c5 = st.k11 + ip * (uxy * rho - uy * jx - ux * jy);
+    const R K20 = third + st.k20, K02 = third + st.k02;
+    const R c6 = st.k21 - uy * K20 - two * ux * st.k11 + ip * ux * (two * uy * jx + ux * jy - uxy * rho);
+    const R c7 = st.k12 - ux * K02 - two * uy * st.k11 + ip * uy * (uy * jx + two * ux * jy - uxy * rho);
+    const R c8 = st.k22 +
+                 ip * (uy2 * K20 + ux2 * K02 + R(4) * uxy * st.k11 - two * uy * st.k21 -
+                       two * ux * st.k12) +
+                 ip * ip * uxy * (uxy * rho - two * uy * jx - two * ux * jy);
 
-  // relaxation with consistent forcing (Eqs. 11, 15-17)
-  const R e3 = c3 - dr * third, e4 = c4 - dr * third;
-  const R sp = (R)d.sp, sm = (R)d.sm, s3c = (R)d.s3c, s3f = (R)d.s3f, s1c = (R)d.s1c,
-          s1f = (R)d.s1f;
-  const R c1s = s1c * c1 + s1f * rFx;
-  const R c2s = s1c * c2 + s1f * rFy;
-  const R c3s = c3 - sp * e3 - sm * e4;
-  const R c4s = c4 - sm * e3 - sp * e4;
-  const R c5s = (R)d.svc * c5;
-  const R c6s = s3c * c6 + s3f * rFy;
-  const R c7s = s3c * c7 + s3f * rFx;
-  const R c8s = c8 - (R)d.s4 * (c8 - dr * (R(1) / R(9)));
+    // relaxation with consistent forcing (Eqs. 11, 15-17)
+    const R e3 = c3 - dr * third, e4 = c4 - dr * third;
+    const R sp = (R)d.sp, sm = (R)d.sm, s3c = (R)d.s3c, s3f = (R)d.s3f, s1c = (R)d.s1c,
+            s1f = (R)d.s1f;
+    const R c1s = s1c * c1 + s1f * rFx;
+    const R c2s = s1c * c2 + s1f * rFy;
+    const R c3s = c3 - sp * e3 - sm * e4;
+    const R c4s = c4 - sm * e3 - sp * e4;
+    const R c5s = (R)d.svc * c5;
+    const R c6s = s3c * c6 + s3f * rFy;
+    const R c7s = s3c * c7 + s3f * rFx;
+    const R c8s = c8 - (R)d.s4 * (c8 - dr * (R(1) / R(9)));
 
-  // back to raw moments with N^-1 (Eq. A1).  The first moments are
-  // rho u + c~*_10.  At a fluid node Eq. 21 makes this j + rho F exactly for
-  // any s1; that form is used there because rebuilding it from the rounded u
-  // would inject a momentum error every step.
-  const R K10 = wall ? ux * rho + c1s : jx + rFx;
-  const R K01 = wall ? uy * rho + c2s : jy + rFy;
-  const R Q20 = ip * ux * (ux * rho + two * c1s) + c3s;
-  const R Q02 = ip * uy * (uy * rho + two * c2s) + c4s;
-  const R Q11 = ip * (uxy * rho + uy * c1s + ux * c2s) + c5s;
-  const R Q21 = ip * ux * (uxy * rho + two * uy * c1s + ux * c2s) + uy * (third + c3s) +
-                two * ux * c5s + c6s;
-  const R Q12 = ip * uy * (uxy * rho + uy * c1s + two * ux * c2s) + ux * (third + c4s) +
-                two * uy * c5s + c7s;
-  const R Q22 = ip * ip * uxy * (uxy * rho + two * uy * c1s + two * ux * c2s) +
-                ip * (uy2 * (third + c3s) + ux2 * (third + c4s) + R(4) * uxy * c5s +
-                      two * uy * c6s + two * ux * c7s) +
-                c8s;
+    // back to raw moments with N^-1 (Eq. A1).  The first moments are
+    // rho u + c~*_10.  At a fluid node Eq. 21 makes this j + rho F exactly for
+    // any s1; that form is used there because rebuilding it from the rounded u
+    // would inject a momentum error every step.
+    K10 = wall ? ux * rho + c1s : jx + rFx;
+    K01 = wall ? uy * rho + c2s : jy + rFy;
+    Q20 = ip * ux * (ux * rho + two * c1s) + c3s;
+    Q02 = ip * uy * (uy * rho + two * c2s) + c4s;
+    Q11 = ip * (uxy * rho + uy * c1s + ux * c2s) + c5s;
+    Q21 = ip * ux * (uxy * rho + two * uy * c1s + ux * c2s) + uy * (third + c3s) +
+                  two * ux * c5s + c6s;
+    Q12 = ip * uy * (uxy * rho + uy * c1s + two * ux * c2s) + ux * (third + c4s) +
+                  two * uy * c5s + c7s;
+    Q22 = ip * ip * uxy * (uxy * rho + two * uy * c1s + two * ux * c2s) +
+                  ip * (uy2 * (third + c3s) + ux2 * (third + c4s) + R(4) * uxy * c5s +
+                        two * uy * c6s + two * ux * c7s) +
+                  c8s;
+
+  } else {
+    // MRT (N = N_T = I): raw moments relax toward the raw equilibria of
+    // Eq. 19 with the raw forcing moments of Eq. 19.  The first moments are
+    // the same expressions as in the cascaded branch.
+    R me[9];
+    meq_dev(dr, ux, uy, ip, me);
+    const R s1c = (R)d.s1c, s1f = (R)d.s1f;
+    const R S3 = two * ux * rFx * ip, S4 = two * uy * rFy * ip;
+    const R S5 = (ux * rFy + uy * rFx) * ip;
+    const R S6 = rFy * third + (rFy * ux2 + two * rFx * uxy) * ip;
+    const R S7 = rFx * third + (rFx * uy2 + two * rFy * uxy) * ip;
+    const R S8 = two * third * (ux * rFx + uy * rFy) * ip +
+                 two * ip * ip * uxy * (rFx * uy + rFy * ux);
+    K10 = wall ? me[1] + s1c * (jx - me[1]) + s1f * rFx : jx + rFx;
+    K01 = wall ? me[2] + s1c * (jy - me[2]) + s1f * rFy : jy + rFy;
+    const R sp = (R)d.sp, sm = (R)d.sm;
+    const R e3 = st.k20 - me[3], e4 = st.k02 - me[4];
+    Q20 = st.k20 - sp * e3 - sm * e4 + S3 - half * (sp * S3 + sm * S4);
+    Q02 = st.k02 - sm * e3 - sp * e4 + S4 - half * (sm * S3 + sp * S4);
+    const R svc = (R)d.svc, s3c = (R)d.s3c, s3h = R(3) * (R)d.s3f, s4 = (R)d.s4;
+    Q11 = me[5] + svc * (st.k11 - me[5]) + half * (R(1) + svc) * S5;
+    Q21 = me[6] + s3c * (st.k21 - me[6]) + s3h * S6;
+    Q12 = me[7] + s3c * (st.k12 - me[7]) + s3h * S7;
+    Q22 = me[8] + (R(1) - s4) * (st.k22 - me[8]) + (R(1) - half * s4) * S8;
+  }
 
   // populations f* = M^-1 m* (deviations; M^-1 maps the rest moments to w_i)
   const R h20 = half * (Q20 - Q22), h02 = half * (Q02 - Q22);
@@ -478,10 +508,16 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
   const R zac = (R)d.zac;
   const R q1 = zac * (st.n1 - ux * T);
   const R q2 = zac * (st.n2 - uy * T);
-  const R e3t = (R)d.zec * (ux2 * T - two * ux * st.n1 + st.n3 - hvth);
-  const R e4t = (R)d.znc * (uy2 * T - two * uy * st.n2 + st.n4 - hvth);
-  const R ax_ = ux2 * T + q1 * two * ux + e3t + hvth;
-  const R ay_ = uy2 * T + q2 * two * uy + e4t + hvth;
+  R ax_, ay_;  // post-collision raw moments g1 + g3, g2 + g4 (deviations)
+  if constexpr (!RAW) {
+    const R e3t = (R)d.zec * (ux2 * T - two * ux * st.n1 + st.n3 - hvth);
+    const R e4t = (R)d.znc * (uy2 * T - two * uy * st.n2 + st.n4 - hvth);
+    ax_ = ux2 * T + q1 * two * ux + e3t + hvth;
+    ay_ = uy2 * T + q2 * two * uy + e4t + hvth;
+  } else {  // MRT: toward the raw equilibria of Eq. 33
+    ax_ = ux2 * T + hvth + (R)d.zec * (st.n3 - hvth - ux2 * T);
+    ay_ = uy2 * T + hvth + (R)d.znc * (st.n4 - hvth - uy2 * T);
+  }
   const R bx_ = ux * T + q1, by_ = uy * T + q2;
   const R g1 = half * (ax_ + bx_);
   const R g3 = half * (ax_ - bx_);
@@ -514,7 +550,7 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
 // the collision for the residual.  counts[2 + parity] holds the index of this
 // step; the kernel passes it on in counts[3 - parity] for the next launch, so
 // captured graphs need no baked-in step numbers.
-template <typename P>
+template <typename P, bool RAW>
 __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ descs,
                                                    const Tile *__restrict__ tiles,
                                                    int32_t *__restrict__ counts, int parity,
@@ -538,7 +574,7 @@ __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ d
       const bool wall = node_state<P>(d, A, x, y, st);
       const int idx = y * d.pitch + x;
       const uint32_t seed = mix32(step * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
-      collide_store<P>(d, st, wall, B, idx, seed);
+      collide_store<P, RAW>(d, st, wall, B, idx, seed);
       if (write_snap) {
         d.snap[idx] = (float)st.ux;
         d.snap[d.plane + idx] = (float)st.uy;
@@ -835,14 +871,18 @@ static void dispatch(int storage, Fn &&f) {
 }
 
 hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
-                       int32_t grid_tiles, int parity, int write_snap, int storage,
+                       int32_t grid_tiles, int parity, int write_snap, int storage, int raw,
                        LaunchShape shape, hipStream_t s) {
   if (grid_tiles <= 0) return hipSuccess;
   const int blocks = shape.blocks > 0 && shape.blocks < grid_tiles ? shape.blocks : grid_tiles;
   dispatch(storage, [&](auto p) {
     using P = decltype(p);
-    hipLaunchKernelGGL(step_kernel<P>, dim3(blocks), block_of(shape), 0, s, descs, tiles, counts,
-                       parity, write_snap);
+    if (raw)
+      hipLaunchKernelGGL((step_kernel<P, true>), dim3(blocks), block_of(shape), 0, s, descs,
+                         tiles, counts, parity, write_snap);
+    else
+      hipLaunchKernelGGL((step_kernel<P, false>), dim3(blocks), block_of(shape), 0, s, descs,
+                         tiles, counts, parity, write_snap);
   });
   return hipGetLastError();
 }

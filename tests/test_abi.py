@@ -130,3 +130,13 @@ def test_network_calls_validate_arguments_on_the_host():
     assert lib.clb_nn_conv3x3_wgrad(a16, a16, 2, 16, 16, 16, 32, a16, None, a16, n.value - 4,
                                     None) == B.ERR_ARG  # workspace too small
     assert lib.clb_set_state_device(None, 0, a16, 16, 1.0, 0.0) == B.ERR_ARG
+
+
+def test_bgk_derivation_uses_one_rate_per_lattice():
+    d = B.derive(nx=64, ny=64, Ra=1e4, Pr=0.71, Da=1e-2, phi=0.6, model="bgk")
+    assert d["s_b"] == d["s1"] == d["s3"] == d["s4"] == d["s_v"]
+    assert d["zeta_e"] == d["zeta_nu"] == d["zeta_a"]
+    m = B.derive(nx=64, ny=64, Ra=1e4, Pr=0.71, Da=1e-2, phi=0.6, model="mrt")
+    assert (m["s_b"], m["s3"], m["s4"]) == (1.5, 1.2, 1.8)
+    with pytest.raises(B.CLBError):
+        B.derive(nx=64, ny=64, Ra=1e4, Pr=0.71, model=3)
