@@ -185,12 +185,17 @@ def table1_bench(args):
             v = [float(x) for x in line.split()]
             for phi, nu in zip((0.4, 0.6, 0.9), v[2:]):
                 ref.append((v[0], v[1], phi, nu))
+    if args.da is not None:
+        ref = [r for r in ref if abs(r[0] / args.da - 1) < 1e-9]
     cases = [workloads.cavity(grid[Da], Ra=Ra, Da=Da, phi=phi, Pr=1.0, storage=args.storage)
              for Da, Ra, phi, _ in ref]
     s = Solver(cases)
     for k, c in enumerate(cases):
-        s.set_state(k, inputs.cavity_initial_T(c["nx"], seed=1))
-    every, chunk, cap, tol = 5000, 500_000, 10_000_000, 1e-9
+        T = inputs.cavity_initial_T(c["nx"], seed=1)
+        if args.init == "conduction":  # linear profile between the hot and cold walls
+            T = T - 0.5 + (1.0 - np.arange(c["nx"]) / (c["nx"] - 1))[None, :]
+        s.set_state(k, T)
+    every, chunk, cap, tol = 5000, 500_000, args.max_steps, 1e-9
     steps = np.zeros(len(cases), dtype=np.int64)
     status = np.full(len(cases), NOT_CONVERGED)
     nu_last = np.full(len(cases), np.nan)
@@ -222,8 +227,8 @@ def table1_bench(args):
            "value": round(float(np.median(dev)), 3) if dev.size else None,
            "unit": "% (median |deviation| over steady cases)", "higher_is_better": False,
            "n_gpus": 1, "data": "synthetic", "dtype": "f64 arithmetic, %s storage" % args.storage,
-           "config": {"workload": "27 porous cavities of Table 1 in one context", "tol": tol,
-                      "check_every": every, "max_steps": cap},
+           "config": {"workload": "%d porous cavities of Table 1 in one context" % len(cases),
+                      "tol": tol, "check_every": every, "max_steps": cap, "init": args.init},
            "wall_s": round(wall, 1), "steady": int((status == OK).sum()),
            "max_abs_dev_pct": round(float(dev.max()), 3) if dev.size else None, "rows": rows}
     print(json.dumps(out), flush=True)
@@ -420,6 +425,10 @@ def main():
                     default="cavity")
     ap.add_argument("--tol", type=float, default=1e-9,
                     help="batch-steady: change per step over 5000-step rounds")
+    ap.add_argument("--da", type=float, default=None, help="table1: only the rows of this Da")
+    ap.add_argument("--init", choices=("rest", "conduction"), default="rest",
+                    help="table1: start from rest or from the conduction profile")
+    ap.add_argument("--max-steps", type=int, default=10_000_000, help="table1: step limit")
     ap.add_argument("--n", type=int, default=4096, help="grid size (cavity; channel: 2048)")
     ap.add_argument("--count", type=int, default=None,
                     help="domains of the batch (256) or warmstart (500) workload")
