@@ -1,23 +1,27 @@
-"""Throughput benchmark of the coupled porous cascaded LB step on one MI355X.
+"""Benchmarks of the coupled porous cascaded LB step on one MI355X.
 
-Default workload: natural convection in a square porous cavity, 4096 x 4096
-nodes, Ra = 1e6, Da = 1e-4, porosity 0.4, Pr = 1, J = sigma = 1, Ergun
-F_phi, FP32 deviation storage (--storage f16 / mixed for the narrow modes).
-Other workloads: --workload batch (256 cavities of 64^2..512^2 with drawn
-parameters, one context) and --workload channel (2048^2 mixed-convection
-channel with a random porosity map, inlet and outlet).
+Default (the headline line): natural convection in a square porous cavity,
+4096 x 4096 nodes, Ra = 1e6, Da = 1e-4, porosity 0.4, Pr = 1, J = sigma = 1,
+Ergun F_phi, FP32 deviation storage (--storage f16 / mixed for the narrow
+modes).  One "step" is one time step of the whole path for every domain:
+pull streaming + macroscopic values + boundary reconstruction + D2Q9 and
+D2Q5 collisions + store, with the FP64 residual, mass and Nusselt reductions
+every 100 steps (their cost is inside the timed region).  Populations are
+resident in HBM before timing starts.  Prints one JSON line with a
+`roofline` object (the step kernel against HBM: algorithmic bytes per node
+update are the 14 populations read and written, 112 B FP32, 56 B FP16, 76 B
+mixed, plus 4 B for a porosity field) and a `cpu_baseline` (the FP64 CPU
+oracle on a bounded sample of the same workload on the host cores).
 
-One "step" is one time step of the whole path for every domain: pull
-streaming + macroscopic values + boundary reconstruction + D2Q9 and D2Q5
-collisions + store, with the FP64 residual, mass and Nusselt reductions every
-100 steps (their cost is inside the timed region).  Populations are resident
-in HBM before timing starts.
-
-Prints one JSON line.  The `roofline` object prices the step kernel against
-HBM: algorithmic bytes per node update are the 14 populations read and
-written (112 B FP32, 56 B FP16, 76 B mixed) plus 4 B for a porosity field.
-`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
-workload on the host cores.
+Other workloads (--workload):
+  batch          256 cavities of 64^2..512^2 with drawn parameters, one context
+  channel        2048^2 mixed-convection channel with a porosity map
+  batch-steady   the batch run to steady state with retirement
+  cavity-sweep   step throughput over Ra x Da x porosity at 1024^2 and 4096^2
+  table1         the 27 cavities of Table 1 run to steady state
+  models         cascaded vs MRT vs BGK collisions: step time and stability
+  warmstart      time to steady state from rest vs from the trained network
+  oracle-timing  the CPU oracle's own speed (1 thread, all threads)
 """
 import argparse
 import hashlib
