@@ -74,7 +74,7 @@ def main(argv=None):
     log("drew %d cavities (%.1f s)" % (len(draws), time.perf_counter() - t0))
     batch = W.Batch(draws)
     batch.start_from_rest()
-    wall = batch.run(args.tol, check_every=args.check, max_steps=args.max_steps, chunk=100_000,
+    wall = batch.run(args.tol, check_every=args.check, max_steps=args.max_steps, chunk=20_000,
                      log=log, record_nu=False)
     n_lu = int(batch.steps.sum()) * 128 * 128
     log("steady states: %.1f s, %d node updates (%.0f MLUPS), steps median %d max %d, "
