@@ -20,6 +20,9 @@ Other workloads (--workload):
   cavity-sweep   step throughput over Ra x Da x porosity at 1024^2 and 4096^2
   table1         the 27 cavities of Table 1 run to steady state
   models         cascaded vs MRT vs BGK collisions: step time and stability
+  paper-channel  the channel of Section 3.1 against its closed form: the N_y
+                 study, the Re family and the low-viscosity runs of Fig. 4
+  sigma          hot-wall Nusselt number against time for several sigma (Fig. 7)
   warmstart      time to steady state from rest vs from the trained network
   oracle-timing  the CPU oracle's own speed (1 thread, all threads)
 """
@@ -131,13 +134,14 @@ def warmstart_bench(args):
     from paper_2110_05943_amd import inputs
     from paper_2110_05943_amd import warmstart as W
     from paper_2110_05943_amd.train_warmstart import load_weights
-    if not os.path.exists(WEIGHTS):
+    weights = args.weights or WEIGHTS
+    if not os.path.exists(weights):
         print("no trained weights at %s (python -m paper_2110_05943_amd.train_warmstart)"
-              % WEIGHTS, file=sys.stderr)
+              % weights, file=sys.stderr)
         sys.exit(2)
     count = args.count or 500
     sur = W.Surrogate(n=128)
-    meta = load_weights(WEIGHTS, sur.net)
+    meta = load_weights(weights, sur.net)
     draws = inputs.warmstart_draws(count, seed=1)
 
     def log(*a):
@@ -161,6 +165,7 @@ def warmstart_bench(args):
                                    "learned": float(np.median(sw[ok]))},
         "median_per_case_speedup": float(np.median(sp[ok] / sw[ok])) if ok.any() else None,
         "cases_compared": int(ok.sum()),
+        "fallback_to_rest": {"count": r["fallback"], "fraction": r["fallback"] / count},
         "wall_s": {"plain": round(r["wall_plain"], 2),
                    "learned": round(r["wall_warm"] + r["inference_s"], 2),
                    "inference": round(r["inference_s"], 3)},
@@ -379,6 +384,147 @@ def models_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def _channel_start(s, k, c):
+    import numpy as np
+    ny, nx, u1 = c["ny"], c["nx"], c["bc_v"][2]
+    s.set_state(k, np.full((ny, nx), 0.5), np.zeros((ny, nx)), np.full((ny, nx), u1))
+
+
+def _channel_errors(m, c):
+    """Global relative errors of Eq. 45 against Eqs. 43-44 (u as a vector)."""
+    import numpy as np
+    from paper_2110_05943_amd import workloads
+    ux_a, uy_a, T_a = workloads.paper_channel_exact(c)
+    ux, uy, T = m["ux"][:, 0], m["uy"][:, 0], m["T"][:, 0]
+    eu = np.sqrt(np.sum((ux - ux_a) ** 2 + (uy - uy_a) ** 2) / np.sum(ux_a ** 2 + uy_a ** 2))
+    eT = np.sqrt(np.sum((T - T_a) ** 2) / np.sum(T_a ** 2))
+    return float(eu), float(eT)
+
+
+def paper_channel_bench(args):
+    """The mixed-convection channel of Section 3.1 (periodic in x, injection
+    through both plates, the y-acceleration of Eq. 42 per row) against its
+    closed form, Eqs. 43-44:
+      - the N_y study (s_v = 1, Re = 5, N_y = 17 .. 97 in one context);
+      - the Re family on 32 x 32 with u0 = u1 = 0.01 (Fig. 2);
+      - the low-viscosity runs of Fig. 4 (nu = 5e-4 and 1e-4, Re = 5,
+        32 x 32) with the cascaded, MRT and BGK collisions, run until the
+        change per step is <= 1e-10 or --max-steps."""
+    import numpy as np
+    from paper_2110_05943_amd import Solver, workloads
+    from paper_2110_05943_amd._binding import ERR_DIVERGED, NOT_CONVERGED, OK
+    out = {"metric": "Section 3.1 channel: global errors against Eqs. 43-44",
+           "storage": args.storage, "ny_study": [], "re_family": [], "low_viscosity": []}
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    ns = (17, 25, 33, 49, 65, 97)
+    cases = [workloads.paper_channel(n, s_v=1.0, Re=5.0, storage=args.storage) for n in ns]
+    s = Solver(cases)
+    for k, c in enumerate(cases):
+        _channel_start(s, k, c)
+    t0 = time.perf_counter()
+    s.step(150_000)
+    s.synchronize()
+    log("N_y study: 150000 steps, %.1f s" % (time.perf_counter() - t0))
+    for k, c in enumerate(cases):
+        eu, eT = _channel_errors(s.macros(k), c)
+        out["ny_study"].append({"ny": c["ny"], "E_u": eu, "E_T": eT})
+        log(out["ny_study"][-1])
+    s.close()
+    fit = lambda key: float(-np.polyfit(np.log(ns), np.log([r[key] for r in out["ny_study"]]), 1)[0])
+    out["slope_u"], out["slope_T"] = round(fit("E_u"), 3), round(fit("E_T"), 3)
+    out["slope_paper"] = {"u": 2.032, "T": 1.996}
+
+    res = (1.0, 5.0, 10.0, 20.0)
+    cases = [workloads.paper_channel(32, nx=32, Re=Re, storage=args.storage) for Re in res]
+    s = Solver(cases)
+    for k, c in enumerate(cases):
+        _channel_start(s, k, c)
+    s.step(300_000)
+    for k, c in enumerate(cases):
+        eu, eT = _channel_errors(s.macros(k), c)
+        out["re_family"].append({"Re": c["Re"], "tau_v": round(1.0 / s_v_of(c), 5), "E_u": eu,
+                                 "E_T": eT})
+        log(out["re_family"][-1])
+    s.close()
+
+    taus = (0.5015, 0.5003)  # nu = 5e-4, 1e-4
+    chunk = 2_000_000
+    for model in ("clb", "mrt", "bgk"):
+        cases = [workloads.paper_channel(32, nx=32, s_v=1.0 / t, Re=5.0, model=model,
+                                         storage=args.storage) for t in taus]
+        s = Solver(cases)
+        for k, c in enumerate(cases):
+            _channel_start(s, k, c)
+        status = np.full(len(cases), NOT_CONVERGED)
+        steps = np.zeros(len(cases), dtype=np.int64)
+        done, t0 = 0, time.perf_counter()
+        while done < args.max_steps and np.any(status == NOT_CONVERGED):
+            r = s.run(min(chunk, args.max_steps - done), check_every=20_000, tol=1e-10)
+            live = status == NOT_CONVERGED
+            steps[live] += r["steps"][live]
+            fin = live & (r["status"] != NOT_CONVERGED)
+            status[fin] = r["status"][fin]
+            done += chunk
+            log("  %s: %d steps, %.1f s" % (model, done, time.perf_counter() - t0))
+        for k, c in enumerate(cases):
+            row = {"model": model, "tau_v": taus[k], "nu": round((taus[k] - 0.5) / 3, 7),
+                   "status": {OK: "steady", ERR_DIVERGED: "diverged",
+                              NOT_CONVERGED: "not steady"}.get(int(status[k]), "?"),
+                   "steps": int(steps[k])}
+            if status[k] != ERR_DIVERGED:
+                row["E_u"], row["E_T"] = _channel_errors(s.macros(k), c)
+            out["low_viscosity"].append(row)
+            log(row)
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
+def sigma_bench(args):
+    """Fig. 7: the hot-wall mean Nusselt number against time for several
+    heat-capacity ratios sigma; Ra = 1e5, Da = 1e-2, phi = 0.6, Pr = 1 on the
+    128^2 grid that Section 3.2 uses for Da = 1e-2, from rest, one context,
+    2e6 steps (over 4 times the longest settling time), Nu recorded every 1000
+    steps.  At steady state sigma drops out of the energy equation, so the
+    final Nusselt numbers should agree; a smaller sigma should settle sooner."""
+    import numpy as np
+    from paper_2110_05943_amd import WEST, Solver, inputs, workloads
+    sigmas = (0.5, 1.0, 2.0, 4.0)
+    every, cap = 1000, 2_000_000
+    cases = [workloads.cavity(128, Ra=1e5, Da=1e-2, phi=0.6, Pr=1.0, sigma=sg,
+                              storage=args.storage) for sg in sigmas]
+    s = Solver(cases)
+    for k in range(len(cases)):
+        s.set_state(k, inputs.cavity_initial_T(128, seed=1))
+    t0 = time.perf_counter()
+    r = s.run(cap, check_every=every, tol=0.0, nu_side=WEST, max_records=cap // every)
+    wall = time.perf_counter() - t0
+    ru, rT, _, _ = s.residual_all()
+    rows = []
+    for k, sg in enumerate(sigmas):
+        rec = r["nu"][k]
+        rec = rec[np.isfinite(rec)]
+        nu_inf = float(rec[-1])
+        off = np.abs(rec - nu_inf)
+        bad = np.nonzero(off > 1e-4)[0]
+        settle = int((bad[-1] + 2) * every) if bad.size else every
+        bad3 = np.nonzero(off > 1e-3 * nu_inf)[0]
+        resp = int((bad3[-1] + 2) * every) if bad3.size else every
+        rows.append({"sigma": sg, "nu_final": round(nu_inf, 7), "steps": int(r["steps"][k]),
+                     "final_change_per_step": {"u": float(ru[k]), "T": float(rT[k])},
+                     "steps_to_nu_within_1e-4": settle, "steps_to_nu_within_0.1pct": resp,
+                     "nu_history": [round(float(v), 5) for v in rec[: 400: 10]]})
+        print({k2: v for k2, v in rows[-1].items() if k2 != "nu_history"}, file=sys.stderr,
+              flush=True)
+    nus = [r_["nu_final"] for r_ in rows]
+    print(json.dumps({"metric": "Fig. 7: hot-wall Nusselt number history against sigma",
+                      "paper_steady_nu": 3.4429, "spread_final_nu": round(max(nus) - min(nus), 7),
+                      "wall_s": round(wall, 1), "history_every_steps": every * 10,
+                      "rows": rows}), flush=True)
+
+
 def s_v_of(case):
     from paper_2110_05943_amd import derive
     kw = {k: v for k, v in case.items() if k != "storage"}
@@ -425,18 +571,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", choices=("cavity", "batch", "channel", "warmstart", "table1",
                                            "batch-steady", "cavity-sweep", "oracle-timing",
-                                           "models"),
+                                           "models", "paper-channel", "sigma"),
                     default="cavity")
     ap.add_argument("--tol", type=float, default=1e-9,
                     help="batch-steady: change per step over 5000-step rounds")
     ap.add_argument("--da", type=float, default=None, help="table1: only the rows of this Da")
     ap.add_argument("--init", choices=("rest", "conduction"), default="rest",
                     help="table1: start from rest or from the conduction profile")
-    ap.add_argument("--max-steps", type=int, default=10_000_000, help="table1: step limit")
+    ap.add_argument("--max-steps", type=int, default=10_000_000,
+                    help="table1, paper-channel (low viscosity): step limit")
     ap.add_argument("--n", type=int, default=4096, help="grid size (cavity; channel: 2048)")
     ap.add_argument("--count", type=int, default=None,
                     help="domains of the batch (256) or warmstart (500) workload")
     ap.add_argument("--storage", choices=("f32", "f16", "mixed"), default="f32")
+    ap.add_argument("--weights", default=None, help="warmstart: network weights (.npz)")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time launch shapes first")
@@ -474,6 +622,10 @@ def main():
         return batch_steady_bench(args)
     if args.workload == "cavity-sweep":
         return cavity_sweep_bench(args)
+    if args.workload == "paper-channel":
+        return paper_channel_bench(args)
+    if args.workload == "sigma":
+        return sigma_bench(args)
     if args.workload == "models":
         return models_bench(args)
     from paper_2110_05943_amd import WEST, Solver

@@ -130,6 +130,10 @@ typedef struct clb_params {
   int32_t storage;           /* CLB_STORE_*; must agree over all domains of a context */
   int32_t model;             /* CLB_MODEL_*: collision operator; default cascaded;
                                 must agree over all domains of a context         */
+  const double *a_rows;      /* optional acceleration per row (host, 2*ny values:
+                                a_x, a_y of row y), added to a[] at every node of the
+                                row; e.g. the y-dependent a_y of Eq. 42.  Copied
+                                during clb_create; NULL for none                     */
 } clb_params;
 
 /* Lattice quantities derived from a clb_params (all lattice units). */
@@ -159,7 +163,8 @@ clb_status clb_workspace_bytes(const clb_params *p, int32_t count, size_t *bytes
 
 /* Create a context for `count` domains described by p[0..count-1] on the
  * caller's device workspace (256-byte aligned, >= clb_workspace_bytes) and
- * stream.  Host arrays referenced by p (eps) are copied during the call.
+ * stream.  Host arrays referenced by p (eps, a_rows) are copied during the
+ * call; a non-finite a_rows entry or eps outside (0, 1) is CLB_ERR_ARG.
  * All domains start at rest with T = T_init at every node.
  * Errors: CLB_ERR_ARG, CLB_ERR_WORKSPACE, CLB_ERR_HIP. */
 clb_status clb_create(const clb_params *p, int32_t count, void *d_workspace, size_t bytes,

@@ -52,6 +52,7 @@ class Params(C.Structure):
         ("s3", C.c_double), ("s4", C.c_double), ("zeta_a", C.c_double), ("zeta_e", C.c_double),
         ("zeta_nu", C.c_double), ("varpi", C.c_double), ("gbeta", C.c_double),
         ("T_init", C.c_double), ("storage", C.c_int32), ("model", C.c_int32),
+        ("a_rows", C.POINTER(C.c_double)),
     ]
 
 
@@ -129,8 +130,9 @@ def _dptr(a):
 def make_params(**kw):
     """A Params struct: library defaults, then the given fields.
 
-    bc may be given as kind names; eps as an (ny, nx) array; storage as
-    "f32"/"f16"; two-element fields as sequences."""
+    bc may be given as kind names; eps as an (ny, nx) array; a_rows as an
+    (ny, 2) array of (a_x, a_y) per row; storage as "f32"/"f16"; two-element
+    fields as sequences."""
     p = Params()
     _lib().clb_params_default(C.byref(p))
     keep = []
@@ -143,13 +145,13 @@ def make_params(**kw):
                 getattr(p, k)[s] = float(v[s])
         elif k in ("g_dir", "a"):
             getattr(p, k)[0], getattr(p, k)[1] = float(v[0]), float(v[1])
-        elif k == "eps":
+        elif k in ("eps", "a_rows"):
             if v is None:
-                p.eps = None
+                setattr(p, k, None)
             else:
                 arr = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
                 keep.append(arr)
-                p.eps = _dptr(arr)
+                setattr(p, k, _dptr(arr))
         elif k == "storage":
             p.storage = STORAGE[v] if isinstance(v, str) else int(v)
         elif k == "model":

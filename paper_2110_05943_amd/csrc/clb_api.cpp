@@ -186,7 +186,7 @@ namespace {
 struct Layout {
   size_t desc, tiles_all, tiles_active, counts, partials, gpart, results, nu, nu_local, nu_part,
       obs;
-  std::vector<size_t> A, B, eps, snap;
+  std::vector<size_t> A, B, eps, arow, snap;
   size_t total;
   size_t max_tiles, obs_elems, max_wall;
   int32_t max_chunks;
@@ -231,6 +231,7 @@ Layout make_layout(const clb_params *p, int count) {
     L.A.push_back(take(pop));
     L.B.push_back(take(pop));
     L.eps.push_back(p[c].eps ? take(plane * sizeof(float)) : 0);
+    L.arow.push_back(p[c].a_rows ? take(2 * (size_t)p[c].ny * sizeof(double)) : 0);
     L.snap.push_back(take(3 * plane * sizeof(float)));
   }
   L.total = off;
@@ -256,7 +257,8 @@ extern "C" clb_status clb_workspace_bytes(const clb_params *p, int32_t count, si
 struct clb_ctx {
   int count = 0;
   int storage = 0;
-  int raw = 0;  // raw-moment (MRT / BGK) collision
+  int raw = 0;   // raw-moment (MRT / BGK) collision
+  int rows = 0;  // some domain has a per-row acceleration
   std::vector<clb_params> p;
   std::vector<clb_derived> der;
   std::vector<CavDesc> desc;
@@ -437,8 +439,9 @@ int grid_tiles(const clb_ctx *c) {
 }
 
 clb_status launch_one(clb_ctx *c, int write_snap, hipStream_t s) {
-  const hipError_t e = clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c),
-                                        c->parity, write_snap, c->storage, c->raw, c->shape, s);
+  const hipError_t e =
+      clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c), c->parity,
+                       write_snap, c->storage, c->raw, c->rows, c->shape, s);
   if (e != hipSuccess) return hip_fail(e, "step kernel launch");
   return CLB_OK;
 }
@@ -449,7 +452,7 @@ clb_status capture_graph(clb_ctx *c, int p0) {
   hipError_t err = hipSuccess;
   for (int k = 0; k < kGraphSteps && err == hipSuccess; ++k)
     err = clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c), (p0 + k) & 1,
-                           0, c->storage, c->raw, c->shape, c->cap_stream);
+                           0, c->storage, c->raw, c->rows, c->shape, c->cap_stream);
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (err != hipSuccess) return hip_fail(err, "graph capture launch");
   if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
@@ -472,6 +475,9 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
     const clb_status s = clb_derive(&p[k], &der[k]);
     if (s != CLB_OK) return s;
     if (p[k].storage != p[0].storage || p[k].model != p[0].model) return CLB_ERR_ARG;
+    if (p[k].a_rows)
+      for (size_t i = 0; i < 2 * (size_t)p[k].ny; ++i)
+        if (!std::isfinite(p[k].a_rows[i])) return CLB_ERR_ARG;
   }
   Layout lay = make_layout(p, count);
   if (!d_workspace || bytes < lay.total || ((uintptr_t)d_workspace % kAlign) != 0)
@@ -482,7 +488,11 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->storage = p[0].storage;
   c->raw = p[0].model != CLB_MODEL_CASCADED;
   c->p.assign(p, p + count);
-  for (auto &q : c->p) q.eps = nullptr;  // host arrays are not kept
+  for (auto &q : c->p) {  // host arrays are not kept
+    c->rows |= q.a_rows != nullptr;
+    q.eps = nullptr;
+    q.a_rows = nullptr;
+  }
   c->der = der;
   c->lay = lay;
   c->ws = static_cast<char *>(d_workspace);
@@ -504,6 +514,8 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
     c->desc[k].A = c->ws + lay.A[k];
     c->desc[k].B = c->ws + lay.B[k];
     c->desc[k].eps = p[k].eps ? reinterpret_cast<const float *>(c->ws + lay.eps[k]) : nullptr;
+    c->desc[k].arow =
+        p[k].a_rows ? reinterpret_cast<const double *>(c->ws + lay.arow[k]) : nullptr;
     c->desc[k].snap = reinterpret_cast<float *>(c->ws + lay.snap[k]);
   }
   c->active.assign(count, 1);
@@ -535,6 +547,15 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
                                   hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(hip_fail(e, "eps upload"));
+  }
+  // per-row accelerations (FP64, 2 values per row)
+  for (int k = 0; k < count; ++k) {
+    if (!p[k].a_rows) continue;
+    const size_t n = 2 * (size_t)p[k].ny;
+    hipError_t e = hipMemcpyAsync(c->ws + lay.arow[k], p[k].a_rows, n * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(hip_fail(e, "a_rows upload"));
   }
   build_tiles(c);
   {

@@ -37,6 +37,7 @@ struct alignas(16) CavDesc {
   char *A;                        // population planes, 14 planes (9 f, 5 g)
   char *B;                        // second buffer (A/B double buffering)
   const float *eps;               // porosity plane (pitch layout) or null
+  const double *arow;             // (a_x, a_y) per row, added to (ax, ay), or null
   float *snap;                    // u, v, theta planes for the residual (pitch layout)
 
   // Constants in FP64; kernels that compute in FP32 round them once.
@@ -80,9 +81,10 @@ struct LaunchShape {
 
 // Kernel launchers (clb_kernels.hip).  All return hipSuccess or the launch error.
 // raw != 0: the raw-moment (MRT) collision instead of the cascaded one.
+// rows != 0: some domain carries a per-row acceleration (CavDesc::arow).
 hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
                        int32_t grid_tiles, int parity, int write_snap, int storage, int raw,
-                       LaunchShape shape, hipStream_t s);
+                       int rows, LaunchShape shape, hipStream_t s);
 hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int parity,
                        const float *uvth /* 3 dense planes or null */, float th_uniform,
                        int storage, hipStream_t s);

@@ -169,6 +169,7 @@ struct NodeState {
   R th;                 // theta = T - T0
   R rho, ux, uy, umag;
   R phi, ip, cd, cf;    // medium at this node
+  R gax, gay;           // external acceleration at this node (per-row variant only)
 };
 
 // Deviation of the equilibrium raw moments of Eq. 19 from their rest values,
@@ -211,10 +212,24 @@ __device__ __forceinline__ void medium_at(const CavDesc &d, int idx, R &phi, R &
   }
 }
 
+// External acceleration a of row y; ROWS adds the domain's per-row profile
+// when it has one.
+template <bool ROWS, typename R>
+__device__ __forceinline__ void accel_at(const CavDesc &d, int y, R &ax, R &ay) {
+  ax = (R)d.ax;
+  ay = (R)d.ay;
+  if constexpr (ROWS) {
+    if (d.arow) {
+      ax = (R)(d.ax + d.arow[2 * y]);
+      ay = (R)(d.ay + d.arow[2 * y + 1]);
+    }
+  }
+}
+
 // Pull the post-streaming populations of node (xs, ys) and reduce them to
 // moments and macroscopic values.  (xs, ys) must have all 8 neighbours inside
 // the domain or across a periodic side.
-template <typename P, typename R = typename P::R>
+template <typename P, bool ROWS, typename R = typename P::R>
 __device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__restrict__ buf,
                                                int xs, int ys, NodeState<R> &st) {
   const int nx = d.nx, ny = d.ny, pitch = d.pitch, plane = d.plane;
@@ -270,7 +285,13 @@ __device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__r
   // Eqs. 20-23: rho, the temporal velocity v and the explicit velocity u.
   st.rho = R(1) + st.dr;
   const R irho = rcp64(st.rho);
-  const R Gx = (R)d.gbx * st.th + (R)d.ax, Gy = (R)d.gby * st.th + (R)d.ay;
+  R gax, gay;
+  accel_at<ROWS>(d, ys, gax, gay);
+  if constexpr (ROWS) {
+    st.gax = gax;
+    st.gay = gay;
+  }
+  const R Gx = (R)d.gbx * st.th + gax, Gy = (R)d.gby * st.th + gay;
   const R hphi = R(0.5) * st.phi;
   const R vx = st.jx * irho + hphi * Gx;
   const R vy = st.jy * irho + hphi * Gy;
@@ -311,7 +332,7 @@ __device__ __forceinline__ R gather_theta(const CavDesc &d, const char *__restri
 // phi_f), which is M applied to f_i^eq(b) + [f_i(x_f) - f_i^eq(x_f)], and
 // likewise for the D2Q5 moments with Eq. 33.  The node then collides with
 // (rho_b, u_b, T_b).  Returns true for boundary nodes.
-template <typename P, typename R = typename P::R>
+template <typename P, bool ROWS, typename R = typename P::R>
 __device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restrict__ A, int x,
                                            int y, NodeState<R> &st) {
   int sx = -1, sy = -1, dx = 0, dy = 0;
@@ -330,7 +351,7 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restr
     dy = -1;
   }
   const bool wall = (sx >= 0) || (sy >= 0);
-  gather_moments<P>(d, A, x + dx, y + dy, st);
+  gather_moments<P, ROWS>(d, A, x + dx, y + dy, st);
   if (wall) {
     const R drf = st.dr, uxf = st.ux, uyf = st.uy, thf = st.th, ipf = st.ip;
     const bool corner = (sx >= 0) && (sy >= 0);
@@ -365,8 +386,9 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restr
       uby = uyf;
       thb = thf;
     }
-    // the boundary node's own medium
+    // the boundary node's own medium and acceleration
     medium_at(d, y * d.pitch + x, st.phi, st.ip, st.cd, st.cf);
+    if constexpr (ROWS) accel_at<ROWS>(d, y, st.gax, st.gay);
     R mb[9], mf[9];
     meq_dev(drb, ubx, uby, st.ip, mb);
     meq_dev(drf, uxf, uyf, ipf, mf);
@@ -398,7 +420,7 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restr
 // Collide one node in central-moment space (RAW: in raw-moment space, the
 // MRT form with N = N_T = I) and store the post-collision deviations to the
 // planes of B at element offset idx.
-template <typename P, bool RAW, typename R = typename P::R>
+template <typename P, bool RAW, bool ROWS, typename R = typename P::R>
 __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<R> &st, bool wall,
                                               char *__restrict__ buf, int idx, uint32_t seed) {
   const int plane = d.plane;
@@ -408,7 +430,12 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
   const R third = R(1) / R(3), two = R(2), half = R(0.5), quarter = R(0.25);
 
   // force of Eq. 4 with G = gb theta + a
-  const R Gx = (R)d.gbx * st.th + (R)d.ax, Gy = (R)d.gby * st.th + (R)d.ay;
+  R gax = (R)d.ax, gay = (R)d.ay;
+  if constexpr (ROWS) {
+    gax = st.gax;
+    gay = st.gay;
+  }
+  const R Gx = (R)d.gbx * st.th + gax, Gy = (R)d.gby * st.th + gay;
   const R drag = st.cd + st.cf * st.umag;
   const R rFx = rho * (st.phi * Gx - drag * ux);
   const R rFy = rho * (st.phi * Gy - drag * uy);
@@ -550,7 +577,7 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
 // the collision for the residual.  counts[2 + parity] holds the index of this
 // step; the kernel passes it on in counts[3 - parity] for the next launch, so
 // captured graphs need no baked-in step numbers.
-template <typename P, bool RAW>
+template <typename P, bool RAW, bool ROWS>
 __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ descs,
                                                    const Tile *__restrict__ tiles,
                                                    int32_t *__restrict__ counts, int parity,
@@ -571,10 +598,10 @@ __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ d
       const char *A = parity ? d.B : d.A;
       char *B = parity ? d.A : d.B;
       NodeState<R> st;
-      const bool wall = node_state<P>(d, A, x, y, st);
+      const bool wall = node_state<P, ROWS>(d, A, x, y, st);
       const int idx = y * d.pitch + x;
       const uint32_t seed = mix32(step * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
-      collide_store<P, RAW>(d, st, wall, B, idx, seed);
+      collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed);
       if (write_snap) {
         d.snap[idx] = (float)st.ux;
         d.snap[d.plane + idx] = (float)st.uy;
@@ -712,7 +739,7 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
   if (x < d.nx && y < d.ny) {
     const char *A = parity ? d.B : d.A;
     NodeState<R> st;
-    node_state<P>(d, A, x, y, st);
+    node_state<P, true>(d, A, x, y, st);
     const int idx = y * d.pitch + x;
     // the snapshot holds FP32 values: compare like with like
     const double ux = (double)(float)st.ux, uy = (double)(float)st.uy, th = (double)(float)st.th;
@@ -787,7 +814,7 @@ __global__ void __launch_bounds__(512) macros_kernel(const CavDesc *__restrict__
   if (x >= d.nx || y >= d.ny) return;
   const char *A = parity ? d.B : d.A;
   NodeState<R> st;
-  node_state<P>(d, A, x, y, st);
+  node_state<P, true>(d, A, x, y, st);
   const int n = d.nx * d.ny, k = y * d.nx + x;
   out[k] = (float)st.dr;
   out[n + k] = (float)st.ux;
@@ -828,7 +855,7 @@ __global__ void __launch_bounds__(256) nusselt_kernel(const CavDesc *__restrict_
         y = side == 2 ? k : d.ny - 1 - k;
       }
       NodeState<R> st;
-      node_state<P>(d, A, x, y, st);
+      node_state<P, true>(d, A, x, y, st);
       t[k] = (double)st.th;  // the gradient does not depend on the reference T0
     }
     const double nu = -L * sign * (-3.0 * t[0] + 4.0 * t[1] - t[2]) * 0.5 / d.dT;
@@ -872,17 +899,24 @@ static void dispatch(int storage, Fn &&f) {
 
 hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
                        int32_t grid_tiles, int parity, int write_snap, int storage, int raw,
-                       LaunchShape shape, hipStream_t s) {
+                       int rows, LaunchShape shape, hipStream_t s) {
   if (grid_tiles <= 0) return hipSuccess;
   const int blocks = shape.blocks > 0 && shape.blocks < grid_tiles ? shape.blocks : grid_tiles;
+  const dim3 grid(blocks), block = block_of(shape);
   dispatch(storage, [&](auto p) {
     using P = decltype(p);
-    if (raw)
-      hipLaunchKernelGGL((step_kernel<P, true>), dim3(blocks), block_of(shape), 0, s, descs,
-                         tiles, counts, parity, write_snap);
+    if (raw && rows)
+      hipLaunchKernelGGL((step_kernel<P, true, true>), grid, block, 0, s, descs, tiles, counts,
+                         parity, write_snap);
+    else if (raw)
+      hipLaunchKernelGGL((step_kernel<P, true, false>), grid, block, 0, s, descs, tiles, counts,
+                         parity, write_snap);
+    else if (rows)
+      hipLaunchKernelGGL((step_kernel<P, false, true>), grid, block, 0, s, descs, tiles, counts,
+                         parity, write_snap);
     else
-      hipLaunchKernelGGL((step_kernel<P, false>), dim3(blocks), block_of(shape), 0, s, descs,
-                         tiles, counts, parity, write_snap);
+      hipLaunchKernelGGL((step_kernel<P, false, false>), grid, block, 0, s, descs, tiles,
+                         counts, parity, write_snap);
   });
   return hipGetLastError();
 }

@@ -193,7 +193,8 @@ def evaluate(sur, draws, tol=1e-9, check_every=5000, max_steps=3_000_000, log=No
     prediction.  Both runs go to the same residual tolerance; the reference
     steady Nusselt number Nu_inf of each cavity is the final value of the run
     from rest.  Time to steady state = steps after which the hot-wall Nusselt
-    number stays within 1e-4 of Nu_inf."""
+    number stays within 1e-4 of Nu_inf.  A warm run that diverges is restarted
+    from rest (res["fallback"] counts them)."""
     eps = np.stack([d["eps"] for d in draws]).astype(np.float32)
     groups = np.stack([groups_of(d) for d in draws])
     res = {}
@@ -213,9 +214,26 @@ def evaluate(sur, draws, tol=1e-9, check_every=5000, max_steps=3_000_000, log=No
     if log:
         log("from the prediction (inference %.3f s):" % res["inference_s"])
     res["wall_warm"] = warm.run(tol, check_every, max_steps, log=log)
+    sw = [settle_steps(warm.nu[k], nu_inf[k], check_every) for k in range(len(draws))]
+    # A warm start that diverges falls back to a run from rest; its time to
+    # steady state counts the steps lost before the divergence.
+    fb = [k for k in range(len(draws)) if warm.status[k] == B.ERR_DIVERGED]
+    res["fallback"] = len(fb)
+    if fb:
+        if log:
+            log("fallback to rest for %d cavities" % len(fb))
+        redo = Batch([draws[k] for k in fb])
+        redo.start_from_rest()
+        res["wall_warm"] += redo.run(tol, check_every, max_steps, log=log)
+        for j, k in enumerate(fb):
+            st = settle_steps(redo.nu[j], nu_inf[k], check_every)
+            sw[k] = None if st is None else int(warm.steps[k]) + st
+            warm.steps[k] += redo.steps[j]
+            warm.status[k] = redo.status[j]
+            warm.nu[k] = redo.nu[j]
+        redo.solver.close()
     nu_w = np.array([x[-1] if x else np.nan for x in warm.nu])
     sp = [settle_steps(plain.nu[k], nu_inf[k], check_every) for k in range(len(draws))]
-    sw = [settle_steps(warm.nu[k], nu_inf[k], check_every) for k in range(len(draws))]
     err = np.sqrt(((pred - f_plain) ** 2).sum(axis=(1, 2)) / (f_plain ** 2).sum(axis=(1, 2)))
     res.update(steps_plain=plain.steps.tolist(), steps_warm=warm.steps.tolist(),
                status_plain=plain.status.tolist(), status_warm=warm.status.tolist(),

@@ -56,6 +56,9 @@ def oracle_values(case):
                  s4=c.get("s4") or 1.8, ze=c.get("zeta_e") or 1.0, zn=c.get("zeta_nu") or 1.0)
     if model == "bgk":  # single relaxation time: every rate equals s_v (D2Q9), zeta_a (D2Q5)
         rates = dict(s_b=s_v, s1=s_v, s3=s_v, s4=s_v, ze=za, zn=za)
+    if c.get("a_rows") is not None:  # per-row acceleration -> the oracle's per-node field
+        ar = np.asarray(c["a_rows"], dtype=np.float64).reshape(ny, 2)
+        rates["accel"] = np.repeat(ar[:, None, :], nx, axis=1)
     return dict(
         model=model, bc=c.get("bc", CAVITY_BC), bc_u=c.get("bc_u", (0, 0, 0, 0)),
         bc_v=c.get("bc_v", (0, 0, 0, 0)), bc_T=c.get("bc_T", (0, 0, 0, 0)),

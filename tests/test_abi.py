@@ -32,11 +32,42 @@ def test_library_exports_every_declared_symbol():
     assert set(nn_names) == set(nn.NN_EXPORTS)
 
 
-def test_struct_sizes_match_header_layout():
-    # 2 ints + 4 ints + 12 doubles + 1 + (phi, eps*, dp, Da, F) + int + 7 + 3 + 2*2 + 11 + T_init + int
-    p = B.make_params(nx=8, ny=8)
-    assert C.sizeof(p) == C.sizeof(B.Params)
-    assert B.Params.storage.offset > B.Params.T_init.offset > B.Params.gbeta.offset
+def test_struct_sizes_match_header_layout(tmp_path):
+    # The ctypes mirrors must have the C compiler's size and field offsets.
+    fields = ("nx", "bc_u", "inlet_U", "eps", "scaling", "u_ref", "a", "gbeta", "T_init",
+              "storage", "model", "a_rows")
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"clb.h\"\nint main(void) {\n"
+                   '  printf("%zu %zu\\n", sizeof(clb_params), sizeof(clb_derived));\n' +
+                   "".join('  printf("%%zu\\n", offsetof(clb_params, %s));\n' % f for f in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert int(out[0]) == C.sizeof(B.Params) and int(out[1]) == C.sizeof(B.Derived)
+    for f, off in zip(fields, out[2:]):
+        assert getattr(B.Params, f).offset == int(off), f
+
+
+def test_create_rejects_non_finite_row_acceleration():
+    lib = B._lib()
+    rows = [0.0, 1e-5] * 7 + [0.0, float("nan")]
+    p = B.make_params(nx=8, ny=8, bc=("periodic", "periodic", "wall_T", "wall_T"), Ra=1e3,
+                      Pr=1.0, a_rows=rows)
+    ctx = C.c_void_p()
+    # rejected before the workspace is looked at
+    assert lib.clb_create(C.byref(p), 1, None, 16, None, C.byref(ctx)) == B.ERR_ARG
+    p = B.make_params(nx=8, ny=8, bc=("periodic", "periodic", "wall_T", "wall_T"), Ra=1e3,
+                      Pr=1.0, a_rows=[0.0, 1e-5] * 8)
+    assert lib.clb_create(C.byref(p), 1, None, 16, None, C.byref(ctx)) == B.ERR_WORKSPACE
+    n8 = C.c_size_t(0)
+    n0 = C.c_size_t(0)
+    assert lib.clb_workspace_bytes(C.byref(p), 1, C.byref(n8)) == B.OK
+    p.a_rows = None
+    assert lib.clb_workspace_bytes(C.byref(p), 1, C.byref(n0)) == B.OK
+    assert n8.value == n0.value + 256  # 16 doubles, one aligned block
 
 
 @pytest.mark.parametrize("n,Ra,Pr,Da,phi", [(64, 1e3, 1.0, 1e-2, 0.6), (128, 1e5, 0.71, 1e-4, 0.4),
