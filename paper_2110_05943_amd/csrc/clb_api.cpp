@@ -305,44 +305,45 @@ void fill_desc(const clb_params &p, const clb_derived &d, CavDesc &k) {
   const double Ts = p.T_init;
   for (int s = 0; s < 4; ++s) {
     k.bc[s] = p.bc[s];
-    k.bc_u[s] = p.bc_u[s];
-    k.bc_v[s] = p.bc_v[s];
-    k.bc_th[s] = (p.bc_T[s] - Ts);
+    k.c.bc_u[s] = p.bc_u[s];
+    k.c.bc_v[s] = p.bc_v[s];
+    k.c.bc_th[s] = (p.bc_T[s] - Ts);
   }
-  k.inlet_U = p.inlet_U;
+  k.c.inlet_U = p.inlet_U;
   k.has_eps = p.eps != nullptr;
   const double phi = p.eps ? 1.0 : p.phi;
-  k.phi = phi;
-  k.ip = (1.0 / phi);
+  k.c.phi = phi;
+  k.c.ip = (1.0 / phi);
   const bool drag = std::isfinite(d.K);
-  k.cd = drag ? (phi * d.nu / d.K) : 0.0;
-  k.cf = drag ? (phi * d.F_phi / std::sqrt(d.K)) : 0.0;
+  k.c.cd = drag ? (phi * d.nu / d.K) : 0.0;
+  k.c.cf = drag ? (phi * d.F_phi / std::sqrt(d.K)) : 0.0;
   if (p.eps) {
-    k.kc_d = (150.0 * d.nu / (p.dp * p.dp));
-    k.kc_f = p.F_phi == 0.0 ? 0.0 : (1.75 / p.dp);
+    k.c.kc_d = (150.0 * d.nu / (p.dp * p.dp));
+    k.c.kc_f = p.F_phi == 0.0 ? 0.0 : (1.75 / p.dp);
   }
-  k.s1c = (1.0 - d.s1);
-  k.s1f = (1.0 - 0.5 * d.s1);
-  k.sp = (0.5 * (d.s_b + d.s_v));
-  k.sm = (0.5 * (d.s_b - d.s_v));
-  k.svc = (1.0 - d.s_v);
-  k.s3c = (1.0 - d.s3);
-  k.s3f = ((1.0 - 0.5 * d.s3) / 3.0);
-  k.s4 = d.s4;
-  k.zac = (1.0 - d.zeta_a);
-  k.zec = (1.0 - d.zeta_e);
-  k.znc = (1.0 - d.zeta_nu);
-  k.hv = (0.5 * d.varpi);
-  k.sig = d.sigma;
-  k.isig = (1.0 / d.sigma);
-  k.sig_mv = (d.sigma - d.varpi);
-  k.T0 = Ts;
+  k.c.s1c = (1.0 - d.s1);
+  k.c.s1f = (1.0 - 0.5 * d.s1);
+  k.c.sp = (0.5 * (d.s_b + d.s_v));
+  k.c.sm = (0.5 * (d.s_b - d.s_v));
+  k.c.svc = (1.0 - d.s_v);
+  k.c.s3c = (1.0 - d.s3);
+  k.c.s3f = ((1.0 - 0.5 * d.s3) / 3.0);
+  k.c.s4 = d.s4;
+  k.c.zac = (1.0 - d.zeta_a);
+  k.c.zec = (1.0 - d.zeta_e);
+  k.c.znc = (1.0 - d.zeta_nu);
+  k.c.hv = (0.5 * d.varpi);
+  k.c.sig = d.sigma;
+  k.c.isig = (1.0 / d.sigma);
+  k.c.sig_mv = (d.sigma - d.varpi);
+  k.c.T0 = Ts;
   const double gbx = -p.g_dir[0] * d.gbeta, gby = -p.g_dir[1] * d.gbeta;
-  k.gbx = gbx;
-  k.gby = gby;
-  k.ax = (p.a[0] + gbx * (Ts - d.T0));
-  k.ay = (p.a[1] + gby * (Ts - d.T0));
-  k.dT = d.dT;
+  k.c.gbx = gbx;
+  k.c.gby = gby;
+  k.c.ax = (p.a[0] + gbx * (Ts - d.T0));
+  k.c.ay = (p.a[1] + gby * (Ts - d.T0));
+  k.c.dT = d.dT;
+  k.c32.assign(k.c);
 }
 
 // Tile width for a row of nx nodes when the shape is chosen per domain: the

@@ -23,6 +23,46 @@ struct Tile {
   int32_t cav, x0, y0, id;
 };
 
+// Per-domain constants in the arithmetic type T of a kernel.  The scalar
+// fields are listed once (CLB_DOMAIN_SCALARS) so that the FP32 copy is made
+// field by field from the FP64 one.
+//   bc_u, bc_v, bc_th: boundary values; temperatures as theta = T - T0
+//   inlet_U:  mean velocity of an inlet side
+//   phi, ip:  uniform porosity and 1/phi (ignored with a porosity field)
+//   cd, cf:   phi nu / K and phi F_phi / sqrt(K)
+//   kc_d, kc_f: porosity field: cd = kc_d (1-eps)^2/eps^2, cf = kc_f (1-eps)/eps^2
+//             (Kozeny-Carman K and the Ergun F_phi of Eq. 5)
+//   s1c, s1f: 1 - s1, 1 - s1/2;  sp, sm: s+, s-;  svc: 1 - s_v (Eq. 15)
+//   s3c, s3f: 1 - s3, (1 - s3/2)/3;  s4
+//   zac, zec, znc: 1 - zeta_a, 1 - zeta_e, 1 - zeta_nu (Eq. 28)
+//   hv:       varpi / 2 = c_sT^2;  sig, isig, sig_mv: sigma, 1/sigma, sigma - varpi
+//   T0:       storage reference temperature
+//   gbx, gby, ax, ay: body force G = gb theta + a
+//   dT:       temperature difference of the Nusselt number
+#define CLB_DOMAIN_SCALARS(X)                                                              \
+  X(inlet_U) X(phi) X(ip) X(cd) X(cf) X(kc_d) X(kc_f) X(s1c) X(s1f) X(sp) X(sm) X(svc)   \
+  X(s3c) X(s3f) X(s4) X(zac) X(zec) X(znc) X(hv) X(sig) X(isig) X(sig_mv) X(T0) X(gbx)   \
+  X(gby) X(ax) X(ay) X(dT)
+
+template <typename T>
+struct DomainConsts {
+  T bc_u[4], bc_v[4], bc_th[4];
+#define CLB_DECLARE(n) T n;
+  CLB_DOMAIN_SCALARS(CLB_DECLARE)
+#undef CLB_DECLARE
+  template <typename U>
+  void assign(const DomainConsts<U> &o) {
+    for (int s = 0; s < 4; ++s) {
+      bc_u[s] = (T)o.bc_u[s];
+      bc_v[s] = (T)o.bc_v[s];
+      bc_th[s] = (T)o.bc_th[s];
+    }
+#define CLB_ASSIGN(n) n = (T)o.n;
+    CLB_DOMAIN_SCALARS(CLB_ASSIGN)
+#undef CLB_ASSIGN
+  }
+};
+
 // Per-domain constants and addresses read by every kernel (scalar loads).
 // Populations are stored as deviations from their rest values:
 //   df_i = f_i - w_i,   dg_i = g_i - g_i^eq(T0, u = 0),
@@ -40,33 +80,10 @@ struct alignas(16) CavDesc {
   const double *arow;             // (a_x, a_y) per row, added to (ax, ay), or null
   float *snap;                    // u, v, theta planes for the residual (pitch layout)
 
-  // Constants in FP64; kernels that compute in FP32 round them once.
-  // boundary values; temperatures as theta = T - T0
-  double bc_u[4], bc_v[4], bc_th[4];
-  double inlet_U;
-
-  // uniform medium (ignored when has_eps)
-  double phi, ip;                 // porosity and 1/phi
-  double cd, cf;                  // phi nu / K and phi F_phi / sqrt(K)
-  // eps field: cd = kc_d (1-eps)^2/eps^2, cf = kc_f (1-eps)/eps^2 (Ergun + Kozeny-Carman)
-  double kc_d, kc_f;
-
-  // D2Q9 relaxation (Eq. 15)
-  double s1c, s1f;                // 1 - s1, 1 - s1/2
-  double sp, sm;                  // s+, s-
-  double svc;                     // 1 - s_v
-  double s3c, s3f;                // 1 - s3, (1 - s3/2)/3
-  double s4;
-
-  // D2Q5 relaxation (Eq. 28); varpi; sigma
-  double zac, zec, znc;           // 1 - zeta_a, 1 - zeta_e, 1 - zeta_nu
-  double hv;                      // varpi / 2 = c_sT^2
-  double sig, isig, sig_mv;       // sigma, 1/sigma, sigma - varpi
-  double T0;
-
-  // body force G = gb * theta + a
-  double gbx, gby, ax, ay;
-  double dT;                      // temperature difference of the Nusselt number
+  // Constants of the domain: FP64, and rounded once to FP32 for the kernels
+  // that compute in FP32 (cst<R>() picks the set).
+  DomainConsts<double> c;
+  DomainConsts<float> c32;
 };
 
 // Tile shape of the node kernels.  tile_x = 0 chooses the width per domain

@@ -90,6 +90,18 @@ using StoreF32 = Store<float, float, double>;        // FP32 planes, FP64 arithm
 using StoreF16 = Store<_Float16, _Float16, float>;   // FP16 planes, FP32 arithmetic
 using StoreMix = Store<_Float16, float, float>;      // FP16 flow, FP32 temperature
 
+// The domain constants in the arithmetic type R of a kernel.
+template <typename R>
+__device__ __forceinline__ const DomainConsts<R> &cst(const CavDesc &d);
+template <>
+__device__ __forceinline__ const DomainConsts<double> &cst<double>(const CavDesc &d) {
+  return d.c;
+}
+template <>
+__device__ __forceinline__ const DomainConsts<float> &cst<float>(const CavDesc &d) {
+  return d.c32;
+}
+
 template <typename P>
 __device__ __forceinline__ const typename P::F *fplanes(const char *buf) {
   return reinterpret_cast<const typename P::F *>(buf);
@@ -130,13 +142,16 @@ __device__ __forceinline__ uint32_t next_bits(uint32_t x) {
 // fraction of the instructions of the IEEE FP64 division and square-root
 // sequences.  rcp64 is used for values of order one (rho, the porosity, the
 // velocity denominator of Eq. 23); sqrt64 takes the IEEE path for arguments below
-// 1e-30, whose FP32 image would be zero or subnormal.
+// 1e-30, whose FP32 image would be zero or subnormal.  The FP32 overloads
+// (FP16 and mixed storage, which compute in FP32) take the hardware
+// estimates directly: their error, about one FP32 unit, is of the order of
+// the FP32 arithmetic itself.
 __device__ __forceinline__ double rcp64(double x) {
   double r = (double)__builtin_amdgcn_rcpf((float)x);
   r = r * (2.0 - x * r);
   return r * (2.0 - x * r);
 }
-__device__ __forceinline__ float rcp64(float x) { return 1.0f / x; }
+__device__ __forceinline__ float rcp64(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double sqrt64(double x) {
   if (!(x > 1e-30)) return sqrt(x);
   double y = (double)__builtin_amdgcn_rsqf((float)x);
@@ -144,7 +159,18 @@ __device__ __forceinline__ double sqrt64(double x) {
   y = y * (1.5 - 0.5 * x * y * y);
   return x * y;
 }
-__device__ __forceinline__ float sqrt64(float x) { return sqrtf(x); }
+__device__ __forceinline__ float sqrt64(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// A plane base that every lane shares, held in scalar registers and opaque
+// to the optimiser: the 14 stores of a node then each take the form
+// "scalar base + the node's 32-bit offset" instead of a chain of 64-bit
+// vector additions from one base (an empty asm statement with an SGPR
+// operand; it emits no instruction).
+template <typename T>
+__device__ __forceinline__ T *uniform_base(T *p) {
+  asm("" : "+s"(p));
+  return p;
+}
 
 // Element i of a plane as a byte offset below 4 GiB from the plane base.
 template <typename T>
@@ -202,13 +228,13 @@ __device__ __forceinline__ void medium_at(const CavDesc &d, int idx, R &phi, R &
     phi = (R)d.eps[idx];
     ip = rcp64(phi);
     const R q = (R(1) - phi) * ip;
-    cd = (R)d.kc_d * q * q;
-    cf = (R)d.kc_f * q * ip;
+    cd = cst<R>(d).kc_d * q * q;
+    cf = cst<R>(d).kc_f * q * ip;
   } else {
-    phi = (R)d.phi;
-    ip = (R)d.ip;
-    cd = (R)d.cd;
-    cf = (R)d.cf;
+    phi = cst<R>(d).phi;
+    ip = cst<R>(d).ip;
+    cd = cst<R>(d).cd;
+    cf = cst<R>(d).cf;
   }
 }
 
@@ -216,12 +242,12 @@ __device__ __forceinline__ void medium_at(const CavDesc &d, int idx, R &phi, R &
 // when it has one.
 template <bool ROWS, typename R>
 __device__ __forceinline__ void accel_at(const CavDesc &d, int y, R &ax, R &ay) {
-  ax = (R)d.ax;
-  ay = (R)d.ay;
+  ax = cst<R>(d).ax;
+  ay = cst<R>(d).ay;
   if constexpr (ROWS) {
     if (d.arow) {
-      ax = (R)(d.ax + d.arow[2 * y]);
-      ay = (R)(d.ay + d.arow[2 * y + 1]);
+      ax += (R)d.arow[2 * y];
+      ay += (R)d.arow[2 * y + 1];
     }
   }
 }
@@ -279,7 +305,7 @@ __device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__r
   st.n3 = g1 + g3;
   st.n4 = g2 + g4;
   st.sg = g0 + (st.n3 + st.n4);
-  st.th = st.sg * (R)d.isig;
+  st.th = st.sg * cst<R>(d).isig;
 
   medium_at(d, r0 + xs, st.phi, st.ip, st.cd, st.cf);
   // Eqs. 20-23: rho, the temporal velocity v and the explicit velocity u.
@@ -291,7 +317,7 @@ __device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__r
     st.gax = gax;
     st.gay = gay;
   }
-  const R Gx = (R)d.gbx * st.th + gax, Gy = (R)d.gby * st.th + gay;
+  const R Gx = cst<R>(d).gbx * st.th + gax, Gy = cst<R>(d).gby * st.th + gay;
   const R hphi = R(0.5) * st.phi;
   const R vx = st.jx * irho + hphi * Gx;
   const R vy = st.jy * irho + hphi * Gy;
@@ -322,7 +348,7 @@ __device__ __forceinline__ R gather_theta(const CavDesc &d, const char *__restri
   const R s = ldv<R>(G + ys * pitch + xs) +
               ((ldv<R>(G + plane + ys * pitch + xm) + ldv<R>(G + 3 * plane + ys * pitch + xp)) +
                (ldv<R>(G + 2 * plane + ym * pitch + xs) + ldv<R>(G + 4 * plane + yp * pitch + xs)));
-  return s * (R)d.isig;
+  return s * cst<R>(d).isig;
 }
 
 // Macroscopic state of node (x, y) ready for the collision.  Boundary nodes
@@ -368,18 +394,18 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restr
     const R thx = thf + (thf - thff) * (R(1) / R(3));
     R drb = drf, ubx = R(0), uby = R(0), thb;
     if (corner) {
-      thb = dirichlet_T(d.bc[sx]) ? (R)d.bc_th[sx]
-                                  : (dirichlet_T(d.bc[sy]) ? (R)d.bc_th[sy] : thx);
+      thb = dirichlet_T(d.bc[sx]) ? cst<R>(d).bc_th[sx]
+                                  : (dirichlet_T(d.bc[sy]) ? cst<R>(d).bc_th[sy] : thx);
     } else if (kind == kWallT || kind == kWallAdiabatic) {
-      ubx = (R)d.bc_u[side];
-      uby = (R)d.bc_v[side];
-      thb = kind == kWallT ? (R)d.bc_th[side] : thx;
+      ubx = cst<R>(d).bc_u[side];
+      uby = cst<R>(d).bc_v[side];
+      thb = kind == kWallT ? cst<R>(d).bc_th[side] : thx;
     } else if (kind == kInlet) {
       const R t = side < 2 ? (R)y / (R)(d.ny - 1) : (R)x / (R)(d.nx - 1);
-      const R un = R(6) * (R)d.inlet_U * t * (R(1) - t);
+      const R un = R(6) * cst<R>(d).inlet_U * t * (R(1) - t);
       ubx = side == 0 ? un : (side == 1 ? -un : R(0));
       uby = side == 2 ? un : (side == 3 ? -un : R(0));
-      thb = (R)d.bc_th[side];
+      thb = cst<R>(d).bc_th[side];
     } else {  // outlet
       drb = R(0);
       ubx = uxf;
@@ -401,13 +427,13 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restr
     st.k21 += mb[6] - mf[6];
     st.k12 += mb[7] - mf[7];
     st.k22 += mb[8] - mf[8];
-    const R T0 = (R)d.T0, hv = (R)d.hv;
+    const R T0 = cst<R>(d).T0, hv = cst<R>(d).hv;
     const R Tb = T0 + thb, Tf = T0 + thf;
     st.n1 += ubx * Tb - uxf * Tf;
     st.n2 += uby * Tb - uyf * Tf;
     st.n3 += (hv * thb + ubx * ubx * Tb) - (hv * thf + uxf * uxf * Tf);
     st.n4 += (hv * thb + uby * uby * Tb) - (hv * thf + uyf * uyf * Tf);
-    st.sg = (R)d.sig * thb;
+    st.sg = cst<R>(d).sig * thb;
     st.th = thb;
     st.rho = R(1) + st.dr;
     st.ux = ubx;
@@ -430,12 +456,12 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
   const R third = R(1) / R(3), two = R(2), half = R(0.5), quarter = R(0.25);
 
   // force of Eq. 4 with G = gb theta + a
-  R gax = (R)d.ax, gay = (R)d.ay;
+  R gax = cst<R>(d).ax, gay = cst<R>(d).ay;
   if constexpr (ROWS) {
     gax = st.gax;
     gay = st.gay;
   }
-  const R Gx = (R)d.gbx * st.th + gax, Gy = (R)d.gby * st.th + gay;
+  const R Gx = cst<R>(d).gbx * st.th + gax, Gy = cst<R>(d).gby * st.th + gay;
   const R drag = st.cd + st.cf * st.umag;
   const R rFx = rho * (st.phi * Gx - drag * ux);
   const R rFy = rho * (st.phi * Gy - drag * uy);
@@ -459,16 +485,16 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
 
     // relaxation with consistent forcing (Eqs. 11, 15-17)
     const R e3 = c3 - dr * third, e4 = c4 - dr * third;
-    const R sp = (R)d.sp, sm = (R)d.sm, s3c = (R)d.s3c, s3f = (R)d.s3f, s1c = (R)d.s1c,
-            s1f = (R)d.s1f;
+    const R sp = cst<R>(d).sp, sm = cst<R>(d).sm, s3c = cst<R>(d).s3c, s3f = cst<R>(d).s3f, s1c = cst<R>(d).s1c,
+            s1f = cst<R>(d).s1f;
     const R c1s = s1c * c1 + s1f * rFx;
     const R c2s = s1c * c2 + s1f * rFy;
     const R c3s = c3 - sp * e3 - sm * e4;
     const R c4s = c4 - sm * e3 - sp * e4;
-    const R c5s = (R)d.svc * c5;
+    const R c5s = cst<R>(d).svc * c5;
     const R c6s = s3c * c6 + s3f * rFy;
     const R c7s = s3c * c7 + s3f * rFx;
-    const R c8s = c8 - (R)d.s4 * (c8 - dr * (R(1) / R(9)));
+    const R c8s = c8 - cst<R>(d).s4 * (c8 - dr * (R(1) / R(9)));
 
     // back to raw moments with N^-1 (Eq. A1).  The first moments are
     // rho u + c~*_10.  At a fluid node Eq. 21 makes this j + rho F exactly for
@@ -494,7 +520,7 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
     // the same expressions as in the cascaded branch.
     R me[9];
     meq_dev(dr, ux, uy, ip, me);
-    const R s1c = (R)d.s1c, s1f = (R)d.s1f;
+    const R s1c = cst<R>(d).s1c, s1f = cst<R>(d).s1f;
     const R S3 = two * ux * rFx * ip, S4 = two * uy * rFy * ip;
     const R S5 = (ux * rFy + uy * rFx) * ip;
     const R S6 = rFy * third + (rFy * ux2 + two * rFx * uxy) * ip;
@@ -503,11 +529,11 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
                  two * ip * ip * uxy * (rFx * uy + rFy * ux);
     K10 = wall ? me[1] + s1c * (jx - me[1]) + s1f * rFx : jx + rFx;
     K01 = wall ? me[2] + s1c * (jy - me[2]) + s1f * rFy : jy + rFy;
-    const R sp = (R)d.sp, sm = (R)d.sm;
+    const R sp = cst<R>(d).sp, sm = cst<R>(d).sm;
     const R e3 = st.k20 - me[3], e4 = st.k02 - me[4];
     Q20 = st.k20 - sp * e3 - sm * e4 + S3 - half * (sp * S3 + sm * S4);
     Q02 = st.k02 - sm * e3 - sp * e4 + S4 - half * (sm * S3 + sp * S4);
-    const R svc = (R)d.svc, s3c = (R)d.s3c, s3h = R(3) * (R)d.s3f, s4 = (R)d.s4;
+    const R svc = cst<R>(d).svc, s3c = cst<R>(d).s3c, s3h = R(3) * cst<R>(d).s3f, s4 = cst<R>(d).s4;
     Q11 = me[5] + svc * (st.k11 - me[5]) + half * (R(1) + svc) * S5;
     Q21 = me[6] + s3c * (st.k21 - me[6]) + s3h * S6;
     Q12 = me[7] + s3c * (st.k12 - me[7]) + s3h * S7;
@@ -530,20 +556,20 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
   const R f0 = dr - (((f1 + f3) + (f2 + f4)) + ((f5 + f6) + (f7 + f8)));
 
   // D2Q5 (Eqs. 28-33, A2) in closed form, as deviations
-  const R T = (R)d.T0 + st.th;
-  const R hvth = (R)d.hv * st.th;
-  const R zac = (R)d.zac;
+  const R T = cst<R>(d).T0 + st.th;
+  const R hvth = cst<R>(d).hv * st.th;
+  const R zac = cst<R>(d).zac;
   const R q1 = zac * (st.n1 - ux * T);
   const R q2 = zac * (st.n2 - uy * T);
   R ax_, ay_;  // post-collision raw moments g1 + g3, g2 + g4 (deviations)
   if constexpr (!RAW) {
-    const R e3t = (R)d.zec * (ux2 * T - two * ux * st.n1 + st.n3 - hvth);
-    const R e4t = (R)d.znc * (uy2 * T - two * uy * st.n2 + st.n4 - hvth);
+    const R e3t = cst<R>(d).zec * (ux2 * T - two * ux * st.n1 + st.n3 - hvth);
+    const R e4t = cst<R>(d).znc * (uy2 * T - two * uy * st.n2 + st.n4 - hvth);
     ax_ = ux2 * T + q1 * two * ux + e3t + hvth;
     ay_ = uy2 * T + q2 * two * uy + e4t + hvth;
   } else {  // MRT: toward the raw equilibria of Eq. 33
-    ax_ = ux2 * T + hvth + (R)d.zec * (st.n3 - hvth - ux2 * T);
-    ay_ = uy2 * T + hvth + (R)d.znc * (st.n4 - hvth - uy2 * T);
+    ax_ = ux2 * T + hvth + cst<R>(d).zec * (st.n3 - hvth - ux2 * T);
+    ay_ = uy2 * T + hvth + cst<R>(d).znc * (st.n4 - hvth - uy2 * T);
   }
   const R bx_ = ux * T + q1, by_ = uy * T + q2;
   const R g1 = half * (ax_ + bx_);
@@ -563,9 +589,10 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
 #pragma unroll
   for (int i = 0; i < kPlanes; ++i) {
     if (i < 9)
-      stv(at(of + (size_t)i * plane, uidx), out[i], (i & 1) ? (w >> 16) : w);
+      stv(at(uniform_base(of + (size_t)i * plane), uidx), out[i], (i & 1) ? (w >> 16) : w);
     else
-      stv(at(og + (size_t)(i - 9) * plane, uidx), out[i], (i & 1) ? (w >> 16) : w);
+      stv(at(uniform_base(og + (size_t)(i - 9) * plane), uidx), out[i],
+          (i & 1) ? (w >> 16) : w);
     if (i & 1) w = next_bits<R>(w);
   }
 }
@@ -634,13 +661,13 @@ __device__ __forceinline__ double feq_dev_dir(int i, double ux, double uy, doubl
 // g_i^eq(T, u) - g_i^eq(T0, 0) from Eq. 34.
 __device__ __forceinline__ double geq_dev_dir(const CavDesc &d, int i, double ux, double uy,
                                               double th) {
-  const double T = d.T0 + th;
+  const double T = d.c.T0 + th;
   switch (i) {
-    case 0: return d.sig_mv * th - (ux * ux + uy * uy) * T;
-    case 1: return 0.5 * d.hv * th + 0.5 * (ux + ux * ux) * T;
-    case 2: return 0.5 * d.hv * th + 0.5 * (uy + uy * uy) * T;
-    case 3: return 0.5 * d.hv * th + 0.5 * (ux * ux - ux) * T;
-    default: return 0.5 * d.hv * th + 0.5 * (uy * uy - uy) * T;
+    case 0: return d.c.sig_mv * th - (ux * ux + uy * uy) * T;
+    case 1: return 0.5 * d.c.hv * th + 0.5 * (ux + ux * ux) * T;
+    case 2: return 0.5 * d.c.hv * th + 0.5 * (uy + uy * uy) * T;
+    case 3: return 0.5 * d.c.hv * th + 0.5 * (ux * ux - ux) * T;
+    default: return 0.5 * d.c.hv * th + 0.5 * (uy * uy - uy) * T;
   }
 }
 
@@ -746,7 +773,7 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
     const double du = ux - d.snap[idx];
     const double dv = uy - d.snap[d.plane + idx];
     const double dth = th - d.snap[2 * d.plane + idx];
-    const double T = d.T0 + (double)st.th;
+    const double T = d.c.T0 + (double)st.th;
     v[0] = du * du + dv * dv;
     v[1] = (double)st.ux * (double)st.ux + (double)st.uy * (double)st.uy;
     v[2] = dth * dth;
@@ -858,7 +885,7 @@ __global__ void __launch_bounds__(256) nusselt_kernel(const CavDesc *__restrict_
       node_state<P, true>(d, A, x, y, st);
       t[k] = (double)st.th;  // the gradient does not depend on the reference T0
     }
-    const double nu = -L * sign * (-3.0 * t[0] + 4.0 * t[1] - t[2]) * 0.5 / d.dT;
+    const double nu = -L * sign * (-3.0 * t[0] + 4.0 * t[1] - t[2]) * 0.5 / d.c.dT;
     if (nu_local) nu_local[j] = nu;
     v[0] = (j == 0 || j == nw - 1) ? 0.5 * nu : nu;  // trapezoid weights
   }

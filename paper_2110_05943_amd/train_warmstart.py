@@ -1,7 +1,9 @@
 """Train the warm-start network on solver-generated steady states.
 
-  python -m paper_2110_05943_amd.train_warmstart --train 4000 --epochs 30 \
+  python -m paper_2110_05943_amd.train_warmstart --train 6000 --epochs 120 \
       --out paper_2110_05943_amd/data/warmstart_unet.npz
+
+(the command that wrote the committed weights; about 13 minutes on one MI355X)
 
 1. Draw `--train` cavities (inputs.warmstart_draws, seed 0): 128^2 nodes,
    Ra log-uniform [1e3, 1e6], mean Da log-uniform [1e-5, 1e-1], Pr in
