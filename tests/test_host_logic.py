@@ -57,3 +57,24 @@ def test_workload_parameter_sets():
     assert ch["eps"].shape == (32, 64)
     # Ri = g beta dT H / U^2 = 1
     assert math.isclose(ch["gbeta"] * 31 / ch["inlet_U"] ** 2, 1.0)
+
+
+def test_paper_channel_workload_matches_eq42_and_closed_form():
+    # a_rows against Eq. 42 with the oracle's own derivation of nu, K, alpha_e
+    # and g beta dT; the closed form meets the plate conditions of Fig. 1.
+    from oracle import params as op
+    ny, Re, u1 = 33, 5.0, 0.01
+    c = workloads.paper_channel(ny, Re=Re, u1=u1)
+    P = op.channel(ny, Re=Re, Ra=100.0, Pr=1.0, Da=0.01, phi=0.6, u_ref=u1)
+    H = ny - 1
+    y = np.arange(ny)
+    ay = P["nu"] / P["K"] * u1 - P["gbeta_dT"] * (np.exp(y * u1 / P["alpha_e"]) - 1) / (
+        math.exp(H * u1 / P["alpha_e"]) - 1)
+    assert np.allclose(c["a_rows"][:, 1], ay, rtol=1e-12, atol=0)
+    assert np.all(c["a_rows"][:, 0] == 0)
+    ux, uy, T = workloads.paper_channel_exact(c)
+    assert ux[0] == 0 and math.isclose(ux[-1], u1) and np.all(uy == u1)
+    assert T[0] == 0 and math.isclose(T[-1], 1.0)
+    # the convergence-study form: u1 follows from s_v = 1 and Re
+    c1 = workloads.paper_channel(17, s_v=1.0, Re=5.0)
+    assert math.isclose(c1["u_ref"], 5.0 * (1 / 6) / 16)
