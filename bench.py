@@ -23,6 +23,7 @@ Other workloads (--workload):
   paper-channel  the channel of Section 3.1 against its closed form: the N_y
                  study, the Re family and the low-viscosity runs of Fig. 4
   sigma          hot-wall Nusselt number against time for several sigma (Fig. 7)
+  net            the warm-start network's kernels: training step and inference
   warmstart      time to steady state from rest vs from the trained network
   oracle-timing  the CPU oracle's own speed (1 thread, all threads)
 """
@@ -525,6 +526,80 @@ def sigma_bench(args):
                       "rows": rows}), flush=True)
 
 
+def net_bench(args):
+    """The warm-start network (nn.UNet, 1.97 M parameters) on its own: a
+    training step (forward, MSE, backward, AdamW) on a batch of 32 inputs of
+    128 x 128 x 16 channels, and inference of 500 inputs, timed with HIP
+    events on the network's stream.  Algorithmic work: 2 * 9 * cin * cout
+    flops per pixel and 3x3 convolution; the backward pass repeats it for the
+    weight gradient and (except the first layer) the input gradient.  Inputs
+    and targets are seeded random tensors of the warm-start shapes."""
+    import numpy as np
+    import torch
+    from paper_2110_05943_amd import nn
+    dev = torch.device("cuda:0")
+    net = nn.UNet(device=dev, stream=torch.cuda.Stream(device=dev))
+    r = np.random.Generator(np.random.PCG64(5))
+    n = 128
+
+    def conv_flops(B):
+        fwd = dgrad = 0
+        for st in net.steps:
+            if st["op"] == "conv":
+                a = st["ins"][0]
+                f = 2 * 9 * net.ch[a] * st["out"] * B * (n >> net.lv[a]) ** 2
+                fwd += f
+                dgrad += f if a > 0 else 0
+        return fwd, dgrad
+
+    def timed(fn, reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(net.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    B = 32
+    x = torch.tensor(r.standard_normal((B, n, n, 16)), dtype=torch.bfloat16, device=dev)
+    tgt = torch.tensor(0.1 * r.standard_normal((B, n, n, 3)), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    def train_step():
+        net.forward(x, B, n, n)
+        net.backward(tgt, 3, B, n, n)
+        net.adamw(1e-4)
+
+    for _ in range(3):
+        train_step()
+    reps = max(args.steps // 40, 10)
+    ms = timed(train_step, reps)
+    fwd, dgrad = conv_flops(B)
+    train_tf = (2 * fwd + dgrad) / ms / 1e9
+    print("train: %.2f ms per step of %d, %.1f TFLOP/s" % (ms, B, train_tf), file=sys.stderr,
+          flush=True)
+    S = 500
+    xi = torch.tensor(r.standard_normal((S, n, n, 16)), dtype=torch.bfloat16, device=dev)
+    net.forward(xi, S, n, n)
+    ms_inf = timed(lambda: net.forward(xi, S, n, n), 5)
+    inf_tf = conv_flops(S)[0] / ms_inf / 1e9
+    print("inference: %.2f ms for %d, %.1f TFLOP/s" % (ms_inf, S, inf_tf), file=sys.stderr,
+          flush=True)
+    print(json.dumps({
+        "metric": "warm-start network: training samples/s and MFMA rate",
+        "value": round(B / ms * 1e3, 1), "unit": "samples/s (training, batch 32, 128x128)",
+        "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "bf16 MFMA, fp32 accumulate",
+        "config": {"workload": "U-Net 5 levels, widths 16..256, 1.97M parameters",
+                   "batch": B, "grid": [n, n], "params": net.nparams},
+        "ms_per_train_step": round(ms, 3), "inference_ms_500": round(ms_inf, 2),
+        "roofline": {"bound": "mfma", "achieved": round(train_tf, 2), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(train_tf / 2500.0, 5),
+                     "inference_achieved": round(inf_tf, 2),
+                     "flops_per_train_step": 2 * fwd + dgrad}}), flush=True)
+
+
 def s_v_of(case):
     from paper_2110_05943_amd import derive
     kw = {k: v for k, v in case.items() if k != "storage"}
@@ -571,7 +646,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", choices=("cavity", "batch", "channel", "warmstart", "table1",
                                            "batch-steady", "cavity-sweep", "oracle-timing",
-                                           "models", "paper-channel", "sigma"),
+                                           "models", "paper-channel", "sigma", "net"),
                     default="cavity")
     ap.add_argument("--tol", type=float, default=1e-9,
                     help="batch-steady: change per step over 5000-step rounds")
@@ -626,6 +701,8 @@ def main():
         return paper_channel_bench(args)
     if args.workload == "sigma":
         return sigma_bench(args)
+    if args.workload == "net":
+        return net_bench(args)
     if args.workload == "models":
         return models_bench(args)
     from paper_2110_05943_amd import WEST, Solver

@@ -51,7 +51,8 @@ clb_status clb_nn_conv3x3(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w
  *   dbias[o]       = sum_{b,i,j} dy[b,i,j,o]   (dbias may be NULL),
  * both FP32, overwritten.  The sum over pixels is split into chunks whose
  * partial sums go to `workspace` (clb_nn_wgrad_workspace_bytes) and are then
- * added in a fixed order: results are bit-reproducible. */
+ * added in a fixed order: results are bit-reproducible.  dy and x must be
+ * 16-byte aligned; cin and cout multiples of 16 (else CLB_ERR_ARG). */
 clb_status clb_nn_wgrad_workspace_bytes(int32_t batch, int32_t h, int32_t w, int32_t cin,
                                         int32_t cout, size_t *bytes);
 clb_status clb_nn_conv3x3_wgrad(const clb_bf16 *dy, const clb_bf16 *x, int32_t batch, int32_t h,

@@ -91,52 +91,89 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(
   }
 }
 
-// Weight gradient as a GEMM: rows = output channels, columns = k = t*cin + c,
-// reduction over the pixels of one chunk.  One wave per (16 channels, 16 k,
-// chunk); partial sums per chunk go to `part` (and, for the first k tile, the
-// bias partial sums to `partb`).
-__global__ void __launch_bounds__(64) wgrad_kernel(const bf16 *__restrict__ dy,
-                                                    const bf16 *__restrict__ x, int B, int H,
-                                                    int W, int cin, int cout, int chunk,
-                                                    float *__restrict__ part,
-                                                    float *__restrict__ partb) {
-  const int lane = threadIdx.x;
-  const int M = B * H * W, K = 9 * cin;
-  const int co = blockIdx.x * 16 + (lane & 15);
-  const int kc = blockIdx.y * 16 + (lane & 15);
-  const int tap = kc / cin, c = kc - tap * cin;
-  const int oy = tap / 3 - 1, ox = tap % 3 - 1;
+// Weight gradient as a GEMM: rows = output channels o, columns = k = t*cin + c,
+// reduction over the pixels of one chunk.  A workgroup (4 waves) computes a
+// 64 x 64 tile of (o, k).  Per step of 32 pixels it loads dy[32 pixels, 64 o]
+// and the tap-shifted x[32 pixels, 64 k] with 16-byte vector loads (8
+// channels per thread; cin and cout are multiples of 16, so 8 consecutive k
+// lie in one tap) and stores both transposed in LDS, pixels contiguous, the
+// layout the MFMA reduction reads; wave w then runs output rows 16 w .. +15
+// against the four 16-column tiles.  Partial sums per chunk go to `part`
+// (and, for the first k tile, the bias partial sums to `partb`).
+constexpr int kWgTile = 64;            // output channels and k per workgroup
+constexpr int kWgPix = 32;             // pixels per step (one MFMA reduction)
+constexpr int kWgRow = kWgPix + 8;     // LDS row length in bf16 (padding: fewer bank conflicts)
+
+__global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
+                                                     const bf16 *__restrict__ x, int B, int H,
+                                                     int W, int cin, int cout, int chunk,
+                                                     float *__restrict__ part,
+                                                     float *__restrict__ partb) {
+  __shared__ __attribute__((aligned(16))) bf16 sA[kWgTile * kWgRow];  // dy^T: [o][pixel]
+  __shared__ __attribute__((aligned(16))) bf16 sB[kWgTile * kWgRow];  // x^T:  [k][pixel]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int HW = H * W, M = B * HW, K = 9 * cin;
+  const int o0 = blockIdx.x * kWgTile, k0 = blockIdx.y * kWgTile;
   const int p0 = blockIdx.z * chunk, p1 = min(M, p0 + chunk);
-  const int q = 8 * (lane >> 4);
-  f4 acc = {0.f, 0.f, 0.f, 0.f};
-  float bsum = 0.0f;
-  for (int p = p0; p < p1; p += 32) {
-    bf16x8 a, b;
-    for (int e = 0; e < 8; ++e) {
-      const int mm = p + q + e;
-      bf16 av = (bf16)0.0f, bv = (bf16)0.0f;
-      if (mm < p1) {
-        av = dy[(size_t)mm * cout + co];
-        const int n = mm / (H * W);
-        const int r = mm - n * H * W;
-        const int yy = r / W + oy, xx = r % W + ox;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          bv = x[((size_t)(n * H + yy) * W + xx) * cin + c];
-      }
-      a[e] = av;
-      b[e] = bv;
-      bsum += (float)av;
-    }
-    acc = mfma16(a, b, acc);
+  // loading role: pixel lp of the step, 8 channels from 8 lg
+  const int lp = tid >> 3, lg = tid & 7;
+  const int lo = o0 + 8 * lg, lk = k0 + 8 * lg;
+  const bool o_ok = lo < cout, k_ok = lk < K;
+  int lc = 0, oy = 0, ox = 0;
+  if (k_ok) {
+    const int tap = lk / cin;
+    lc = lk - tap * cin;
+    oy = tap / 3 - 1;
+    ox = tap % 3 - 1;
   }
+  // MFMA role: A row (output channel) and 8 pixels of the reduction
+  const int row = lane & 15, q = 8 * (lane >> 4);
+  const bool bias = partb && blockIdx.y == 0;
+  f4 acc[4];
+  for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.0f;
+  const bf16x8 zero = {};
+  for (int p = p0; p < p1; p += kWgPix) {
+    const int mm = p + lp;
+    bf16x8 va = zero, vb = zero;
+    if (mm < p1) {
+      if (o_ok) va = *reinterpret_cast<const bf16x8 *>(dy + (size_t)mm * cout + lo);
+      if (k_ok) {
+        const int n = mm / HW, r = mm - n * HW;
+        const int py = r / W, yy = py + oy, xx = r - py * W + ox;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          vb = *reinterpret_cast<const bf16x8 *>(x + ((size_t)(n * H + yy) * W + xx) * cin + lc);
+      }
+    }
+    __syncthreads();  // the previous step's LDS reads are done
+    for (int e = 0; e < 8; ++e) {
+      sA[(8 * lg + e) * kWgRow + lp] = va[e];
+      sB[(8 * lg + e) * kWgRow + lp] = vb[e];
+    }
+    __syncthreads();
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sA + (16 * wave + row) * kWgRow + q);
+    for (int t = 0; t < 4; ++t) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(sB + (16 * t + row) * kWgRow + q);
+      acc[t] = mfma16(a, b, acc[t]);
+    }
+    if (bias)
+      for (int e = 0; e < 8; ++e) bsum += (float)a[e];
+  }
+  // D: lane holds column k0 + 16 t + row, output channels o0 + 16 wave + 4 (lane / 16) + e
   const size_t base = (size_t)blockIdx.z * cout * K;
-  for (int e = 0; e < 4; ++e)
-    part[base + (size_t)(blockIdx.x * 16 + 4 * (lane >> 4) + e) * K + blockIdx.y * 16 +
-         (lane & 15)] = acc[e];
-  if (blockIdx.y == 0 && partb) {
+  for (int t = 0; t < 4; ++t) {
+    const int kk = k0 + 16 * t + row;
+    if (kk >= K) continue;
+    for (int e = 0; e < 4; ++e) {
+      const int o = o0 + 16 * wave + 4 * (lane >> 4) + e;
+      if (o < cout) part[base + (size_t)o * K + kk] = acc[t][e];
+    }
+  }
+  if (bias) {
     bsum += __shfl_xor(bsum, 16, 64);
     bsum += __shfl_xor(bsum, 32, 64);
-    if (lane < 16) partb[(size_t)blockIdx.z * cout + co] = bsum;
+    const int o = o0 + 16 * wave + row;
+    if (lane < 16 && o < cout) partb[(size_t)blockIdx.z * cout + o] = bsum;
   }
 }
 
@@ -363,11 +400,16 @@ clb_status launched() {
 
 unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
 
+// Workgroup tiles of the weight gradient (64 output channels x 64 k).
+int64_t wgrad_tiles(int cin, int cout) {
+  return (int64_t)((cout + kWgTile - 1) / kWgTile) * ((9LL * cin + kWgTile - 1) / kWgTile);
+}
+
 // Split of the pixel reduction of the weight gradient: enough chunks for
-// about 4096 workgroups, each chunk a multiple of 32 pixels and >= 256.
+// about 2048 workgroups, each chunk a multiple of 32 pixels and >= 512.
 void wgrad_plan(int64_t M, int64_t tiles, int *nsplit, int *chunk) {
-  int64_t ns = std::max<int64_t>(1, (4096 + tiles - 1) / tiles);
-  ns = std::min<int64_t>(ns, std::max<int64_t>(1, M / 256));
+  int64_t ns = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, M / 512));
   int64_t ch = (M + ns - 1) / ns;
   ch = (ch + 31) / 32 * 32;
   *chunk = (int)ch;
@@ -401,7 +443,7 @@ extern "C" clb_status clb_nn_wgrad_workspace_bytes(int32_t batch, int32_t h, int
     return CLB_ERR_ARG;
   int nsplit, chunk;
   const int64_t K = 9LL * cin;
-  wgrad_plan((int64_t)batch * h * w, (cout / 16) * (K / 16), &nsplit, &chunk);
+  wgrad_plan((int64_t)batch * h * w, wgrad_tiles(cin, cout), &nsplit, &chunk);
   *bytes = sizeof(float) * (size_t)nsplit * (cout * K + cout);
   return CLB_OK;
 }
@@ -412,15 +454,18 @@ extern "C" clb_status clb_nn_conv3x3_wgrad(const clb_bf16 *dy, const clb_bf16 *x
                                            size_t bytes, void *stream) {
   size_t need = 0;
   if (clb_nn_wgrad_workspace_bytes(batch, h, w, cin, cout, &need) != CLB_OK || !dy || !x ||
-      !dweight || !workspace || bytes < need)
+      !dweight || !workspace || bytes < need || !aligned16(dy) || !aligned16(x))
     return CLB_ERR_ARG;
   int nsplit, chunk;
   const int64_t K = 9LL * cin, M = (int64_t)batch * h * w;
-  wgrad_plan(M, (cout / 16) * (K / 16), &nsplit, &chunk);
+  wgrad_plan(M, wgrad_tiles(cin, cout), &nsplit, &chunk);
   float *part = static_cast<float *>(workspace);
   float *partb = part + (size_t)nsplit * cout * K;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(wgrad_kernel, dim3(cout / 16, (unsigned)(K / 16), nsplit), dim3(64), 0, s,
+  hipLaunchKernelGGL(wgrad_kernel,
+                     dim3((unsigned)((cout + kWgTile - 1) / kWgTile),
+                          (unsigned)((K + kWgTile - 1) / kWgTile), nsplit),
+                     dim3(256), 0, s,
                      reinterpret_cast<const bf16 *>(dy), reinterpret_cast<const bf16 *>(x), batch,
                      h, w, cin, cout, chunk, part, partb);
   const size_t n = (size_t)cout * K;
