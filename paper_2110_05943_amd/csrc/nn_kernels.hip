@@ -31,52 +31,58 @@ __device__ __forceinline__ f4 mfma16(const bf16x8 &a, const bf16x8 &b, const f4 
 
 // Forward 3x3 convolution as a GEMM: rows = pixels (b, i, j), columns =
 // output channels, reduction index k = t * cin + c (tap-major, channels
-// contiguous).  Each wave computes 16 pixels x up to 64 channels; the
-// reduction runs in steps of 32 (one MFMA per column tile).  cin is a
-// multiple of 16, so a lane's 8 consecutive k lie in one tap and are 16
-// contiguous bytes of x and of the weight row.
-__global__ void __launch_bounds__(256) conv3x3_kernel(
-    const bf16 *__restrict__ x, int B, int H, int W, int cin, const bf16 *__restrict__ wt,
-    const float *__restrict__ bias, int cout, int act, float slope, void *__restrict__ y,
-    int y_fp32) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int M = B * H * W;
-  const int m0 = blockIdx.x * kPixTile + wave * 16;
-  const int co0 = blockIdx.y * kCoTile;
-  const int nt = min(4, (cout - co0) >> 4);
-  const int K = 9 * cin;
-  const int row = lane & 15, kq = 8 * (lane >> 4);
-  const int m = m0 + row;
-  const bool mok = m < M;
-  int n = 0, py = 0, px = 0;
-  if (mok) {
-    n = m / (H * W);
-    const int r = m - n * H * W;
-    py = r / W;
-    px = r - py * W;
+// contiguous).  The reduction runs in steps of 32 (one 16x16x32 MFMA per
+// 16-channel column tile); cin is a multiple of 16, so a lane's 8
+// consecutive k lie in one tap and are 16 contiguous bytes of x and of the
+// weight row.  A workgroup (4 waves) computes up to 64 output channels for
+//   - KSPLIT = false: 64 pixels, wave w the pixels 16 w .. +15.  The weight
+//     slice of each step (64 channels x 32 k) is loaded once per workgroup
+//     into LDS (double-buffered) and read by all four waves;
+//   - KSPLIT = true (few pixels, deep layers): 16 pixels, wave w the steps
+//     w, w + 4, ...; the four partial sums are added in wave order through
+//     LDS, which gives four times as many workgroups and a quarter of the
+//     sequential steps per wave.
+// Both load the next step's operands before the current step's MFMAs.
+constexpr int kWRow = 32 + 8;  // LDS row of the weight slice in bf16 (padded)
+
+struct ConvPixel {
+  int n, py, px;
+  bool ok;
+};
+
+__device__ __forceinline__ ConvPixel conv_pixel(int m, int M, int H, int W) {
+  ConvPixel p{0, 0, 0, m < M};
+  if (p.ok) {
+    p.n = m / (H * W);
+    const int r = m - p.n * H * W;
+    p.py = r / W;
+    p.px = r - p.py * W;
   }
-  f4 acc[4];
-  for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-  const bf16x8 zero = {};
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    const int k = k0 + kq;
-    bf16x8 a = zero;
-    if (k < K && mok) {
-      const int tap = k / cin, c = k - tap * cin;
-      const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-        a = *reinterpret_cast<const bf16x8 *>(x + ((size_t)(n * H + yy) * W + xx) * cin + c);
-    }
-    for (int t = 0; t < 4; ++t) {
-      if (t >= nt) break;
-      bf16x8 b = zero;
-      if (k < K) b = *reinterpret_cast<const bf16x8 *>(wt + (size_t)(co0 + 16 * t + row) * K + k);
-      acc[t] = mfma16(a, b, acc[t]);
-    }
+  return p;
+}
+
+// 8 consecutive k of one pixel (zero outside the image or beyond K).
+__device__ __forceinline__ bf16x8 conv_a(const bf16 *__restrict__ x, const ConvPixel &p, int k,
+                                         int K, int H, int W, int cin) {
+  bf16x8 a = {};
+  if (k < K && p.ok) {
+    const int tap = k / cin, c = k - tap * cin;
+    const int yy = p.py + tap / 3 - 1, xx = p.px + tap % 3 - 1;
+    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+      a = *reinterpret_cast<const bf16x8 *>(x + ((size_t)(p.n * H + yy) * W + xx) * cin + c);
   }
+  return a;
+}
+
+// Bias, activation and store of one wave's 16 pixels x nt column tiles.
+__device__ __forceinline__ void conv_store(const f4 *acc, int nt, int m0, int M, int co0,
+                                           int lane, const float *__restrict__ bias, int cout,
+                                           int act, float slope, void *__restrict__ y,
+                                           int y_fp32) {
+#pragma unroll
   for (int t = 0; t < 4; ++t) {
-    if (t >= nt) break;
-    const int co = co0 + 16 * t + row;
+    if (t >= nt) continue;
+    const int co = co0 + 16 * t + (lane & 15);
     const float bb = bias ? bias[co] : 0.0f;
     for (int e = 0; e < 4; ++e) {
       const int mm = m0 + 4 * (lane >> 4) + e;
@@ -87,6 +93,96 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(
         static_cast<float *>(y)[(size_t)mm * cout + co] = v;
       else
         static_cast<bf16 *>(y)[(size_t)mm * cout + co] = (bf16)v;
+    }
+  }
+}
+
+template <bool KSPLIT>
+__global__ void __launch_bounds__(256) conv3x3_kernel(
+    const bf16 *__restrict__ x, int B, int H, int W, int cin, const bf16 *__restrict__ wt,
+    const float *__restrict__ bias, int cout, int act, float slope, void *__restrict__ y,
+    int y_fp32) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int M = B * H * W, K = 9 * cin, nsteps = (K + 31) / 32;
+  const int co0 = blockIdx.y * kCoTile;
+  const int nt = min(4, (cout - co0) >> 4);
+  const int row = lane & 15, kq = 8 * (lane >> 4);
+  const bf16x8 zero = {};
+  f4 acc[4];
+  for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (!KSPLIT) {
+    __shared__ __attribute__((aligned(16))) bf16 sw[2][kCoTile * kWRow];
+    const int m0 = blockIdx.x * kPixTile + wave * 16;
+    const ConvPixel px = conv_pixel(m0 + row, M, H, W);
+    // weight loading role: channel wo of the slice, k offset 8 wk
+    const int wo = threadIdx.x >> 2, wk = 8 * (threadIdx.x & 3);
+    const bool wok = co0 + wo < cout;
+    const bf16 *wrow = wt + (size_t)(co0 + wo) * K;
+    bf16x8 a = conv_a(x, px, kq, K, H, W, cin);
+    bf16x8 wv = (wok && wk < K) ? *reinterpret_cast<const bf16x8 *>(wrow + wk) : zero;
+    *reinterpret_cast<bf16x8 *>(&sw[0][wo * kWRow + wk]) = wv;
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+      const int cur = s & 1;
+      const int kn = 32 * (s + 1);
+      bf16x8 an = zero;
+      if (s + 1 < nsteps) {
+        an = conv_a(x, px, kn + kq, K, H, W, cin);
+        wv = (wok && kn + wk < K) ? *reinterpret_cast<const bf16x8 *>(wrow + kn + wk) : zero;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < nt) {
+          const bf16x8 b =
+              *reinterpret_cast<const bf16x8 *>(&sw[cur][(16 * t + row) * kWRow + kq]);
+          acc[t] = mfma16(a, b, acc[t]);
+        }
+      }
+      if (s + 1 < nsteps) *reinterpret_cast<bf16x8 *>(&sw[cur ^ 1][wo * kWRow + wk]) = wv;
+      __syncthreads();
+      a = an;
+    }
+    conv_store(acc, nt, m0, M, co0, lane, bias, cout, act, slope, y, y_fp32);
+  } else {
+    __shared__ f4 red[3][4][64];
+    const int m0 = blockIdx.x * 16;
+    const ConvPixel px = conv_pixel(m0 + row, M, H, W);
+    const bf16 *wrow = wt + (size_t)(co0 + row) * K;  // column tile t adds 16 t rows
+    auto load_b = [&](int k, int t) {
+      return k < K ? *reinterpret_cast<const bf16x8 *>(wrow + (size_t)16 * t * K + k) : zero;
+    };
+    int s = wave;
+    bf16x8 a = zero, b[4] = {zero, zero, zero, zero};
+    if (s < nsteps) {
+      a = conv_a(x, px, 32 * s + kq, K, H, W, cin);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nt) b[t] = load_b(32 * s + kq, t);
+    }
+    for (; s < nsteps; s += 4) {
+      bf16x8 an = zero, bn[4] = {zero, zero, zero, zero};
+      if (s + 4 < nsteps) {
+        an = conv_a(x, px, 32 * (s + 4) + kq, K, H, W, cin);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < nt) bn[t] = load_b(32 * (s + 4) + kq, t);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nt) acc[t] = mfma16(a, b[t], acc[t]);
+      a = an;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) b[t] = bn[t];
+    }
+    if (wave > 0)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) red[wave - 1][t][lane] = acc[t];
+    __syncthreads();
+    if (wave == 0) {
+      for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] += red[w][t][lane];
+      conv_store(acc, nt, m0, M, co0, lane, bias, cout, act, slope, y, y_fp32);
     }
   }
 }
@@ -177,15 +273,24 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
   }
 }
 
-// Sum of `nsplit` partial arrays of length n in split order.
+// Sum of `nsplit` partial arrays of length n in a fixed order: block b adds
+// outputs [64 b, 64 b + 64); wave w of the block takes the splits w, w + 4,
+// w + 8, ... in increasing order (64 consecutive outputs per load: coalesced),
+// and the four wave sums are added in wave order.
 __global__ void __launch_bounds__(256) sum_parts_kernel(const float *__restrict__ part,
                                                         int nsplit, size_t n,
                                                         float *__restrict__ out) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  __shared__ float lds[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const size_t i = (size_t)blockIdx.x * 64 + lane;
   float s = 0.0f;
-  for (int z = 0; z < nsplit; ++z) s += part[(size_t)z * n + i];
-  out[i] = s;
+  if (i < n) {
+#pragma unroll 8
+    for (int z = w; z < nsplit; z += 4) s += part[(size_t)z * n + i];
+  }
+  lds[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i < n) out[i] = ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane];
 }
 
 __global__ void __launch_bounds__(256) weights_kernel(const float *__restrict__ w32, int cout,
@@ -430,10 +535,18 @@ extern "C" clb_status clb_nn_conv3x3(const clb_bf16 *x, int32_t batch, int32_t h
       cout % 16 || (act != 0 && act != 1) || !aligned16(x) || !aligned16(weight))
     return CLB_ERR_ARG;
   const int64_t M = (int64_t)batch * h * w;
-  const dim3 grid((unsigned)((M + kPixTile - 1) / kPixTile), (unsigned)((cout + kCoTile - 1) / kCoTile));
-  hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream),
-                     reinterpret_cast<const bf16 *>(x), batch, h, w, cin,
-                     reinterpret_cast<const bf16 *>(weight), bias, cout, act, slope, y, y_fp32);
+  const unsigned cot = (unsigned)((cout + kCoTile - 1) / kCoTile);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bf16 *xb = reinterpret_cast<const bf16 *>(x), *wb = reinterpret_cast<const bf16 *>(weight);
+  // Pixel tiles while they give at least ~1024 workgroups; split the
+  // reduction over the waves of a workgroup below that.
+  if (((M + kPixTile - 1) / kPixTile) * cot >= 1024)
+    hipLaunchKernelGGL(conv3x3_kernel<false>, dim3((unsigned)((M + kPixTile - 1) / kPixTile), cot),
+                       dim3(256), 0, s, xb, batch, h, w, cin, wb, bias, cout, act, slope, y,
+                       y_fp32);
+  else
+    hipLaunchKernelGGL(conv3x3_kernel<true>, dim3((unsigned)((M + 15) / 16), cot), dim3(256), 0,
+                       s, xb, batch, h, w, cin, wb, bias, cout, act, slope, y, y_fp32);
   return launched();
 }
 
@@ -469,11 +582,11 @@ extern "C" clb_status clb_nn_conv3x3_wgrad(const clb_bf16 *dy, const clb_bf16 *x
                      reinterpret_cast<const bf16 *>(dy), reinterpret_cast<const bf16 *>(x), batch,
                      h, w, cin, cout, chunk, part, partb);
   const size_t n = (size_t)cout * K;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks_for(n)), dim3(256), 0, s, part, nsplit, n,
-                     dweight);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part,
+                     nsplit, n, dweight);
   if (dbias)
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks_for(cout)), dim3(256), 0, s, partb, nsplit,
-                       (size_t)cout, dbias);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((cout + 63) / 64)), dim3(256), 0, s,
+                       partb, nsplit, (size_t)cout, dbias);
   return launched();
 }
 

@@ -65,14 +65,27 @@ def bf16_steps(a, b):
     return np.abs(ua.astype(np.int64) - ub.astype(np.int64))
 
 
-def check_bf16(got, ref, what, frac=1e-3):
+def check_bf16(got, ref, what, frac=1e-3, bound=None):
+    """bfloat16 results against the FP64 reference: at most one bfloat16 step
+    from the rounded reference, and only for a fraction `frac` of the values.
+    With `bound` (the reference's own FP32 error bound per value), values
+    whose magnitude is within 1024 bounds of zero, where the FP32 sum itself
+    may move the result by several bfloat16 steps, are held to
+    |got - ref| <= 2^-7 |ref| + bound instead."""
     d = bf16_steps(got, N.round_bf16(ref))
-    log("%s: %d of %d values one bfloat16 step off, max %d" % (what, int((d > 0).sum()), d.size,
-                                                               int(d.max())))
-    assert d.max() <= 1 and (d > 0).mean() <= frac
+    sel = np.ones(d.shape, bool) if bound is None else np.abs(ref) > 1024 * bound
+    log("%s: %d of %d values one bfloat16 step off, max %d (%d near zero)"
+        % (what, int((d[sel] > 0).sum()), d.size, int(d[sel].max()), int((~sel).sum())))
+    assert d[sel].max() <= 1 and (d[sel] > 0).mean() <= frac
+    if bound is not None:
+        assert np.all(np.abs(got - ref)[~sel] <= 2.0 ** -7 * np.abs(ref[~sel]) + bound[~sel])
 
 
-CONV_SHAPES = [(2, 9, 13, 16, 16), (1, 5, 7, 48, 80), (2, 8, 8, 384, 128), (3, 16, 16, 16, 32)]
+# The last shape has over 1024 tiles of 64 pixels: the convolution takes its
+# pixel-tiled path there (the others split the reduction over the waves), with
+# a ragged last tile and a partial column tile.
+CONV_SHAPES = [(2, 9, 13, 16, 16), (1, 5, 7, 48, 80), (2, 8, 8, 384, 128), (3, 16, 16, 16, 32),
+               (1, 255, 259, 32, 48)]
 
 
 @pytest.mark.parametrize("shape", CONV_SHAPES)
@@ -95,7 +108,8 @@ def test_conv3x3_forward_fp32_and_bf16(nn, shape):
     y16 = empty(ref.size)
     nn.call("clb_nn_conv3x3", nn.ptr(dx), Bn, H, W, ci, nn.ptr(dw), nn.ptr(db), co, 1,
             nn.SLOPE, nn.ptr(y16), 0, None)
-    check_bf16(host(y16).reshape(ref.shape), N.leaky(ref, nn.SLOPE), "conv %s bf16" % (shape,))
+    check_bf16(host(y16).reshape(ref.shape), N.leaky(ref, nn.SLOPE), "conv %s bf16" % (shape,),
+               bound=bound)
 
 
 @pytest.mark.parametrize("shape", CONV_SHAPES)
