@@ -189,31 +189,40 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(
 
 // Weight gradient as a GEMM: rows = output channels o, columns = k = t*cin + c,
 // reduction over the pixels of one chunk.  A workgroup (4 waves) computes a
-// 64 x 64 tile of (o, k).  Per step of 32 pixels it loads dy[32 pixels, 64 o]
-// and the tap-shifted x[32 pixels, 64 k] with 16-byte vector loads (8
-// channels per thread; cin and cout are multiples of 16, so 8 consecutive k
-// lie in one tap) and stores both transposed in LDS, pixels contiguous, the
-// layout the MFMA reduction reads; wave w then runs output rows 16 w .. +15
-// against the four 16-column tiles.  Partial sums per chunk go to `part`
-// (and, for the first k tile, the bias partial sums to `partb`).
-constexpr int kWgTile = 64;            // output channels and k per workgroup
-constexpr int kWgPix = 32;             // pixels per step (one MFMA reduction)
-constexpr int kWgRow = kWgPix + 8;     // LDS row length in bf16 (padding: fewer bank conflicts)
+// (16 OB) x 64 tile of (o, k), OB = 1, 2 or 4 output blocks of 16 channels;
+// the 4 waves form OB output blocks x 4/OB pixel groups, so that small
+// layers (16 or 32 channels) keep every wave busy.  Per step of 128/OB pixels
+// the workgroup loads dy[pixels, 16 OB o] and the tap-shifted x[pixels, 64 k]
+// with 16-byte vector loads (8 channels per load; cin and cout are multiples
+// of 16, so 8 consecutive k lie in one tap) and stores both transposed in LDS,
+// pixels contiguous, the layout the MFMA reduction reads; wave (ob, pg) runs
+// its output block against the four 16-column tiles over its 32 pixels.  The
+// pixel groups' sums are added through LDS in group order.  Partial sums per
+// chunk go to `part` (and, for the first k tile, the bias partial sums to
+// `partb`).
+constexpr int kWgK = 64;  // k columns per workgroup
 
+template <int OB>
 __global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
                                                      const bf16 *__restrict__ x, int B, int H,
                                                      int W, int cin, int cout, int chunk,
                                                      float *__restrict__ part,
                                                      float *__restrict__ partb) {
-  __shared__ __attribute__((aligned(16))) bf16 sA[kWgTile * kWgRow];  // dy^T: [o][pixel]
-  __shared__ __attribute__((aligned(16))) bf16 sB[kWgTile * kWgRow];  // x^T:  [k][pixel]
+  constexpr int PG = 4 / OB;         // pixel groups
+  constexpr int PX = 32 * PG;        // pixels per step
+  constexpr int ROW = PX + 8;        // LDS row length in bf16 (padding: fewer bank conflicts)
+  __shared__ __attribute__((aligned(16))) bf16 sA[16 * OB * ROW];  // dy^T: [o][pixel]
+  __shared__ __attribute__((aligned(16))) bf16 sB[kWgK * ROW];     // x^T:  [k][pixel]
+  __shared__ f4 red[PG > 1 ? PG - 1 : 1][OB][4][64];
+  __shared__ float redb[PG > 1 ? PG - 1 : 1][OB][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ob = wave % OB, pg = wave / OB;
   const int HW = H * W, M = B * HW, K = 9 * cin;
-  const int o0 = blockIdx.x * kWgTile, k0 = blockIdx.y * kWgTile;
+  const int o0 = blockIdx.x * 16 * OB, k0 = blockIdx.y * kWgK;
   const int p0 = blockIdx.z * chunk, p1 = min(M, p0 + chunk);
-  // loading role: pixel lp of the step, 8 channels from 8 lg
-  const int lp = tid >> 3, lg = tid & 7;
-  const int lo = o0 + 8 * lg, lk = k0 + 8 * lg;
+  // loading roles: dy pixel ap with channels 8 ag..; x pixels tid/8 + 32 j with k 8 kg..
+  const int ap = tid / (2 * OB), ag = tid % (2 * OB), kg = tid & 7;
+  const int lo = o0 + 8 * ag, lk = k0 + 8 * kg;
   const bool o_ok = lo < cout, k_ok = lk < K;
   int lc = 0, oy = 0, ox = 0;
   if (k_ok) {
@@ -223,52 +232,77 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
     ox = tap % 3 - 1;
   }
   // MFMA role: A row (output channel) and 8 pixels of the reduction
-  const int row = lane & 15, q = 8 * (lane >> 4);
+  const int row = lane & 15, q = 32 * pg + 8 * (lane >> 4);
   const bool bias = partb && blockIdx.y == 0;
   f4 acc[4];
+#pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.0f;
   const bf16x8 zero = {};
-  for (int p = p0; p < p1; p += kWgPix) {
-    const int mm = p + lp;
-    bf16x8 va = zero, vb = zero;
-    if (mm < p1) {
-      if (o_ok) va = *reinterpret_cast<const bf16x8 *>(dy + (size_t)mm * cout + lo);
-      if (k_ok) {
+  for (int p = p0; p < p1; p += PX) {
+    bf16x8 va = zero, vb[PG];
+    const int ma = p + ap;
+    if (ma < p1 && o_ok) va = *reinterpret_cast<const bf16x8 *>(dy + (size_t)ma * cout + lo);
+#pragma unroll
+    for (int j = 0; j < PG; ++j) {
+      vb[j] = zero;
+      const int mm = p + (tid >> 3) + 32 * j;
+      if (mm < p1 && k_ok) {
         const int n = mm / HW, r = mm - n * HW;
         const int py = r / W, yy = py + oy, xx = r - py * W + ox;
         if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          vb = *reinterpret_cast<const bf16x8 *>(x + ((size_t)(n * H + yy) * W + xx) * cin + lc);
+          vb[j] = *reinterpret_cast<const bf16x8 *>(x + ((size_t)(n * H + yy) * W + xx) * cin + lc);
       }
     }
     __syncthreads();  // the previous step's LDS reads are done
-    for (int e = 0; e < 8; ++e) {
-      sA[(8 * lg + e) * kWgRow + lp] = va[e];
-      sB[(8 * lg + e) * kWgRow + lp] = vb[e];
-    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sA[(8 * ag + e) * ROW + ap] = va[e];
+#pragma unroll
+    for (int j = 0; j < PG; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sB[(8 * kg + e) * ROW + (tid >> 3) + 32 * j] = vb[j][e];
     __syncthreads();
-    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sA + (16 * wave + row) * kWgRow + q);
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sA + (16 * ob + row) * ROW + q);
+#pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(sB + (16 * t + row) * kWgRow + q);
+      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(sB + (16 * t + row) * ROW + q);
       acc[t] = mfma16(a, b, acc[t]);
     }
     if (bias)
+#pragma unroll
       for (int e = 0; e < 8; ++e) bsum += (float)a[e];
   }
-  // D: lane holds column k0 + 16 t + row, output channels o0 + 16 wave + 4 (lane / 16) + e
+  if constexpr (PG > 1) {  // add the pixel groups' sums in group order
+    if (pg > 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) red[pg - 1][ob][t][lane] = acc[t];
+      redb[pg - 1][ob][lane] = bsum;
+    }
+    __syncthreads();
+    if (pg == 0)
+      for (int g = 0; g < PG - 1; ++g) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] += red[g][ob][t][lane];
+        bsum += redb[g][ob][lane];
+      }
+  }
+  if (pg != 0) return;
+  // D: lane holds column k0 + 16 t + row, output channels o0 + 16 ob + 4 (lane / 16) + e
   const size_t base = (size_t)blockIdx.z * cout * K;
+#pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int kk = k0 + 16 * t + row;
     if (kk >= K) continue;
+#pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int o = o0 + 16 * wave + 4 * (lane >> 4) + e;
+      const int o = o0 + 16 * ob + 4 * (lane >> 4) + e;
       if (o < cout) part[base + (size_t)o * K + kk] = acc[t][e];
     }
   }
   if (bias) {
     bsum += __shfl_xor(bsum, 16, 64);
     bsum += __shfl_xor(bsum, 32, 64);
-    const int o = o0 + 16 * wave + row;
+    const int o = o0 + 16 * ob + row;
     if (lane < 16 && o < cout) partb[(size_t)blockIdx.z * cout + o] = bsum;
   }
 }
@@ -505,18 +539,22 @@ clb_status launched() {
 
 unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
 
-// Workgroup tiles of the weight gradient (64 output channels x 64 k).
+// Output blocks of 16 channels per weight-gradient workgroup.
+int wgrad_ob(int cout) { return cout % 64 == 0 ? 4 : (cout % 32 == 0 ? 2 : 1); }
+
+// Workgroup tiles of the weight gradient ((16 OB) output channels x 64 k).
 int64_t wgrad_tiles(int cin, int cout) {
-  return (int64_t)((cout + kWgTile - 1) / kWgTile) * ((9LL * cin + kWgTile - 1) / kWgTile);
+  return (int64_t)(cout / (16 * wgrad_ob(cout))) * ((9LL * cin + kWgK - 1) / kWgK);
 }
 
 // Split of the pixel reduction of the weight gradient: enough chunks for
-// about 2048 workgroups, each chunk a multiple of 32 pixels and >= 512.
+// about 2048 workgroups, each chunk a multiple of 128 pixels (a whole number
+// of steps for every OB) and >= 512.
 void wgrad_plan(int64_t M, int64_t tiles, int *nsplit, int *chunk) {
   int64_t ns = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, M / 512));
   int64_t ch = (M + ns - 1) / ns;
-  ch = (ch + 31) / 32 * 32;
+  ch = (ch + 127) / 128 * 128;
   *chunk = (int)ch;
   *nsplit = (int)((M + ch - 1) / ch);
 }
@@ -575,12 +613,18 @@ extern "C" clb_status clb_nn_conv3x3_wgrad(const clb_bf16 *dy, const clb_bf16 *x
   float *part = static_cast<float *>(workspace);
   float *partb = part + (size_t)nsplit * cout * K;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(wgrad_kernel,
-                     dim3((unsigned)((cout + kWgTile - 1) / kWgTile),
-                          (unsigned)((K + kWgTile - 1) / kWgTile), nsplit),
-                     dim3(256), 0, s,
-                     reinterpret_cast<const bf16 *>(dy), reinterpret_cast<const bf16 *>(x), batch,
-                     h, w, cin, cout, chunk, part, partb);
+  const int ob = wgrad_ob(cout);
+  const dim3 grid((unsigned)(cout / (16 * ob)), (unsigned)((K + kWgK - 1) / kWgK), nsplit);
+  const bf16 *dyb = reinterpret_cast<const bf16 *>(dy), *xb = reinterpret_cast<const bf16 *>(x);
+  if (ob == 4)
+    hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, dyb, xb, batch, h, w, cin, cout,
+                       chunk, part, partb);
+  else if (ob == 2)
+    hipLaunchKernelGGL(wgrad_kernel<2>, grid, dim3(256), 0, s, dyb, xb, batch, h, w, cin, cout,
+                       chunk, part, partb);
+  else
+    hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, dyb, xb, batch, h, w, cin, cout,
+                       chunk, part, partb);
   const size_t n = (size_t)cout * K;
   hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part,
                      nsplit, n, dweight);
