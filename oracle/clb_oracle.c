@@ -19,10 +19,10 @@
  * Pins (tests/test_oracle_pins.py): matrix identities, a brute-force 4x4 step,
  * consistent forcing, conservation, uniform Darcy-Forchheimer flow, linear
  * decay rates, pure conduction (Nu = 1), the Darcy-Brinkman channel and the
- * paper's mixed-convection channel with second-order convergence.
- * Parity unpinned: the inlet and outlet side kinds and the corner temperature
- * rule between two Dirichlet sides; nothing printed in the paper and no closed
- * form exercises them.
+ * paper's mixed-convection channel with second-order convergence, and plane
+ * Poiseuille flow between an inlet and an outlet side.
+ * Parity unpinned: the corner temperature rule between two Dirichlet sides;
+ * nothing printed in the paper and no closed form exercises it.
  */
 #include "clb_oracle.h"
 

@@ -390,6 +390,37 @@ def test_low_viscosity_channel_stays_finite(orc):
     assert np.max(np.abs(m["ux"])) < 10 * np.max(np.abs(ux_a)) + 10 * u1
 
 
+# ------------------------------------------------------ inlet and outlet (C8)
+
+def test_inlet_outlet_channel_develops_poiseuille_flow(orc):
+    # Clear fluid (phi = 1, no drag), parabolic inflow of mean U at the west
+    # side, the outlet reading at the east side, no-slip walls.  The inflow is
+    # already the developed profile, so the steady state is plane Poiseuille
+    # flow: a parabolic profile everywhere, a linear pressure drop of
+    # 12 nu U / H^2 (rho c_s^2 = p), and the same mass flux through every
+    # interior column.
+    nx, ny, U, s_v = 49, 17, 0.02, 1.0
+    nu = (1 / s_v - 0.5) / 3
+    lat = oracle.Lattice(nx, ny, bc=("inlet", "outlet", "wall_T", "wall_T"),
+                         bc_T=(0.5, 0.5, 0.5, 0.5), inlet_U=U, nu=nu, s_v=s_v, za=1.0, phi=1.0,
+                         Fphi=0.0, nthreads=1)
+    lat.init_equilibrium(0.5)
+    m = _run_to_steady(lat, 500, 1e-14)
+    H = ny - 1
+    t = np.arange(ny) / H
+    par = 6 * U * t * (1 - t)
+    ux, rho = m["ux"], m["rho"]
+    mid = ux[:, nx // 2]
+    assert np.max(np.abs(mid / mid.max() - par / par.max())) < 1e-3   # parabolic shape
+    assert np.max(np.abs(ux[:, 0] - par)) < 1e-12                      # inlet nodes carry u_b
+    slope = np.polyfit(np.arange(nx), rho[ny // 2], 1)[0]
+    assert abs(slope / (-12 * nu * U / H ** 2 * 3) - 1) < 0.03         # Poiseuille gradient
+    flux = (rho * ux)[1:-1, 1:-1].sum(axis=0)
+    assert (flux.max() - flux.min()) / flux.mean() < 1e-3              # mass conserved
+    assert abs(flux.mean() / par[1:-1].sum() - 1) < 0.02
+    assert np.max(np.abs(m["uy"])) < 5e-3 * U                           # nearly parallel
+
+
 # ---------------------------------------------------------- parameter derivation
 
 def test_cavity_parameters_satisfy_definitions():
