@@ -5,7 +5,8 @@ by both implementations would still show.
 - uniform Darcy-Forchheimer flow in a periodic box (Eqs. 4, 21-23 at F = 0);
 - pure conduction between isothermal walls (T linear, Nu = 1; walls on the
   nodes, L = n - 1, the boundary reconstruction, the Nusselt discretisation);
-- the Darcy-Brinkman channel (cosh profile), second order in the height.
+- the Darcy-Brinkman channel (cosh profile), second order in the height;
+- plane Poiseuille flow between an inlet and an outlet side.
 FP32 storage; tolerances allow its rounding noise (~1e-7 relative).
 """
 import math
@@ -100,3 +101,27 @@ def test_darcy_brinkman_channel_second_order(B):
     log("errors %s, slope %.3f" % (["%.3e" % e for e in errs], slope))
     assert errs[-1] < 1e-3
     assert 1.8 < slope < 2.3
+
+
+def test_inlet_outlet_poiseuille_flow(B):
+    # The developed parabolic inflow stays parabolic: shape, pressure gradient
+    # 12 nu U / H^2 (p = rho c_s^2) and one mass flux through every column.
+    nx, ny, U = 49, 17, 0.02
+    c = dict(nx=nx, ny=ny, bc=("inlet", "outlet", "wall_T", "wall_T"), bc_T=(0.5, 0.5, 0.5, 0.5),
+             inlet_U=U, scaling="channel", s_v=1.0, zeta_a=1.0, phi=1.0, Da=0.0, F_phi=0.0,
+             Ra=0.0, T_init=0.5)
+    s = B.Solver(c)
+    s.step(12000)
+    m = s.macros()
+    nu = B.derive(**c)["nu"]
+    H = ny - 1
+    t = np.arange(ny) / H
+    par = 6 * U * t * (1 - t)
+    mid = m["ux"][:, nx // 2]
+    shape = np.max(np.abs(mid / mid.max() - par / par.max()))
+    slope = np.polyfit(np.arange(nx), m["rho"][ny // 2], 1)[0] / (-12 * nu * U / H ** 2 * 3)
+    flux = (m["rho"] * m["ux"])[1:-1, 1:-1].sum(axis=0)
+    spread = (flux.max() - flux.min()) / flux.mean()
+    log("shape err %.2e, pressure gradient ratio %.4f, flux spread %.2e" % (shape, slope, spread))
+    assert shape < 1e-3 and abs(slope - 1) < 0.03 and spread < 1e-3
+    assert abs(flux.mean() / par[1:-1].sum() - 1) < 0.02
