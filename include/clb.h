@@ -97,7 +97,9 @@ enum {
  * linearly unstable for s_v < 1.19.  Call clb_params_default() first.
  */
 typedef struct clb_params {
-  int32_t nx, ny;            /* nodes including wall nodes; >= 4 on a walled axis    */
+  int32_t nx, ny;            /* nodes including wall nodes; >= 4 on a walled axis;
+                                ny * (nx rounded up to 64, or to 128 with FP16 planes)
+                                <= 2^30 (a 32768^2 domain), else CLB_ERR_ARG          */
   int32_t bc[4];             /* side kinds W, E, S, N                                */
   double bc_u[4], bc_v[4];   /* wall velocity per side (lattice units)               */
   double bc_T[4];            /* Dirichlet temperature per side                       */

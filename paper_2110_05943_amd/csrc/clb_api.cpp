@@ -105,6 +105,10 @@ extern "C" clb_status clb_derive(const clb_params *pp, clb_derived *out) {
   if ((p.bc[2] == CLB_PERIODIC) != (p.bc[3] == CLB_PERIODIC)) return CLB_ERR_ARG;
   if (walled_x(p) && p.nx < 4) return CLB_ERR_ARG;
   if (walled_y(p) && p.ny < 4) return CLB_ERR_ARG;
+  // The kernels address a plane with 32-bit element indices and 32-bit byte
+  // offsets from the plane base: at most 2^30 elements (a 32768^2 domain).
+  if (p.nx > (1 << 30) || p.ny > (1 << 30)) return CLB_ERR_ARG;
+  if ((int64_t)p.ny * pitch_of(p) > (int64_t(1) << 30)) return CLB_ERR_ARG;
   if (p.model < CLB_MODEL_CASCADED || p.model > CLB_MODEL_BGK) return CLB_ERR_ARG;
   if (p.storage != CLB_STORE_F32 && p.storage != CLB_STORE_F16 && p.storage != CLB_STORE_MIXED)
     return CLB_ERR_ARG;

@@ -171,3 +171,13 @@ def test_bgk_derivation_uses_one_rate_per_lattice():
     assert (m["s_b"], m["s3"], m["s4"]) == (1.5, 1.2, 1.8)
     with pytest.raises(B.CLBError):
         B.derive(nx=64, ny=64, Ra=1e4, Pr=0.71, model=3)
+
+
+def test_largest_domain_is_accepted_and_one_row_more_rejected():
+    # 32-bit plane addressing: ny * pitch <= 2^30 elements
+    ok = B.derive(nx=32768, ny=32768, Ra=1e6, Pr=1.0)
+    assert ok["L"] == 32767
+    with pytest.raises(B.CLBError):
+        B.derive(nx=32768, ny=32769, Ra=1e6, Pr=1.0)
+    with pytest.raises(B.CLBError):
+        B.derive(nx=2 ** 31 - 1, ny=4, Ra=1e6, Pr=1.0)
