@@ -49,9 +49,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def profile_record(key):
+    """The committed rocprofv3 counter summary of a workload's dominant step
+    kernel (HBM bytes per launch; for FP32 also VALU counts), or None when the
+    kernel source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     try:
         data = json.load(open(path))
@@ -60,7 +61,13 @@ def measured_traffic(key):
     rec = data.get(key)
     if not rec or rec.get("kernel_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the dominant step kernel, or None."""
+    rec = profile_record(key)
+    return rec.get("bytes_per_launch") if rec else None
 
 
 def build_workload(args):
@@ -639,6 +646,50 @@ def oracle_timing():
                       "rows": rows, "paper_clb_mlups_context": 3.5}), flush=True)
 
 
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9  # lane instructions per second (one wave64 op / 4 cycles / SIMD)
+FP64_PEAK_TFLOPS = 78.6
+
+
+def alu_roofline(key, nodes, step_ms, bytes_per_lu):
+    """Roofline of the two-steps-per-launch kernel, bound by VALU issue.
+
+    Peak: one wave64 VALU instruction per four cycles on each of the 1024
+    SIMDs at 2.4 GHz, i.e. 256 x 4 x 16 x 2.4e9 = 39.3e12 lane operations per
+    second.  Algorithmic work: the VALU lane operations of one node update as
+    issued by the one-step kernel on the 4096^2 cavity (which recomputes
+    nothing; SQ_INSTS_VALU x 64 per node, counted by rocprofv3), times the two
+    updates per node of a launch, over the launch time measured here.  Also
+    reported: the fraction of the issue peak this kernel really uses (its own
+    instruction count, ring recomputation included), the FP64 flop rate
+    against the FP64 vector peak, and the HBM traffic per launch."""
+    launch_s = 2 * step_ms * 1e-3
+    single = profile_record("cavity4096_f32_single") or {}
+    rec = profile_record(key) or {}
+    out = {"bound": "alu", "kernel": "step2_kernel", "steps_per_launch": 2,
+           "kernel_us": round(launch_s * 1e6, 2), "peak": round(VALU_LANE_PEAK / 1e12, 2),
+           "unit": "TOP/s (VALU lane ops)"}
+    if single.get("valu_instr_per_launch"):
+        ops_lu = single["valu_instr_per_launch"] * 64 / single["nodes"]
+        achieved = ops_lu * 2 * nodes / launch_s / 1e12
+        out.update(achieved=round(achieved, 2), frac=round(achieved * 1e12 / VALU_LANE_PEAK, 4),
+                   valu_ops_per_node_update=round(ops_lu, 1))
+    else:
+        out.update(achieved=None, frac=None)
+    out["traffic"] = rec.get("bytes_per_launch")
+    if rec.get("bytes_per_launch"):
+        out["hbm_GBps"] = round(rec["bytes_per_launch"] / launch_s / 1e9, 1)
+    if rec.get("valu_instr_per_launch"):
+        out["valu_issued_frac"] = round(rec["valu_instr_per_launch"] * 64 / launch_s
+                                        / VALU_LANE_PEAK, 4)
+    if single.get("fp64_flops_per_launch"):
+        flops_lu = single["fp64_flops_per_launch"] / single["nodes"]
+        fp64 = flops_lu * 2 * nodes / launch_s / 1e12
+        out.update(fp64_tflops=round(fp64, 2), fp64_frac=round(fp64 / FP64_PEAK_TFLOPS, 4),
+                   fp64_flops_per_node_update=round(flops_lu, 1))
+    out["bytes_per_node_update_one_step"] = bytes_per_lu
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -664,6 +715,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time launch shapes first")
     ap.add_argument("--launch", type=str, default=None, help="tile_x,tile_y,blocks")
+    ap.add_argument("--steps-per-launch", type=int, default=None, choices=(1, 2),
+                    help="time steps per launch (default: 2 for FP32 storage, else 1)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
@@ -713,6 +766,9 @@ def main():
     initial_state(s, cases)
     if args.launch:
         s.set_launch(*[int(v) for v in args.launch.split(",")])
+    if args.steps_per_launch is None:
+        args.steps_per_launch = 2 if args.storage == "f32" else 1
+    s.set_steps_per_launch(args.steps_per_launch)
     if args.autotune:
         s.autotune()
     shape = s.get_launch()
@@ -739,12 +795,20 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    kernel_ms = sum(a.elapsed_time(b) for a, b, _ in events) / K
+    kernel_ms = sum(a.elapsed_time(b) for a, b, _ in events) / K  # per time step
     nodes = sum(c["nx"] * c["ny"] for c in cases)
     bytes_per_lu = BYTES_PER_UPDATE[args.storage] + (4 if cases[0].get("eps") is not None else 0)
-    achieved = bytes_per_lu * nodes / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(key)
     mlups = nodes * K / wall / 1e6
+    if args.steps_per_launch == 2:
+        roofline = alu_roofline(key, nodes, kernel_ms, bytes_per_lu)
+    else:
+        achieved = bytes_per_lu * nodes / (kernel_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(key + "_single" if args.storage == "f32"
+                                                else key),
+                    "kernel": "step_kernel", "kernel_us": round(kernel_ms * 1e3, 2),
+                    "bytes_per_node_update": bytes_per_lu}
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -761,12 +825,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "domains": len(cases), "nodes": nodes,
                    "storage": args.storage, "launch_shape": list(shape),
+                   "steps_per_launch": args.steps_per_launch,
                    "reductions_every": REDUCE_EVERY},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "step_kernel", "kernel_us": round(kernel_ms * 1e3, 2),
-                     "bytes_per_node_update": bytes_per_lu},
+        "roofline": roofline,
         "state_check": {"res_u_max": float(max(ru)), "res_T_max": float(max(rT)),
                         "diverged": int((status != 0).sum()), "mass": float(sum(mass)),
                         "nu_first": float(nu[0])},

@@ -277,6 +277,17 @@ clb_status clb_steps_done(clb_ctx *ctx, int64_t *steps);
 clb_status clb_set_launch(clb_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t blocks);
 clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_t *blocks);
 
+/* Time steps per kernel launch: 1, or 2 (FP32 storage only, else
+ * CLB_ERR_ARG; 2 is the default for FP32 storage).  With 2, pairs of steps
+ * run in one launch while every domain is active: each 64 x 8 tile and a
+ * one-node ring around it are collided into LDS, then the tile again from
+ * there, so that the populations cross HBM once per two node updates.  The
+ * per-node arithmetic and rounding are those of single steps (the results
+ * have been bit-identical in every test).  The step that records the residual
+ * snapshot, an odd remainder, and any step while a domain is retired run
+ * singly.  Re-captures the step graphs. */
+clb_status clb_set_steps_per_launch(clb_ctx *ctx, int32_t steps);
+
 /* Time the step kernel over the candidate launch shapes on the live state
  * (which the timing runs advance) and keep the fastest.  When cache_path is
  * non-NULL the choice is read from / appended to that text file, keyed by

@@ -66,7 +66,8 @@ EXPORTS = (
     "clb_params_default", "clb_derive", "clb_workspace_bytes", "clb_create", "clb_step",
     "clb_macros", "clb_nusselt", "clb_nusselt_all", "clb_residual", "clb_residual_all",
     "clb_set_state", "clb_set_state_device", "clb_set_active", "clb_run", "clb_state_bytes", "clb_get_state", "clb_put_state",
-    "clb_steps_done", "clb_set_launch", "clb_get_launch", "clb_autotune", "clb_destroy",
+    "clb_steps_done", "clb_set_launch", "clb_get_launch", "clb_set_steps_per_launch",
+    "clb_autotune", "clb_destroy",
     "clb_strerror",
 )
 
@@ -102,6 +103,7 @@ def _lib():
             "clb_put_state": (st, [vp, vp, C.c_size_t]),
             "clb_steps_done": (st, [vp, C.POINTER(C.c_int64)]),
             "clb_set_launch": (st, [vp, C.c_int32, C.c_int32, C.c_int32]),
+            "clb_set_steps_per_launch": (st, [vp, C.c_int32]),
             "clb_get_launch": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]),
             "clb_autotune": (st, [vp, C.c_char_p]),
@@ -313,6 +315,10 @@ class Solver:
 
     def set_launch(self, tile_x, tile_y, blocks=0):
         _check(_lib().clb_set_launch(self._ctx, tile_x, tile_y, blocks), "clb_set_launch")
+
+    def set_steps_per_launch(self, steps):
+        """1 or 2 time steps per kernel launch (2: FP32 storage only)."""
+        _check(_lib().clb_set_steps_per_launch(self._ctx, int(steps)), "clb_set_steps_per_launch")
 
     def get_launch(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

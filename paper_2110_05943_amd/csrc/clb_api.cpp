@@ -188,17 +188,23 @@ extern "C" clb_status clb_derive(const clb_params *pp, clb_derived *out) {
 namespace {
 
 struct Layout {
-  size_t desc, tiles_all, tiles_active, counts, partials, gpart, results, nu, nu_local, nu_part,
-      obs;
+  size_t desc, tiles_all, tiles_active, tiles2, counts, partials, gpart, results, nu, nu_local,
+      nu_part, obs;
   std::vector<size_t> A, B, eps, arow, snap;
   size_t total;
-  size_t max_tiles, obs_elems, max_wall;
+  size_t max_tiles, max_tiles2, obs_elems, max_wall;
   int32_t max_chunks;
 };
 
 size_t max_tiles_of(const clb_params &p) {
   // smallest tile is 64 x 1
   return (size_t)((p.nx + 63) / 64) * p.ny;
+}
+
+// Tiles of the two-step kernel in one domain.
+size_t tiles2_of(const clb_params &p) {
+  return (size_t)((p.nx + clb::kFusedX - 1) / clb::kFusedX) *
+         ((p.ny + clb::kFusedY - 1) / clb::kFusedY);
 }
 
 Layout make_layout(const clb_params *p, int count) {
@@ -210,16 +216,19 @@ Layout make_layout(const clb_params *p, int count) {
     return o;
   };
   L.max_tiles = 0;
+  L.max_tiles2 = 0;
   L.obs_elems = 0;
   L.max_wall = 0;
   for (int c = 0; c < count; ++c) {
     L.max_tiles += max_tiles_of(p[c]);
+    L.max_tiles2 += tiles2_of(p[c]);
     L.obs_elems = std::max(L.obs_elems, (size_t)p[c].nx * p[c].ny);
     L.max_wall = std::max(L.max_wall, (size_t)std::max(p[c].nx, p[c].ny));
   }
   L.desc = take(sizeof(CavDesc) * count);
   L.tiles_all = take(sizeof(Tile) * L.max_tiles);
   L.tiles_active = take(sizeof(Tile) * (L.max_tiles + 8));
+  L.tiles2 = take(sizeof(Tile) * (L.max_tiles2 + 8));
   L.counts = take(sizeof(int32_t) * 4);
   L.partials = take(sizeof(double) * clb::kRed * L.max_tiles);
   L.gpart = take(sizeof(double) * clb::kRed * L.max_tiles);
@@ -263,6 +272,7 @@ struct clb_ctx {
   int storage = 0;
   int raw = 0;   // raw-moment (MRT / BGK) collision
   int rows = 0;  // some domain has a per-row acceleration
+  int fused = 0;  // two steps per launch (FP32 planes, all domains active)
   std::vector<clb_params> p;
   std::vector<clb_derived> der;
   std::vector<CavDesc> desc;
@@ -271,7 +281,8 @@ struct clb_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
   CavDesc *d_desc = nullptr;
-  Tile *d_tiles_all = nullptr, *d_tiles_active = nullptr;
+  Tile *d_tiles_all = nullptr, *d_tiles_active = nullptr, *d_tiles2 = nullptr;
+  int32_t ntiles2 = 0;  // length of the XCD-ordered two-step tile list
   int32_t *d_counts = nullptr;
   double *d_partials = nullptr, *d_gpart = nullptr, *d_results = nullptr, *d_nu = nullptr,
          *d_nu_local = nullptr, *d_nu_part = nullptr;
@@ -285,16 +296,18 @@ struct clb_ctx {
   bool snap_valid = false;
   int64_t snap_span = 1;  // steps between the snapshot and the current state
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph2[2] = {nullptr, nullptr};  // two-step launches
 };
 
 namespace {
 
 void drop_graphs(clb_ctx *c) {
-  for (auto &g : c->graph)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto *set : {c->graph, c->graph2})
+    for (int k = 0; k < 2; ++k)
+      if (set[k]) {
+        (void)hipGraphExecDestroy(set[k]);
+        set[k] = nullptr;
+      }
 }
 
 void fill_desc(const clb_params &p, const clb_derived &d, CavDesc &k) {
@@ -430,6 +443,48 @@ clb_status upload_tiles(clb_ctx *c) {
   return CLB_OK;
 }
 
+// Origin of tile i of a two-step tiling along an axis of n nodes: the last
+// tile ends at the last node (it overlaps its neighbour when n is not a
+// multiple of the tile).  The boundary reconstruction of step two gathers up
+// to three nodes inward from a wall; with the wall at the far end of its tile
+// those nodes stay inside the tile's LDS region.  Overlapping nodes are
+// computed by both tiles with identical results.
+int tile2_origin(int i, int tile, int n) { return n >= tile ? std::min(i * tile, n - tile) : 0; }
+
+// The two-step tile list: every tile of every domain, laid out for the XCDs
+// like the active list.  It does not change after creation; the two-step
+// kernel runs only while every domain is active.
+clb_status upload_tiles2(clb_ctx *c) {
+  std::vector<Tile> order;
+  for (int k = 0; k < c->count; ++k) {
+    const int nx = c->p[k].nx, ny = c->p[k].ny;
+    const int tx = (nx + clb::kFusedX - 1) / clb::kFusedX;
+    const int ty = (ny + clb::kFusedY - 1) / clb::kFusedY;
+    for (int j = 0; j < ty; ++j)
+      for (int i = 0; i < tx; ++i)
+        order.push_back(Tile{k, tile2_origin(i, clb::kFusedX, nx),
+                             tile2_origin(j, clb::kFusedY, ny), (int32_t)order.size()});
+  }
+  const size_t n = order.size(), m = (n + kXcds - 1) / kXcds;
+  std::vector<Tile> list(m * kXcds, Tile{-1, 0, 0, 0});
+  for (size_t b = 0; b < m * kXcds; ++b) {
+    const size_t t = (b % kXcds) * m + b / kXcds;
+    if (t < n) list[b] = order[t];
+  }
+  c->ntiles2 = (int32_t)list.size();
+  HIPCHK(hipMemcpyAsync(c->d_tiles2, list.data(), sizeof(Tile) * list.size(),
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CLB_OK;
+}
+
+bool fused_now(const clb_ctx *c) {
+  if (!c->fused) return false;
+  for (int k = 0; k < c->count; ++k)
+    if (!c->active[k]) return false;
+  return true;
+}
+
 bool shape_ok(int tx, int ty) {
   if (tx == 0 && ty == 0) return true;  // width chosen per domain
   if (tx != 64 && tx != 128 && tx != 256) return false;
@@ -451,20 +506,34 @@ clb_status launch_one(clb_ctx *c, int write_snap, hipStream_t s) {
   return CLB_OK;
 }
 
+clb_status launch_two(clb_ctx *c, hipStream_t s) {
+  const hipError_t e = clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts,
+                                         c->parity, 0, c->raw, c->rows, s);
+  if (e != hipSuccess) return hip_fail(e, "two-step kernel launch");
+  return CLB_OK;
+}
+
 clb_status capture_graph(clb_ctx *c, int p0) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
-  for (int k = 0; k < kGraphSteps && err == hipSuccess; ++k)
-    err = clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c), (p0 + k) & 1,
-                           0, c->storage, c->raw, c->rows, c->shape, c->cap_stream);
+  // kGraphSteps steps: single-step launches, or half as many two-step ones
+  const bool two = fused_now(c);
+  const int launches = two ? kGraphSteps / 2 : kGraphSteps;
+  for (int k = 0; k < launches && err == hipSuccess; ++k)
+    err = two ? clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts, (p0 + k) & 1,
+                                  0, c->raw, c->rows, c->cap_stream)
+              : clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c),
+                                 (p0 + k) & 1, 0, c->storage, c->raw, c->rows, c->shape,
+                                 c->cap_stream);
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (err != hipSuccess) return hip_fail(err, "graph capture launch");
   if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-  const hipError_t e3 = hipGraphInstantiate(&c->graph[p0], g, nullptr, nullptr, 0);
+  hipGraphExec_t &slot = two ? c->graph2[p0] : c->graph[p0];
+  const hipError_t e3 = hipGraphInstantiate(&slot, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e3 != hipSuccess) {
-    c->graph[p0] = nullptr;
+    slot = nullptr;
     return hip_fail(e3, "hipGraphInstantiate");
   }
   return CLB_OK;
@@ -492,6 +561,7 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->count = count;
   c->storage = p[0].storage;
   c->raw = p[0].model != CLB_MODEL_CASCADED;
+  c->fused = p[0].storage == CLB_STORE_F32;  // two steps per launch by default for FP32
   c->p.assign(p, p + count);
   for (auto &q : c->p) {  // host arrays are not kept
     c->rows |= q.a_rows != nullptr;
@@ -505,6 +575,7 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->d_desc = reinterpret_cast<CavDesc *>(c->ws + lay.desc);
   c->d_tiles_all = reinterpret_cast<Tile *>(c->ws + lay.tiles_all);
   c->d_tiles_active = reinterpret_cast<Tile *>(c->ws + lay.tiles_active);
+  c->d_tiles2 = reinterpret_cast<Tile *>(c->ws + lay.tiles2);
   c->d_counts = reinterpret_cast<int32_t *>(c->ws + lay.counts);
   c->d_partials = reinterpret_cast<double *>(c->ws + lay.partials);
   c->d_gpart = reinterpret_cast<double *>(c->ws + lay.gpart);
@@ -564,7 +635,8 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   }
   build_tiles(c);
   {
-    const clb_status s = upload_tiles(c);
+    clb_status s = upload_tiles(c);
+    if (s == CLB_OK) s = upload_tiles2(c);
     if (s != CLB_OK) return fail(s);
   }
   for (int k = 0; k < count; ++k) {
@@ -599,14 +671,21 @@ clb_status advance(clb_ctx *c, int64_t n, bool snap_first) {
     c->parity ^= 1;
   }
   int64_t rest = n - 1;  // steps besides the one that records the snapshot
+  const bool two = fused_now(c);
   while (rest > 0) {
     if (rest >= kGraphSteps) {
-      if (!c->graph[c->parity]) {
+      hipGraphExec_t &g = two ? c->graph2[c->parity] : c->graph[c->parity];
+      if (!g) {
         const clb_status s = capture_graph(c, c->parity);
         if (s != CLB_OK) return s;
       }
-      HIPCHK(hipGraphLaunch(c->graph[c->parity], c->stream));
-      rest -= kGraphSteps;  // even count: parity unchanged
+      HIPCHK(hipGraphLaunch(g, c->stream));
+      rest -= kGraphSteps;  // an even number of buffer swaps: parity unchanged
+    } else if (two && rest >= 2) {
+      const clb_status s = launch_two(c, c->stream);
+      if (s != CLB_OK) return s;
+      c->parity ^= 1;
+      rest -= 2;
     } else {
       const clb_status s = launch_one(c, 0, c->stream);
       if (s != CLB_OK) return s;
@@ -944,6 +1023,13 @@ extern "C" clb_status clb_set_launch(clb_ctx *c, int32_t tx, int32_t ty, int32_t
   c->shape = LaunchShape{tx, ty, blocks};
   build_tiles(c);
   return upload_tiles(c);
+}
+
+extern "C" clb_status clb_set_steps_per_launch(clb_ctx *c, int32_t k) {
+  if (!c || (k != 1 && k != 2) || (k == 2 && c->storage != CLB_STORE_F32)) return CLB_ERR_ARG;
+  drop_graphs(c);
+  c->fused = k == 2;
+  return CLB_OK;
 }
 
 extern "C" clb_status clb_get_launch(clb_ctx *c, int32_t *tx, int32_t *ty, int32_t *blocks) {

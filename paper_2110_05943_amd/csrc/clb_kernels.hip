@@ -57,11 +57,14 @@ __device__ __forceinline__ R ldv(const _Float16 *p) {
 // FP64 -> FP32 with stochastic rounding: 16 random bits are added below the
 // FP32 precision of the value (29 bits lie below a normal FP32 significand),
 // which is then truncated toward zero.
-__device__ __forceinline__ void stv(float *p, double v, uint32_t r) {
+__device__ __forceinline__ float round_sr(double v, uint32_t r) {
   unsigned long long u = (unsigned long long)__double_as_longlong(v);
   u += (unsigned long long)(r & 0xFFFFu) << 13;
   u &= ~((1ull << 29) - 1ull);
-  __builtin_nontemporal_store((float)__longlong_as_double((long long)u), (gptr<float>)p);
+  return (float)__longlong_as_double((long long)u);
+}
+__device__ __forceinline__ void stv(float *p, double v, uint32_t r) {
+  __builtin_nontemporal_store(round_sr(v, r), (gptr<float>)p);
 }
 // FP32 -> FP16 (scaled) with stochastic rounding: 12 random bits below the
 // FP16 precision (13 bits lie below a normal FP16 significand).
@@ -252,40 +255,117 @@ __device__ __forceinline__ void accel_at(const CavDesc &d, int y, R &ax, R &ay) 
   }
 }
 
-// Pull the post-streaming populations of node (xs, ys) and reduce them to
-// moments and macroscopic values.  (xs, ys) must have all 8 neighbours inside
-// the domain or across a periodic side.
-template <typename P, bool ROWS, typename R = typename P::R>
-__device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__restrict__ buf,
-                                               int xs, int ys, NodeState<R> &st) {
-  const int nx = d.nx, ny = d.ny, pitch = d.pitch, plane = d.plane;
-  int xm = xs - 1, xp = xs + 1, ym = ys - 1, yp = ys + 1;
-  if (d.bc[0] == kPeriodic) {
-    xm = xm < 0 ? xm + nx : xm;
-    xp = xp >= nx ? xp - nx : xp;
+// Where a gather reads populations.  GlobalSrc: the planes of a buffer in
+// global memory; (xs, ys) must have all 8 neighbours inside the domain or
+// across a periodic side, which wraps.  LdsSrc (two-step kernel): FP32
+// populations of a rectangular region held in LDS, 14 planes of kRegion
+// elements, rows kRegionW long; the region's element 0 is the node (ox, oy)
+// of the domain in unwrapped coordinates, and every neighbour read lies in
+// the region by construction of the caller.
+template <typename P>
+struct GlobalSrc {
+  const char *buf;
+
+  template <typename R>
+  __device__ __forceinline__ void pull(const CavDesc &d, int xs, int ys, R f[9], R g[5]) const {
+    const int nx = d.nx, ny = d.ny, pitch = d.pitch, plane = d.plane;
+    int xm = xs - 1, xp = xs + 1, ym = ys - 1, yp = ys + 1;
+    if (d.bc[0] == kPeriodic) {
+      xm = xm < 0 ? xm + nx : xm;
+      xp = xp >= nx ? xp - nx : xp;
+    }
+    if (d.bc[2] == kPeriodic) {
+      ym = ym < 0 ? ym + ny : ym;
+      yp = yp >= ny ? yp - ny : yp;
+    }
+    const int r0 = ys * pitch, rm = ym * pitch, rp = yp * pitch;
+    const typename P::F *A = fplanes<P>(buf);
+    const typename P::G *G = gplanes<P>(buf, plane);
+    // f_i(x) = f_i*(x - e_i), velocities of Eq. 6.
+    f[0] = ldv<R>(at(A, r0 + xs));
+    f[1] = ldv<R>(at(A + (size_t)plane, r0 + xm));
+    f[2] = ldv<R>(at(A + (size_t)2 * plane, rm + xs));
+    f[3] = ldv<R>(at(A + (size_t)3 * plane, r0 + xp));
+    f[4] = ldv<R>(at(A + (size_t)4 * plane, rp + xs));
+    f[5] = ldv<R>(at(A + (size_t)5 * plane, rm + xm));
+    f[6] = ldv<R>(at(A + (size_t)6 * plane, rm + xp));
+    f[7] = ldv<R>(at(A + (size_t)7 * plane, rp + xp));
+    f[8] = ldv<R>(at(A + (size_t)8 * plane, rp + xm));
+    g[0] = ldv<R>(at(G, r0 + xs));
+    g[1] = ldv<R>(at(G + (size_t)plane, r0 + xm));
+    g[2] = ldv<R>(at(G + (size_t)2 * plane, rm + xs));
+    g[3] = ldv<R>(at(G + (size_t)3 * plane, r0 + xp));
+    g[4] = ldv<R>(at(G + (size_t)4 * plane, rp + xs));
   }
-  if (d.bc[2] == kPeriodic) {
-    ym = ym < 0 ? ym + ny : ym;
-    yp = yp >= ny ? yp - ny : yp;
+
+  // Sum of the five pulled D2Q5 populations.
+  template <typename R>
+  __device__ __forceinline__ R gsum(const CavDesc &d, int xs, int ys) const {
+    const int nx = d.nx, ny = d.ny, pitch = d.pitch, plane = d.plane;
+    int xm = xs - 1, xp = xs + 1, ym = ys - 1, yp = ys + 1;
+    if (d.bc[0] == kPeriodic) {
+      xm = xm < 0 ? xm + nx : xm;
+      xp = xp >= nx ? xp - nx : xp;
+    }
+    if (d.bc[2] == kPeriodic) {
+      ym = ym < 0 ? ym + ny : ym;
+      yp = yp >= ny ? yp - ny : yp;
+    }
+    const typename P::G *G = gplanes<P>(buf, plane);
+    return ldv<R>(G + ys * pitch + xs) +
+           ((ldv<R>(G + plane + ys * pitch + xm) + ldv<R>(G + 3 * plane + ys * pitch + xp)) +
+            (ldv<R>(G + 2 * plane + ym * pitch + xs) + ldv<R>(G + 4 * plane + yp * pitch + xs)));
   }
-  const int r0 = ys * pitch, rm = ym * pitch, rp = yp * pitch;
-  const typename P::F *A = fplanes<P>(buf);
-  const typename P::G *G = gplanes<P>(buf, plane);
-  // f_i(x) = f_i*(x - e_i), velocities of Eq. 6.
-  const R f0 = ldv<R>(at(A, r0 + xs));
-  const R f1 = ldv<R>(at(A + (size_t)plane, r0 + xm));
-  const R f2 = ldv<R>(at(A + (size_t)2 * plane, rm + xs));
-  const R f3 = ldv<R>(at(A + (size_t)3 * plane, r0 + xp));
-  const R f4 = ldv<R>(at(A + (size_t)4 * plane, rp + xs));
-  const R f5 = ldv<R>(at(A + (size_t)5 * plane, rm + xm));
-  const R f6 = ldv<R>(at(A + (size_t)6 * plane, rm + xp));
-  const R f7 = ldv<R>(at(A + (size_t)7 * plane, rp + xp));
-  const R f8 = ldv<R>(at(A + (size_t)8 * plane, rp + xm));
-  const R g0 = ldv<R>(at(G, r0 + xs));
-  const R g1 = ldv<R>(at(G + (size_t)plane, r0 + xm));
-  const R g2 = ldv<R>(at(G + (size_t)2 * plane, rm + xs));
-  const R g3 = ldv<R>(at(G + (size_t)3 * plane, r0 + xp));
-  const R g4 = ldv<R>(at(G + (size_t)4 * plane, rp + xs));
+};
+
+constexpr int kRegionW = kFusedX + 2;             // the two-step tile plus a one-node ring
+constexpr int kRegion = kRegionW * (kFusedY + 2);
+
+struct LdsSrc {
+  const float *lds;
+  int ox, oy;
+
+  template <typename R>
+  __device__ __forceinline__ void pull(const CavDesc &, int xs, int ys, R f[9], R g[5]) const {
+    const int c = (ys - oy) * kRegionW + (xs - ox);
+    const int W = kRegionW;
+    f[0] = (R)lds[c];
+    f[1] = (R)lds[kRegion + c - 1];
+    f[2] = (R)lds[2 * kRegion + c - W];
+    f[3] = (R)lds[3 * kRegion + c + 1];
+    f[4] = (R)lds[4 * kRegion + c + W];
+    f[5] = (R)lds[5 * kRegion + c - W - 1];
+    f[6] = (R)lds[6 * kRegion + c - W + 1];
+    f[7] = (R)lds[7 * kRegion + c + W + 1];
+    f[8] = (R)lds[8 * kRegion + c + W - 1];
+    g[0] = (R)lds[9 * kRegion + c];
+    g[1] = (R)lds[10 * kRegion + c - 1];
+    g[2] = (R)lds[11 * kRegion + c - W];
+    g[3] = (R)lds[12 * kRegion + c + 1];
+    g[4] = (R)lds[13 * kRegion + c + W];
+  }
+
+  template <typename R>
+  __device__ __forceinline__ R gsum(const CavDesc &, int xs, int ys) const {
+    const int c = (ys - oy) * kRegionW + (xs - ox);
+    const int W = kRegionW;
+    return (R)lds[9 * kRegion + c] +
+           (((R)lds[10 * kRegion + c - 1] + (R)lds[12 * kRegion + c + 1]) +
+            ((R)lds[11 * kRegion + c - W] + (R)lds[13 * kRegion + c + W]));
+  }
+};
+
+// Pull the post-streaming populations of node (xs, ys) from `src` and reduce
+// them to moments and macroscopic values.
+template <typename P, bool ROWS, typename Src, typename R = typename P::R>
+__device__ __forceinline__ void gather_moments(const CavDesc &d, const Src &src, int xs, int ys,
+                                               NodeState<R> &st) {
+  R fv[9], gv[5];
+  src.template pull<R>(d, xs, ys, fv, gv);
+  const R f0 = fv[0], f1 = fv[1], f2 = fv[2], f3 = fv[3], f4 = fv[4], f5 = fv[5], f6 = fv[6],
+          f7 = fv[7], f8 = fv[8];
+  const R g0 = gv[0], g1 = gv[1], g2 = gv[2], g3 = gv[3], g4 = gv[4];
+  const int r0 = ys * d.pitch;
 
   // raw moments (Eq. 7 on Eq. 6), as deviations
   const R p13 = f1 + f3, m13 = f1 - f3, p24 = f2 + f4, m24 = f2 - f4;
@@ -331,24 +411,9 @@ __device__ __forceinline__ void gather_moments(const CavDesc &d, const char *__r
 }
 
 // theta at node (xs, ys) from its post-streaming D2Q5 populations.
-template <typename P, typename R = typename P::R>
-__device__ __forceinline__ R gather_theta(const CavDesc &d, const char *__restrict__ buf, int xs,
-                                          int ys) {
-  const int nx = d.nx, ny = d.ny, pitch = d.pitch, plane = d.plane;
-  int xm = xs - 1, xp = xs + 1, ym = ys - 1, yp = ys + 1;
-  if (d.bc[0] == kPeriodic) {
-    xm = xm < 0 ? xm + nx : xm;
-    xp = xp >= nx ? xp - nx : xp;
-  }
-  if (d.bc[2] == kPeriodic) {
-    ym = ym < 0 ? ym + ny : ym;
-    yp = yp >= ny ? yp - ny : yp;
-  }
-  const typename P::G *G = gplanes<P>(buf, plane);
-  const R s = ldv<R>(G + ys * pitch + xs) +
-              ((ldv<R>(G + plane + ys * pitch + xm) + ldv<R>(G + 3 * plane + ys * pitch + xp)) +
-               (ldv<R>(G + 2 * plane + ym * pitch + xs) + ldv<R>(G + 4 * plane + yp * pitch + xs)));
-  return s * cst<R>(d).isig;
+template <typename P, typename Src, typename R = typename P::R>
+__device__ __forceinline__ R gather_theta(const CavDesc &d, const Src &src, int xs, int ys) {
+  return src.template gsum<R>(d, xs, ys) * cst<R>(d).isig;
 }
 
 // Macroscopic state of node (x, y) ready for the collision.  Boundary nodes
@@ -358,9 +423,9 @@ __device__ __forceinline__ R gather_theta(const CavDesc &d, const char *__restri
 // phi_f), which is M applied to f_i^eq(b) + [f_i(x_f) - f_i^eq(x_f)], and
 // likewise for the D2Q5 moments with Eq. 33.  The node then collides with
 // (rho_b, u_b, T_b).  Returns true for boundary nodes.
-template <typename P, bool ROWS, typename R = typename P::R>
-__device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restrict__ A, int x,
-                                           int y, NodeState<R> &st) {
+template <typename P, bool ROWS, typename Src, typename R = typename P::R>
+__device__ __forceinline__ bool node_state(const CavDesc &d, const Src &A, int x, int y,
+                                           NodeState<R> &st) {
   int sx = -1, sy = -1, dx = 0, dy = 0;
   if (x == 0 && d.bc[0] != kPeriodic) {
     sx = 0;
@@ -444,12 +509,10 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const char *__restr
 }
 
 // Collide one node in central-moment space (RAW: in raw-moment space, the
-// MRT form with N = N_T = I) and store the post-collision deviations to the
-// planes of B at element offset idx.
+// MRT form with N = N_T = I): the 14 post-collision deviations, D2Q9 first.
 template <typename P, bool RAW, bool ROWS, typename R = typename P::R>
-__device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<R> &st, bool wall,
-                                              char *__restrict__ buf, int idx, uint32_t seed) {
-  const int plane = d.plane;
+__device__ __forceinline__ void collide(const CavDesc &d, const NodeState<R> &st, bool wall,
+                                        R out[kPlanes]) {
   const R rho = st.rho, ux = st.ux, uy = st.uy, ip = st.ip, dr = st.dr;
   const R jx = st.jx, jy = st.jy;
   const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
@@ -580,7 +643,28 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
   // (sigma - varpi) theta - |u|^2 T - 2 u.q - e3 - e4)
   const R g0 = st.sg - ((g1 + g3) + (g2 + g4));
 
-  const R out[kPlanes] = {f0, f1, f2, f3, f4, f5, f6, f7, f8, g0, g1, g2, g3, g4};
+  out[0] = f0;
+  out[1] = f1;
+  out[2] = f2;
+  out[3] = f3;
+  out[4] = f4;
+  out[5] = f5;
+  out[6] = f6;
+  out[7] = f7;
+  out[8] = f8;
+  out[9] = g0;
+  out[10] = g1;
+  out[11] = g2;
+  out[12] = g3;
+  out[13] = g4;
+}
+
+// Store post-collision deviations to the planes of `buf` at element offset
+// idx, stochastically rounded with random words of (idx, seed).
+template <typename P, typename R = typename P::R>
+__device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlanes],
+                                             char *__restrict__ buf, int idx, uint32_t seed) {
+  const int plane = d.plane;
   typename P::F *of = const_cast<typename P::F *>(fplanes<P>(buf));
   typename P::G *og = const_cast<typename P::G *>(gplanes<P>(buf, plane));
   const uint32_t uidx = (uint32_t)idx;
@@ -595,6 +679,26 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
           (i & 1) ? (w >> 16) : w);
     if (i & 1) w = next_bits<R>(w);
   }
+}
+
+// The same rounding into FP32 values (the two-step kernel's LDS region at
+// element c), identical to what store_planes writes for FP32 planes.
+__device__ __forceinline__ void store_region(const double out[kPlanes], float *lds, int c,
+                                             int idx, uint32_t seed) {
+  uint32_t w = mix32((uint32_t)idx + seed);
+#pragma unroll
+  for (int i = 0; i < kPlanes; ++i) {
+    lds[i * kRegion + c] = round_sr(out[i], (i & 1) ? (w >> 16) : w);
+    if (i & 1) w = next_bits<double>(w);
+  }
+}
+
+template <typename P, bool RAW, bool ROWS, typename R = typename P::R>
+__device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<R> &st, bool wall,
+                                              char *__restrict__ buf, int idx, uint32_t seed) {
+  R out[kPlanes];
+  collide<P, RAW, ROWS>(d, st, wall, out);
+  store_planes<P>(d, out, buf, idx, seed);
 }
 
 // ------------------------------------------------------------ step kernel
@@ -625,7 +729,7 @@ __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ d
       const char *A = parity ? d.B : d.A;
       char *B = parity ? d.A : d.B;
       NodeState<R> st;
-      const bool wall = node_state<P, ROWS>(d, A, x, y, st);
+      const bool wall = node_state<P, ROWS>(d, GlobalSrc<P>{A}, x, y, st);
       const int idx = y * d.pitch + x;
       const uint32_t seed = mix32(step * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
       collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed);
@@ -635,6 +739,68 @@ __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ d
         d.snap[2 * d.plane + idx] = (float)st.th;
       }
     }
+  }
+}
+
+// ------------------------------------------------------- two-step kernel
+
+// Two time steps of every tile of a two-step tile list (kFusedX x kFusedY
+// nodes) in one launch, FP32 planes.  Step one collides the tile and a
+// one-node ring around it from the source buffer into LDS, rounded exactly as
+// a stored step would be; step two collides the tile again from LDS and
+// stores it to the other buffer.  The populations cross HBM once per two node
+// updates; each ring is recomputed by the neighbouring tiles.  The region is
+// in unwrapped coordinates: the ring of a tile at a periodic side holds the
+// wrapped neighbours, and ring nodes outside a walled side are neither
+// computed nor read (boundary nodes gather inward).  counts[2 + parity]
+// holds the index of the first step; the kernel passes step + 2 on.
+template <bool RAW, bool ROWS>
+__global__ void __launch_bounds__(256) step2_kernel(const CavDesc *__restrict__ descs,
+                                                    const Tile *__restrict__ tiles, int ntiles,
+                                                    int32_t *__restrict__ counts, int parity,
+                                                    int write_snap) {
+  using P = StoreF32;
+  __shared__ float lds[kPlanes * kRegion];
+  const uint32_t step = (uint32_t)counts[2 + parity];
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[3 - parity] = (int32_t)(step + 2);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int cav = __builtin_amdgcn_readfirstlane(tiles[t].cav);
+    if (cav < 0) continue;  // padding entry of the XCD-ordered list
+    const int x0 = __builtin_amdgcn_readfirstlane(tiles[t].x0);
+    const int y0 = __builtin_amdgcn_readfirstlane(tiles[t].y0);
+    const CavDesc &d = descs[cav];
+    const char *A = parity ? d.B : d.A;
+    char *B = parity ? d.A : d.B;
+    const bool wrap_x = d.bc[0] == kPeriodic, wrap_y = d.bc[2] == kPeriodic;
+    const uint32_t seed1 = mix32(step * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
+    for (int c = threadIdx.x; c < kRegion; c += blockDim.x) {
+      int x = x0 - 1 + c % kRegionW, y = y0 - 1 + c / kRegionW;
+      if (wrap_x) x = x < 0 ? x + d.nx : (x >= d.nx ? x - d.nx : x);
+      if (wrap_y) y = y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y);
+      if (x < 0 || x >= d.nx || y < 0 || y >= d.ny) continue;
+      NodeState<double> st;
+      const bool wall = node_state<P, ROWS>(d, GlobalSrc<P>{A}, x, y, st);
+      double out[kPlanes];
+      collide<P, RAW, ROWS>(d, st, wall, out);
+      store_region(out, lds, c, y * d.pitch + x, seed1);
+    }
+    __syncthreads();
+    const uint32_t seed2 = mix32((step + 1) * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
+    const LdsSrc src{lds, x0 - 1, y0 - 1};
+    for (int q = threadIdx.x; q < kFusedX * kFusedY; q += blockDim.x) {
+      const int x = x0 + q % kFusedX, y = y0 + q / kFusedX;
+      if (x >= d.nx || y >= d.ny) continue;
+      NodeState<double> st;
+      const bool wall = node_state<P, ROWS>(d, src, x, y, st);
+      const int idx = y * d.pitch + x;
+      collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed2);
+      if (write_snap) {
+        d.snap[idx] = (float)st.ux;
+        d.snap[d.plane + idx] = (float)st.uy;
+        d.snap[2 * d.plane + idx] = (float)st.th;
+      }
+    }
+    __syncthreads();  // the next tile overwrites the region
   }
 }
 
@@ -766,7 +932,7 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
   if (x < d.nx && y < d.ny) {
     const char *A = parity ? d.B : d.A;
     NodeState<R> st;
-    node_state<P, true>(d, A, x, y, st);
+    node_state<P, true>(d, GlobalSrc<P>{A}, x, y, st);
     const int idx = y * d.pitch + x;
     // the snapshot holds FP32 values: compare like with like
     const double ux = (double)(float)st.ux, uy = (double)(float)st.uy, th = (double)(float)st.th;
@@ -841,7 +1007,7 @@ __global__ void __launch_bounds__(512) macros_kernel(const CavDesc *__restrict__
   if (x >= d.nx || y >= d.ny) return;
   const char *A = parity ? d.B : d.A;
   NodeState<R> st;
-  node_state<P, true>(d, A, x, y, st);
+  node_state<P, true>(d, GlobalSrc<P>{A}, x, y, st);
   const int n = d.nx * d.ny, k = y * d.nx + x;
   out[k] = (float)st.dr;
   out[n + k] = (float)st.ux;
@@ -882,7 +1048,7 @@ __global__ void __launch_bounds__(256) nusselt_kernel(const CavDesc *__restrict_
         y = side == 2 ? k : d.ny - 1 - k;
       }
       NodeState<R> st;
-      node_state<P, true>(d, A, x, y, st);
+      node_state<P, true>(d, GlobalSrc<P>{A}, x, y, st);
       t[k] = (double)st.th;  // the gradient does not depend on the reference T0
     }
     const double nu = -L * sign * (-3.0 * t[0] + 4.0 * t[1] - t[2]) * 0.5 / d.c.dT;
@@ -945,6 +1111,25 @@ hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
       hipLaunchKernelGGL((step_kernel<P, false, false>), grid, block, 0, s, descs, tiles,
                          counts, parity, write_snap);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
+                        int parity, int write_snap, int raw, int rows, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const dim3 grid(ntiles), block(256);
+  if (raw && rows)
+    hipLaunchKernelGGL((step2_kernel<true, true>), grid, block, 0, s, descs, tiles, ntiles, counts,
+                       parity, write_snap);
+  else if (raw)
+    hipLaunchKernelGGL((step2_kernel<true, false>), grid, block, 0, s, descs, tiles, ntiles,
+                       counts, parity, write_snap);
+  else if (rows)
+    hipLaunchKernelGGL((step2_kernel<false, true>), grid, block, 0, s, descs, tiles, ntiles,
+                       counts, parity, write_snap);
+  else
+    hipLaunchKernelGGL((step2_kernel<false, false>), grid, block, 0, s, descs, tiles, ntiles,
+                       counts, parity, write_snap);
   return hipGetLastError();
 }
 

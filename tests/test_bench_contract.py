@@ -20,9 +20,28 @@ def test_traffic_summary_matches_the_kernel_source():
     import bench
     data = json.load(open(os.path.join(ROOT, "profiles", "step_kernel_traffic.json")))
     h = bench.kernel_source_hash()
-    for key in ("cavity4096_f32", "cavity4096_f16", "cavity4096_mixed", "batch256_f32",
-                "channel2048_f32"):
+    for key in ("cavity4096_f32", "cavity4096_f32_single", "cavity4096_f16", "cavity4096_mixed",
+                "batch256_f32", "channel2048_f32"):
         assert data[key]["kernel_hash"] == h, key
         t = bench.measured_traffic(key)
-        assert t is not None and 1.0 <= t / data[key]["algorithmic_bytes"] < 1.1, key
+        # one step per launch: close to the populations read and written once;
+        # two: the ring of every tile is read again (mostly from L2)
+        hi = 1.1 if data[key]["steps_per_launch"] == 1 else 1.5
+        assert t is not None and 1.0 <= t / data[key]["algorithmic_bytes"] < hi, key
         assert os.path.exists(os.path.join(ROOT, "profiles", "step_kernel_%s.md" % key))
+    # the FP32 records of the default launch mode come from the two-step
+    # kernel, the "single" one from the one-step kernel
+    for key in ("cavity4096_f32", "batch256_f32", "channel2048_f32"):
+        assert data[key]["steps_per_launch"] == 2 and "step2_kernel" in data[key]["kernel"], key
+    one, two = data["cavity4096_f32_single"], data["cavity4096_f32"]
+    assert one["steps_per_launch"] == 1 and "step2_kernel" not in one["kernel"]
+    # the work of one node update, counted on the one-step kernel; the two-step
+    # kernel issues more per update (it also updates each tile's ring)
+    assert one["fp64_flops_per_launch"] > 0 and one["valu_instr_per_launch"] > 0
+    per_lu_one = one["valu_instr_per_launch"] / one["nodes"]
+    per_lu_two = two["valu_instr_per_launch"] / (2 * two["nodes"])
+    assert 1.0 < per_lu_two / per_lu_one < 660 / 512 + 0.05
+    # the roofline of the measured launch time stays below the issue peak
+    r = bench.alu_roofline("cavity4096_f32", two["nodes"], two["avg_launch_us"] / 2e3, 112)
+    assert 0 < r["frac"] <= r["valu_issued_frac"] < 1
+    assert r["traffic"] == two["bytes_per_launch"] and 0 < r["fp64_frac"] < 1

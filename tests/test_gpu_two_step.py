@@ -1,0 +1,136 @@
+"""GPU: two time steps per launch (clb_set_steps_per_launch(ctx, 2), FP32
+storage) against single steps on the same inputs, over every side kind, the
+porosity field, the per-row acceleration, the raw-moment collision, ragged
+domains narrower and wider than the 64 x 8 tiles, and retirement in clb_run;
+and against the FP64 oracle.  The two paths run the same per-node code on the
+same stored values, so they agree to the last bits (asserted within 1e-12
+relative; bit equality is logged)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2110_05943_amd import inputs, workloads
+from tests.cases import cavity, oracle_lattice, rel_l2, vel_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "needs the MI355X"
+    import paper_2110_05943_amd._binding as b
+    return b
+
+
+def hetero_periodic(nx, ny):
+    eps = inputs.porosity_map(nx, ny, ell=8, seed=7, eps_min=0.3, eps_max=0.9)
+    dp = inputs.particle_diameter_for_mean_Da(eps, 1e-2, nx - 1)
+    return dict(nx=nx, ny=ny, bc=("periodic",) * 4, eps=eps, dp=dp, F_phi=-1.0, Ra=1e4, Pr=0.71,
+                sigma=0.9, scaling="cavity")
+
+
+def make_cases(name):
+    """The domains of one case (built inside the test: the workloads call the
+    library's parameter derivation)."""
+    return {
+        "cavity 97x70": lambda: [cavity(97, ny=70, Ra=1e5, Da=1e-3, phi=0.45, sigma=1.15)],
+        "cavity 65x9 (one-column and one-row last tiles)": lambda: [cavity(65, ny=9, Ra=1e4,
+                                                                           Da=1e-2)],
+        "small cavity 5x4": lambda: [cavity(5, ny=4, Ra=1e3, Da=1e-2)],
+        "periodic porosity map 96x80": lambda: [hetero_periodic(96, 80)],
+        "periodic narrow 3x17 channel with rows": lambda: [workloads.paper_channel(17, nx=3,
+                                                                                   Re=5.0)],
+        "inlet/outlet with porosity map": lambda: [workloads.hetero_channel(130, 41, ell=4,
+                                                                            seed=2)],
+        "mrt batch": lambda: [cavity(64, Ra=1e4, model="mrt"),
+                              cavity(70, ny=33, Ra=1e5, model="mrt")],
+        "batch of four": lambda: [cavity(64, Ra=1e4), cavity(129, ny=66, Ra=1e5, Da=1e-3, phi=0.4),
+                                  hetero_periodic(40, 24), workloads.paper_channel(33, nx=8)],
+    }[name]()
+
+
+CASE_NAMES = ["cavity 97x70", "cavity 65x9 (one-column and one-row last tiles)",
+              "small cavity 5x4", "periodic porosity map 96x80",
+              "periodic narrow 3x17 channel with rows", "inlet/outlet with porosity map",
+              "mrt batch", "batch of four"]
+
+
+def start(s, cases):
+    for k, c in enumerate(cases):
+        if "inlet_U" in c and c.get("bc", ("",))[0] == "inlet":
+            continue  # the channel starts from its own initial state
+        u, v, T = inputs.random_fields(c["nx"], c["ny"], seed=3 + k, u_amp=0.01, T_amp=0.2)
+        s.set_state(k, T, u, v)
+
+
+@pytest.mark.parametrize("name", CASE_NAMES)
+def test_two_step_launches_match_single_steps(B, name):
+    cases = make_cases(name)
+    log(name)
+    runs = []
+    for k in (1, 2):
+        s = B.Solver(cases)
+        s.set_steps_per_launch(k)
+        start(s, cases)
+        s.step(1)
+        s.step(77)   # odd: pairs plus a single step, graphs of 32
+        s.step(64)
+        runs.append(s)
+    a, b = runs
+    for i, c in enumerate(cases):
+        ma, mb = a.macros(i), b.macros(i)
+        d = max(vel_rel_l2(mb, ma), rel_l2(mb["T"], ma["T"]), rel_l2(mb["rho"] - 1, ma["rho"] - 1))
+        same = all(np.array_equal(ma[k], mb[k]) for k in ma)
+        log("  domain %d (%dx%d): max rel-L2 difference %.2e, bit-identical %s"
+            % (i, c["nx"], c["ny"], d, same))
+        assert d <= 1e-12
+    ra, rb = a.residual_all(), b.residual_all()
+    assert np.allclose(ra[0], rb[0], rtol=1e-9, atol=0) and np.allclose(ra[2], rb[2], rtol=1e-12)
+    assert a.steps_done == b.steps_done == 142
+
+
+def test_two_step_launches_match_oracle(B):
+    case = cavity(64, Ra=1e3, Da=1e-2, phi=0.6)
+    T = inputs.cavity_initial_T(64, seed=1)
+    s = B.Solver(case)
+    s.set_steps_per_launch(2)
+    s.set_state(0, T)
+    lat = oracle_lattice(case)
+    lat.init_equilibrium(T)
+    s.step(5000)
+    lat.step(5000)
+    g, o = s.macros(), lat.macros()
+    eu, eT = vel_rel_l2(g, o), rel_l2(g["T"], o["T"])
+    log("two-step cavity 64, 5000 steps: rel-L2 u %.2e T %.2e" % (eu, eT))
+    assert eu <= 1e-6 and eT <= 1e-6
+    assert abs(s.nusselt(0, 0) - lat.nusselt(0)) <= 1e-4
+
+
+def test_two_step_run_with_retirement_matches(B):
+    cases = [cavity(32, Ra=1e3, Da=1e-2), cavity(48, Ra=1e4, Da=1e-2)]
+    out = []
+    for k in (1, 2):
+        s = B.Solver(cases)
+        s.set_steps_per_launch(k)
+        for i in range(2):
+            s.set_state(i, inputs.cavity_initial_T(cases[i]["nx"], seed=1))
+        r = s.run(60000, check_every=1000, tol=1e-6)
+        out.append((r["steps"].copy(), s.macros(1)["T"]))
+    log("steps single %s two-step %s" % (out[0][0], out[1][0]))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert rel_l2(out[1][1], out[0][1]) <= 1e-12
+
+
+def test_two_steps_need_fp32_storage(B):
+    s = B.Solver(cavity(32, Ra=1e3, storage="f16"))
+    with pytest.raises(B.CLBError):
+        s.set_steps_per_launch(2)
+    with pytest.raises(B.CLBError):
+        s.set_steps_per_launch(3)
