@@ -201,7 +201,8 @@ size_t max_tiles_of(const clb_params &p) {
   return (size_t)((p.nx + 63) / 64) * p.ny;
 }
 
-// Tiles of the two-step kernel in one domain.
+// Tiles of the two-step kernel in one domain (the narrow tiles: an upper
+// bound for either width).
 size_t tiles2_of(const clb_params &p) {
   return (size_t)((p.nx + clb::kFusedX - 1) / clb::kFusedX) *
          ((p.ny + clb::kFusedY - 1) / clb::kFusedY);
@@ -283,6 +284,7 @@ struct clb_ctx {
   CavDesc *d_desc = nullptr;
   Tile *d_tiles_all = nullptr, *d_tiles_active = nullptr, *d_tiles2 = nullptr;
   int32_t ntiles2 = 0;  // length of the XCD-ordered two-step tile list
+  int tile2_x = clb::kFusedX;  // two-step tile width: 128 when every domain is that wide
   int32_t *d_counts = nullptr;
   double *d_partials = nullptr, *d_gpart = nullptr, *d_results = nullptr, *d_nu = nullptr,
          *d_nu_local = nullptr, *d_nu_part = nullptr;
@@ -458,11 +460,12 @@ clb_status upload_tiles2(clb_ctx *c) {
   std::vector<Tile> order;
   for (int k = 0; k < c->count; ++k) {
     const int nx = c->p[k].nx, ny = c->p[k].ny;
-    const int tx = (nx + clb::kFusedX - 1) / clb::kFusedX;
+    const int w = c->tile2_x;
+    const int tx = (nx + w - 1) / w;
     const int ty = (ny + clb::kFusedY - 1) / clb::kFusedY;
     for (int j = 0; j < ty; ++j)
       for (int i = 0; i < tx; ++i)
-        order.push_back(Tile{k, tile2_origin(i, clb::kFusedX, nx),
+        order.push_back(Tile{k, tile2_origin(i, w, nx),
                              tile2_origin(j, clb::kFusedY, ny), (int32_t)order.size()});
   }
   const size_t n = order.size(), m = (n + kXcds - 1) / kXcds;
@@ -508,7 +511,7 @@ clb_status launch_one(clb_ctx *c, int write_snap, hipStream_t s) {
 
 clb_status launch_two(clb_ctx *c, hipStream_t s) {
   const hipError_t e = clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts,
-                                         c->parity, 0, c->raw, c->rows, s);
+                                         c->parity, 0, c->raw, c->rows, c->tile2_x, s);
   if (e != hipSuccess) return hip_fail(e, "two-step kernel launch");
   return CLB_OK;
 }
@@ -522,7 +525,7 @@ clb_status capture_graph(clb_ctx *c, int p0) {
   const int launches = two ? kGraphSteps / 2 : kGraphSteps;
   for (int k = 0; k < launches && err == hipSuccess; ++k)
     err = two ? clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts, (p0 + k) & 1,
-                                  0, c->raw, c->rows, c->cap_stream)
+                                  0, c->raw, c->rows, c->tile2_x, c->cap_stream)
               : clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c),
                                  (p0 + k) & 1, 0, c->storage, c->raw, c->rows, c->shape,
                                  c->cap_stream);
@@ -562,6 +565,11 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->storage = p[0].storage;
   c->raw = p[0].model != CLB_MODEL_CASCADED;
   c->fused = p[0].storage == CLB_STORE_F32;  // two steps per launch by default for FP32
+  // 128-wide two-step tiles (fewer partly used cache lines at the tile
+  // edges) when no domain would leave most of such a tile idle
+  c->tile2_x = clb::kFusedXWide;
+  for (int k = 0; k < count; ++k)
+    if (p[k].nx < clb::kFusedXWide) c->tile2_x = clb::kFusedX;
   c->p.assign(p, p + count);
   for (auto &q : c->p) {  // host arrays are not kept
     c->rows |= q.a_rows != nullptr;

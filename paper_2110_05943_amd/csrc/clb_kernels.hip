@@ -140,27 +140,27 @@ __device__ __forceinline__ uint32_t next_bits(uint32_t x) {
 
 // ------------------------------------------------------- fast FP64 helpers
 
-// 1/x and sqrt(x) in FP64 from the hardware FP32 estimates refined by two
-// Newton steps (each doubles the number of correct bits: 23 -> 46 -> 92), a
-// fraction of the instructions of the IEEE FP64 division and square-root
-// sequences.  rcp64 is used for values of order one (rho, the porosity, the
-// velocity denominator of Eq. 23); sqrt64 takes the IEEE path for arguments below
+// 1/x and sqrt(x) in FP64 from the hardware FP32 estimates refined by one
+// Newton step.  The estimates are good to about one FP32 unit (2^-23); one
+// step squares the relative error to about 2^-46 (1e-14), eight orders of
+// magnitude below the FP32 rounding of the stored populations, at a fraction
+// of the instructions of the IEEE FP64 division and square-root sequences.
+// rcp64 is used for values of order one (rho, the porosity, the velocity
+// denominator of Eq. 23); sqrt64 takes the IEEE path for arguments below
 // 1e-30, whose FP32 image would be zero or subnormal.  The FP32 overloads
 // (FP16 and mixed storage, which compute in FP32) take the hardware
 // estimates directly: their error, about one FP32 unit, is of the order of
 // the FP32 arithmetic itself.
 __device__ __forceinline__ double rcp64(double x) {
-  double r = (double)__builtin_amdgcn_rcpf((float)x);
-  r = r * (2.0 - x * r);
+  const double r = (double)__builtin_amdgcn_rcpf((float)x);
   return r * (2.0 - x * r);
 }
 __device__ __forceinline__ float rcp64(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double sqrt64(double x) {
   if (!(x > 1e-30)) return sqrt(x);
-  double y = (double)__builtin_amdgcn_rsqf((float)x);
-  y = y * (1.5 - 0.5 * x * y * y);
-  y = y * (1.5 - 0.5 * x * y * y);
-  return x * y;
+  const double y = (double)__builtin_amdgcn_rsqf((float)x);
+  const double s = x * y;  // sqrt(x) (1 + e); Newton on 1/sqrt folded into s
+  return s * (1.5 - 0.5 * s * y);
 }
 __device__ __forceinline__ float sqrt64(float x) { return __builtin_amdgcn_sqrtf(x); }
 
@@ -318,10 +318,16 @@ struct GlobalSrc {
   }
 };
 
-constexpr int kRegionW = kFusedX + 2;             // the two-step tile plus a one-node ring
-constexpr int kRegion = kRegionW * (kFusedY + 2);
+// The LDS region of a two-step tile TX x kFusedY: the tile plus a one-node ring.
+template <int TX>
+struct Region {
+  static constexpr int W = TX + 2;
+  static constexpr int N = W * (kFusedY + 2);
+};
 
+template <int TX>
 struct LdsSrc {
+  static constexpr int kRegionW = Region<TX>::W, kRegion = Region<TX>::N;
   const float *lds;
   int ox, oy;
 
@@ -683,12 +689,13 @@ __device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlan
 
 // The same rounding into FP32 values (the two-step kernel's LDS region at
 // element c), identical to what store_planes writes for FP32 planes.
+template <int TX>
 __device__ __forceinline__ void store_region(const double out[kPlanes], float *lds, int c,
                                              int idx, uint32_t seed) {
   uint32_t w = mix32((uint32_t)idx + seed);
 #pragma unroll
   for (int i = 0; i < kPlanes; ++i) {
-    lds[i * kRegion + c] = round_sr(out[i], (i & 1) ? (w >> 16) : w);
+    lds[i * Region<TX>::N + c] = round_sr(out[i], (i & 1) ? (w >> 16) : w);
     if (i & 1) w = next_bits<double>(w);
   }
 }
@@ -709,7 +716,7 @@ __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<
 // step; the kernel passes it on in counts[3 - parity] for the next launch, so
 // captured graphs need no baked-in step numbers.
 template <typename P, bool RAW, bool ROWS>
-__global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ descs,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) step_kernel(const CavDesc *__restrict__ descs,
                                                    const Tile *__restrict__ tiles,
                                                    int32_t *__restrict__ counts, int parity,
                                                    int write_snap) {
@@ -744,8 +751,9 @@ __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ d
 
 // ------------------------------------------------------- two-step kernel
 
-// Two time steps of every tile of a two-step tile list (kFusedX x kFusedY
-// nodes) in one launch, FP32 planes.  Step one collides the tile and a
+// Two time steps of every tile of a two-step tile list (TX x kFusedY nodes,
+// TX = 64 or 128, 4 TX threads: four waves per SIMD either way, as LDS
+// allows) in one launch, FP32 planes.  Step one collides the tile and a
 // one-node ring around it from the source buffer into LDS, rounded exactly as
 // a stored step would be; step two collides the tile again from LDS and
 // stores it to the other buffer.  The populations cross HBM once per two node
@@ -754,12 +762,13 @@ __global__ void __launch_bounds__(512) step_kernel(const CavDesc *__restrict__ d
 // wrapped neighbours, and ring nodes outside a walled side are neither
 // computed nor read (boundary nodes gather inward).  counts[2 + parity]
 // holds the index of the first step; the kernel passes step + 2 on.
-template <bool RAW, bool ROWS>
-__global__ void __launch_bounds__(256) step2_kernel(const CavDesc *__restrict__ descs,
-                                                    const Tile *__restrict__ tiles, int ntiles,
-                                                    int32_t *__restrict__ counts, int parity,
-                                                    int write_snap) {
+template <int TX, bool RAW, bool ROWS>
+__global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict__ descs,
+                                                       const Tile *__restrict__ tiles, int ntiles,
+                                                       int32_t *__restrict__ counts, int parity,
+                                                       int write_snap) {
   using P = StoreF32;
+  constexpr int kRegionW = Region<TX>::W, kRegion = Region<TX>::N;
   __shared__ float lds[kPlanes * kRegion];
   const uint32_t step = (uint32_t)counts[2 + parity];
   if (blockIdx.x == 0 && threadIdx.x == 0) counts[3 - parity] = (int32_t)(step + 2);
@@ -782,13 +791,13 @@ __global__ void __launch_bounds__(256) step2_kernel(const CavDesc *__restrict__ 
       const bool wall = node_state<P, ROWS>(d, GlobalSrc<P>{A}, x, y, st);
       double out[kPlanes];
       collide<P, RAW, ROWS>(d, st, wall, out);
-      store_region(out, lds, c, y * d.pitch + x, seed1);
+      store_region<TX>(out, lds, c, y * d.pitch + x, seed1);
     }
     __syncthreads();
     const uint32_t seed2 = mix32((step + 1) * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
-    const LdsSrc src{lds, x0 - 1, y0 - 1};
-    for (int q = threadIdx.x; q < kFusedX * kFusedY; q += blockDim.x) {
-      const int x = x0 + q % kFusedX, y = y0 + q / kFusedX;
+    const LdsSrc<TX> src{lds, x0 - 1, y0 - 1};
+    for (int q = threadIdx.x; q < TX * kFusedY; q += blockDim.x) {
+      const int x = x0 + q % TX, y = y0 + q / TX;
       if (x >= d.nx || y >= d.ny) continue;
       NodeState<double> st;
       const bool wall = node_state<P, ROWS>(d, src, x, y, st);
@@ -1114,22 +1123,35 @@ hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
   return hipGetLastError();
 }
 
-hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
-                        int parity, int write_snap, int raw, int rows, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  const dim3 grid(ntiles), block(256);
+namespace {
+template <int TX>
+void launch_step2_tx(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
+                     int parity, int write_snap, int raw, int rows, hipStream_t s) {
+  const dim3 grid(ntiles), block(TX * 4);
   if (raw && rows)
-    hipLaunchKernelGGL((step2_kernel<true, true>), grid, block, 0, s, descs, tiles, ntiles, counts,
-                       parity, write_snap);
+    hipLaunchKernelGGL((step2_kernel<TX, true, true>), grid, block, 0, s, descs, tiles, ntiles,
+                       counts, parity, write_snap);
   else if (raw)
-    hipLaunchKernelGGL((step2_kernel<true, false>), grid, block, 0, s, descs, tiles, ntiles,
+    hipLaunchKernelGGL((step2_kernel<TX, true, false>), grid, block, 0, s, descs, tiles, ntiles,
                        counts, parity, write_snap);
   else if (rows)
-    hipLaunchKernelGGL((step2_kernel<false, true>), grid, block, 0, s, descs, tiles, ntiles,
+    hipLaunchKernelGGL((step2_kernel<TX, false, true>), grid, block, 0, s, descs, tiles, ntiles,
                        counts, parity, write_snap);
   else
-    hipLaunchKernelGGL((step2_kernel<false, false>), grid, block, 0, s, descs, tiles, ntiles,
+    hipLaunchKernelGGL((step2_kernel<TX, false, false>), grid, block, 0, s, descs, tiles, ntiles,
                        counts, parity, write_snap);
+}
+}  // namespace
+
+hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
+                        int parity, int write_snap, int raw, int rows, int tile_x, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (tile_x == kFusedXWide)
+    launch_step2_tx<kFusedXWide>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows, s);
+  else if (tile_x == kFusedX)
+    launch_step2_tx<kFusedX>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows, s);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

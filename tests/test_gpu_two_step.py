@@ -1,8 +1,9 @@
 """GPU: two time steps per launch (clb_set_steps_per_launch(ctx, 2), FP32
 storage) against single steps on the same inputs, over every side kind, the
 porosity field, the per-row acceleration, the raw-moment collision, ragged
-domains narrower and wider than the 64 x 8 tiles, and retirement in clb_run;
-and against the FP64 oracle.  The two paths run the same per-node code on the
+domains narrower and wider than the tiles (64 x 8; 128 x 8 when every domain
+of the context is at least 128 wide), and retirement in clb_run; and against
+the FP64 oracle.  The two paths run the same per-node code on the
 same stored values, so they agree to the last bits (asserted within 1e-12
 relative; bit equality is logged)."""
 import sys
@@ -53,13 +54,23 @@ def make_cases(name):
                               cavity(70, ny=33, Ra=1e5, model="mrt")],
         "batch of four": lambda: [cavity(64, Ra=1e4), cavity(129, ny=66, Ra=1e5, Da=1e-3, phi=0.4),
                                   hetero_periodic(40, 24), workloads.paper_channel(33, nx=8)],
+        # every domain at least 128 wide: 128 x 8 tiles
+        "wide cavity 300x37 (ragged last tiles)": lambda: [cavity(300, ny=37, Ra=1e5, Da=1e-3,
+                                                                  phi=0.5)],
+        "wide periodic porosity map 256x40": lambda: [hetero_periodic(256, 40)],
+        "wide mrt 150x30": lambda: [cavity(150, ny=30, Ra=1e5, model="mrt")],
+        "wide batch: cavity, channel with rows, inlet/outlet": lambda: [
+            cavity(128, ny=20, Ra=1e4), workloads.paper_channel(33, nx=130),
+            workloads.hetero_channel(200, 24, ell=4, seed=5)],
     }[name]()
 
 
 CASE_NAMES = ["cavity 97x70", "cavity 65x9 (one-column and one-row last tiles)",
               "small cavity 5x4", "periodic porosity map 96x80",
               "periodic narrow 3x17 channel with rows", "inlet/outlet with porosity map",
-              "mrt batch", "batch of four"]
+              "mrt batch", "batch of four", "wide cavity 300x37 (ragged last tiles)",
+              "wide periodic porosity map 256x40", "wide mrt 150x30",
+              "wide batch: cavity, channel with rows, inlet/outlet"]
 
 
 def start(s, cases):
@@ -96,9 +107,10 @@ def test_two_step_launches_match_single_steps(B, name):
     assert a.steps_done == b.steps_done == 142
 
 
-def test_two_step_launches_match_oracle(B):
-    case = cavity(64, Ra=1e3, Da=1e-2, phi=0.6)
-    T = inputs.cavity_initial_T(64, seed=1)
+@pytest.mark.parametrize("n", [64, 160])  # 64 x 8 and 128 x 8 tiles
+def test_two_step_launches_match_oracle(B, n):
+    case = cavity(n, Ra=1e3, Da=1e-2, phi=0.6)
+    T = inputs.cavity_initial_T(n, seed=1)
     s = B.Solver(case)
     s.set_steps_per_launch(2)
     s.set_state(0, T)
@@ -108,7 +120,7 @@ def test_two_step_launches_match_oracle(B):
     lat.step(5000)
     g, o = s.macros(), lat.macros()
     eu, eT = vel_rel_l2(g, o), rel_l2(g["T"], o["T"])
-    log("two-step cavity 64, 5000 steps: rel-L2 u %.2e T %.2e" % (eu, eT))
+    log("two-step cavity %d, 5000 steps: rel-L2 u %.2e T %.2e" % (n, eu, eT))
     assert eu <= 1e-6 and eT <= 1e-6
     assert abs(s.nusselt(0, 0) - lat.nusselt(0)) <= 1e-4
 
