@@ -460,13 +460,17 @@ clb_status upload_tiles2(clb_ctx *c) {
   std::vector<Tile> order;
   for (int k = 0; k < c->count; ++k) {
     const int nx = c->p[k].nx, ny = c->p[k].ny;
-    const int w = c->tile2_x;
+    const int w = c->tile2_x, h = clb::kFusedY;
     const int tx = (nx + w - 1) / w;
-    const int ty = (ny + clb::kFusedY - 1) / clb::kFusedY;
+    const int ty = (ny + h - 1) / h;
     for (int j = 0; j < ty; ++j)
-      for (int i = 0; i < tx; ++i)
-        order.push_back(Tile{k, tile2_origin(i, w, nx),
-                             tile2_origin(j, clb::kFusedY, ny), (int32_t)order.size()});
+      for (int i = 0; i < tx; ++i) {
+        const int x0 = tile2_origin(i, w, nx), y0 = tile2_origin(j, h, ny);
+        // interior: the region [x0 - 1, x0 + w] x [y0 - 1, y0 + h] lies in
+        // [1, nx - 2] x [1, ny - 2], so its pulls stay inside the domain
+        const bool interior = x0 >= 2 && x0 + w <= nx - 2 && y0 >= 2 && y0 + h <= ny - 2;
+        order.push_back(Tile{k, x0, y0, interior ? 0 : 1});
+      }
   }
   const size_t n = order.size(), m = (n + kXcds - 1) / kXcds;
   std::vector<Tile> list(m * kXcds, Tile{-1, 0, 0, 0});

@@ -19,6 +19,10 @@ constexpr int kRed = 8;
 // One work tile: domain index (-1: padding entry, skipped), the origin of a
 // tile of nodes, and its index in the list of all tiles (the slot of its
 // residual partial sums).
+// One tile of a tile list.  id: the slot of the tile's partial sums (one-step
+// lists); in the two-step list, 1 when the tile's LDS region reaches a node
+// on or next to a side of its domain (boundary nodes, wrapped or skipped ring
+// nodes: the general path), 0 for an interior tile.
 struct Tile {
   int32_t cav, x0, y0, id;
 };

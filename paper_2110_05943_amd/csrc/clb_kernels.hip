@@ -29,6 +29,8 @@
 
 #include "clb_internal.h"
 
+#include <type_traits>
+
 namespace clb {
 
 // ---------------------------------------------------------------- storage
@@ -257,12 +259,12 @@ __device__ __forceinline__ void accel_at(const CavDesc &d, int y, R &ax, R &ay) 
 
 // Where a gather reads populations.  GlobalSrc: the planes of a buffer in
 // global memory; (xs, ys) must have all 8 neighbours inside the domain or
-// across a periodic side, which wraps.  LdsSrc (two-step kernel): FP32
+// across a periodic side, which wraps (WRAP = false: all 8 inside).  LdsSrc (two-step kernel): FP32
 // populations of a rectangular region held in LDS, 14 planes of kRegion
 // elements, rows kRegionW long; the region's element 0 is the node (ox, oy)
 // of the domain in unwrapped coordinates, and every neighbour read lies in
 // the region by construction of the caller.
-template <typename P>
+template <typename P, bool WRAP = true>
 struct GlobalSrc {
   const char *buf;
 
@@ -270,11 +272,11 @@ struct GlobalSrc {
   __device__ __forceinline__ void pull(const CavDesc &d, int xs, int ys, R f[9], R g[5]) const {
     const int nx = d.nx, ny = d.ny, pitch = d.pitch, plane = d.plane;
     int xm = xs - 1, xp = xs + 1, ym = ys - 1, yp = ys + 1;
-    if (d.bc[0] == kPeriodic) {
+    if (WRAP && d.bc[0] == kPeriodic) {
       xm = xm < 0 ? xm + nx : xm;
       xp = xp >= nx ? xp - nx : xp;
     }
-    if (d.bc[2] == kPeriodic) {
+    if (WRAP && d.bc[2] == kPeriodic) {
       ym = ym < 0 ? ym + ny : ym;
       yp = yp >= ny ? yp - ny : yp;
     }
@@ -429,9 +431,13 @@ __device__ __forceinline__ R gather_theta(const CavDesc &d, const Src &src, int 
 // phi_f), which is M applied to f_i^eq(b) + [f_i(x_f) - f_i^eq(x_f)], and
 // likewise for the D2Q5 moments with Eq. 33.  The node then collides with
 // (rho_b, u_b, T_b).  Returns true for boundary nodes.
-template <typename P, bool ROWS, typename Src, typename R = typename P::R>
+template <typename P, bool ROWS, typename Src, bool EDGE = true, typename R = typename P::R>
 __device__ __forceinline__ bool node_state(const CavDesc &d, const Src &A, int x, int y,
                                            NodeState<R> &st) {
+  if constexpr (!EDGE) {  // caller guarantees (x, y) is no boundary node
+    gather_moments<P, ROWS>(d, A, x, y, st);
+    return false;
+  }
   int sx = -1, sy = -1, dx = 0, dy = 0;
   if (x == 0 && d.bc[0] != kPeriodic) {
     sx = 0;
@@ -781,33 +787,58 @@ __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict
     const char *A = parity ? d.B : d.A;
     char *B = parity ? d.A : d.B;
     const bool wrap_x = d.bc[0] == kPeriodic, wrap_y = d.bc[2] == kPeriodic;
-    const uint32_t seed1 = mix32(step * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
-    for (int c = threadIdx.x; c < kRegion; c += blockDim.x) {
-      int x = x0 - 1 + c % kRegionW, y = y0 - 1 + c / kRegionW;
-      if (wrap_x) x = x < 0 ? x + d.nx : (x >= d.nx ? x - d.nx : x);
-      if (wrap_y) y = y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y);
-      if (x < 0 || x >= d.nx || y < 0 || y >= d.ny) continue;
-      NodeState<double> st;
-      const bool wall = node_state<P, ROWS>(d, GlobalSrc<P>{A}, x, y, st);
-      double out[kPlanes];
-      collide<P, RAW, ROWS>(d, st, wall, out);
-      store_region<TX>(out, lds, c, y * d.pitch + x, seed1);
-    }
-    __syncthreads();
-    const uint32_t seed2 = mix32((step + 1) * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
-    const LdsSrc<TX> src{lds, x0 - 1, y0 - 1};
-    for (int q = threadIdx.x; q < TX * kFusedY; q += blockDim.x) {
-      const int x = x0 + q % TX, y = y0 + q / TX;
-      if (x >= d.nx || y >= d.ny) continue;
-      NodeState<double> st;
-      const bool wall = node_state<P, ROWS>(d, src, x, y, st);
-      const int idx = y * d.pitch + x;
-      collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed2);
-      if (write_snap) {
-        d.snap[idx] = (float)st.ux;
-        d.snap[d.plane + idx] = (float)st.uy;
-        d.snap[2 * d.plane + idx] = (float)st.th;
+    // Both steps of the tile.  EDGE = false: the tile's region holds no
+    // boundary node and every pull stays inside the domain (no wrap, no
+    // skipped ring node), so the per-node side tests are left out.  (A
+    // lambda rather than a separate function: the compiler then keeps the
+    // domain constants out of the scalar registers as in the plain loop.)
+    auto tile = [&](auto edge_tag) {
+      constexpr bool EDGE = decltype(edge_tag)::value;
+      const uint32_t seed1 = mix32(step * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
+      for (int c = threadIdx.x; c < kRegion; c += blockDim.x) {
+        int x = x0 - 1 + c % kRegionW, y = y0 - 1 + c / kRegionW;
+        if constexpr (EDGE) {
+          if (wrap_x) x = x < 0 ? x + d.nx : (x >= d.nx ? x - d.nx : x);
+          if (wrap_y) y = y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y);
+          if (x < 0 || x >= d.nx || y < 0 || y >= d.ny) continue;
+        }
+        NodeState<double> st;
+        const bool wall =
+            node_state<P, ROWS, GlobalSrc<P, EDGE>, EDGE>(d, GlobalSrc<P, EDGE>{A}, x, y, st);
+        double out[kPlanes];
+        collide<P, RAW, ROWS>(d, st, wall, out);
+        store_region<TX>(out, lds, c, y * d.pitch + x, seed1);
       }
+      __syncthreads();
+      const uint32_t seed2 = mix32((step + 1) * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
+      const LdsSrc<TX> src{lds, x0 - 1, y0 - 1};
+      for (int q = threadIdx.x; q < TX * kFusedY; q += blockDim.x) {
+        const int x = x0 + q % TX, y = y0 + q / TX;
+        if constexpr (EDGE) {
+          if (x >= d.nx || y >= d.ny) continue;
+        }
+        NodeState<double> st;
+        const bool wall = node_state<P, ROWS, LdsSrc<TX>, EDGE>(d, src, x, y, st);
+        const int idx = y * d.pitch + x;
+        collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed2);
+        if (write_snap) {
+          d.snap[idx] = (float)st.ux;
+          d.snap[d.plane + idx] = (float)st.uy;
+          d.snap[2 * d.plane + idx] = (float)st.th;
+        }
+      }
+    };
+    // Interior tiles take the path without side tests in the wide kernel.
+    // The narrow one serves contexts with small domains, whose tiles are
+    // mostly edge tiles: there a second copy of the body costs more
+    // (instruction cache, registers) than it saves.
+    if constexpr (TX == kFusedXWide) {
+      if (__builtin_amdgcn_readfirstlane(tiles[t].id))
+        tile(std::true_type{});
+      else
+        tile(std::false_type{});
+    } else {
+      tile(std::true_type{});
     }
     __syncthreads();  // the next tile overwrites the region
   }

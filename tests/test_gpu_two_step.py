@@ -62,6 +62,13 @@ def make_cases(name):
         "wide batch: cavity, channel with rows, inlet/outlet": lambda: [
             cavity(128, ny=20, Ra=1e4), workloads.paper_channel(33, nx=130),
             workloads.hetero_channel(200, 24, ell=4, seed=5)],
+        # a narrow domain keeps 64 x 8 tiles; the wide ones then hold interior
+        # tiles (regions clear of every side) of that width
+        "mixed widths: interior 64 x 8 tiles": lambda: [
+            cavity(40, ny=24, Ra=1e4), cavity(200, ny=50, Ra=1e5, Da=1e-3),
+            hetero_periodic(192, 40)],
+        "mixed widths, mrt": lambda: [cavity(40, ny=24, Ra=1e4, model="mrt"),
+                                      cavity(210, ny=44, Ra=1e5, model="mrt")],
     }[name]()
 
 
@@ -70,7 +77,8 @@ CASE_NAMES = ["cavity 97x70", "cavity 65x9 (one-column and one-row last tiles)",
               "periodic narrow 3x17 channel with rows", "inlet/outlet with porosity map",
               "mrt batch", "batch of four", "wide cavity 300x37 (ragged last tiles)",
               "wide periodic porosity map 256x40", "wide mrt 150x30",
-              "wide batch: cavity, channel with rows, inlet/outlet"]
+              "wide batch: cavity, channel with rows, inlet/outlet",
+              "mixed widths: interior 64 x 8 tiles", "mixed widths, mrt"]
 
 
 def start(s, cases):
@@ -107,22 +115,33 @@ def test_two_step_launches_match_single_steps(B, name):
     assert a.steps_done == b.steps_done == 142
 
 
-@pytest.mark.parametrize("n", [64, 160])  # 64 x 8 and 128 x 8 tiles
-def test_two_step_launches_match_oracle(B, n):
-    case = cavity(n, Ra=1e3, Da=1e-2, phi=0.6)
-    T = inputs.cavity_initial_T(n, seed=1)
-    s = B.Solver(case)
+# (tile width, domains, the domain compared): each compared domain holds
+# edge tiles and interior tiles of that width
+ORACLE_CASES = {
+    "64 x 8 tiles": ([(40, 24), (200, 40)], 1),
+    "128 x 8 tiles": ([(260, 40)], 0),
+}
+
+
+@pytest.mark.parametrize("name", list(ORACLE_CASES))
+def test_two_step_launches_match_oracle(B, name):
+    sizes, k = ORACLE_CASES[name]
+    cases = [cavity(nx, ny=ny, Ra=1e3, Da=1e-2, phi=0.6) for nx, ny in sizes]
+    s = B.Solver(cases)
     s.set_steps_per_launch(2)
-    s.set_state(0, T)
+    for i, (nx, ny) in enumerate(sizes):
+        s.set_state(i, inputs.cavity_initial_T(nx, seed=1, ny=ny))
+    case = cases[k]
     lat = oracle_lattice(case)
-    lat.init_equilibrium(T)
+    lat.init_equilibrium(inputs.cavity_initial_T(sizes[k][0], seed=1, ny=sizes[k][1]))
     s.step(5000)
     lat.step(5000)
-    g, o = s.macros(), lat.macros()
+    g, o = s.macros(k), lat.macros()
     eu, eT = vel_rel_l2(g, o), rel_l2(g["T"], o["T"])
-    log("two-step cavity %d, 5000 steps: rel-L2 u %.2e T %.2e" % (n, eu, eT))
+    log("two-step %s, domain %dx%d, 5000 steps: rel-L2 u %.2e T %.2e"
+        % (name, case["nx"], case["ny"], eu, eT))
     assert eu <= 1e-6 and eT <= 1e-6
-    assert abs(s.nusselt(0, 0) - lat.nusselt(0)) <= 1e-4
+    assert abs(s.nusselt(k, 0) - lat.nusselt(0)) <= 1e-4
 
 
 def test_two_step_run_with_retirement_matches(B):
