@@ -3,9 +3,10 @@ storage) against single steps on the same inputs, over every side kind, the
 porosity field, the per-row acceleration, the raw-moment collision, ragged
 domains narrower and wider than the tiles (64 x 8; 128 x 8 when every domain
 of the context is at least 128 wide), and retirement in clb_run; and against
-the FP64 oracle.  The two paths run the same per-node code on the
-same stored values, so they agree to the last bits (asserted within 1e-12
-relative; bit equality is logged)."""
+the FP64 oracle.  Interior tiles of the 128-wide kernel skip the per-node
+side tests; the wide cases hold both kinds.  Both paths do the same
+arithmetic on the same stored values, so they agree to the last bits
+(asserted within 1e-12 relative; bit equality is logged)."""
 import sys
 
 import numpy as np
@@ -62,9 +63,9 @@ def make_cases(name):
         "wide batch: cavity, channel with rows, inlet/outlet": lambda: [
             cavity(128, ny=20, Ra=1e4), workloads.paper_channel(33, nx=130),
             workloads.hetero_channel(200, 24, ell=4, seed=5)],
-        # a narrow domain keeps 64 x 8 tiles; the wide ones then hold interior
-        # tiles (regions clear of every side) of that width
-        "mixed widths: interior 64 x 8 tiles": lambda: [
+        # a narrow domain keeps the 64 x 8 tiles (one general tile body) for
+        # every domain of the context, wide ones included
+        "mixed widths: 64 x 8 tiles on wide domains": lambda: [
             cavity(40, ny=24, Ra=1e4), cavity(200, ny=50, Ra=1e5, Da=1e-3),
             hetero_periodic(192, 40)],
         "mixed widths, mrt": lambda: [cavity(40, ny=24, Ra=1e4, model="mrt"),
@@ -78,7 +79,7 @@ CASE_NAMES = ["cavity 97x70", "cavity 65x9 (one-column and one-row last tiles)",
               "mrt batch", "batch of four", "wide cavity 300x37 (ragged last tiles)",
               "wide periodic porosity map 256x40", "wide mrt 150x30",
               "wide batch: cavity, channel with rows, inlet/outlet",
-              "mixed widths: interior 64 x 8 tiles", "mixed widths, mrt"]
+              "mixed widths: 64 x 8 tiles on wide domains", "mixed widths, mrt"]
 
 
 def start(s, cases):
@@ -115,8 +116,9 @@ def test_two_step_launches_match_single_steps(B, name):
     assert a.steps_done == b.steps_done == 142
 
 
-# (tile width, domains, the domain compared): each compared domain holds
-# edge tiles and interior tiles of that width
+# (tile width, domains, the domain compared).  The 128-wide compared domain
+# holds both edge tiles and interior tiles (regions clear of every side, run
+# without the per-node side tests).
 ORACLE_CASES = {
     "64 x 8 tiles": ([(40, 24), (200, 40)], 1),
     "128 x 8 tiles": ([(260, 40)], 0),
