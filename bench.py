@@ -293,8 +293,7 @@ def batch_steady_bench(args):
     out = {"metric": "batched run to steady state with retirement",
            "value": round(lu / wall / 1e6, 1), "unit": "MLUPS (aggregate over the run)",
            "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
-           "dtype": {"f32": "f64 arithmetic, f32 storage", "f16": "f32 arithmetic, f16 storage",
-                     "mixed": "f32 arithmetic, f16 flow / f32 temperature storage"}[args.storage],
+           "dtype": DTYPE[args.storage],
            "config": {"workload": "256 porous cavities (seed 3), from rest", "tol": args.tol,
                       "check_every": every, "max_steps": cap},
            "wall_s": round(wall, 1), "node_updates": lu, "steady": int(ok.sum()),
@@ -646,35 +645,49 @@ def oracle_timing():
                       "rows": rows, "paper_clb_mlups_context": 3.5}), flush=True)
 
 
+DTYPE = {"f32": "f64 arithmetic, f32 storage", "f32c": "f32 arithmetic, f32 storage",
+         "f16": "f32 arithmetic, f16 storage",
+         "mixed": "f32 arithmetic, f16 flow / f32 temperature storage"}
 VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9  # lane instructions per second (one wave64 op / 4 cycles / SIMD)
 FP64_PEAK_TFLOPS = 78.6
 
 
-def alu_roofline(key, nodes, step_ms, bytes_per_lu):
-    """Roofline of the two-steps-per-launch kernel, bound by VALU issue.
+def two_step_roofline(key, storage, nodes, step_ms, bytes_per_lu):
+    """Roofline of the two-steps-per-launch kernel.
 
-    Peak: one wave64 VALU instruction per four cycles on each of the 1024
-    SIMDs at 2.4 GHz, i.e. 256 x 4 x 16 x 2.4e9 = 39.3e12 lane operations per
-    second.  Algorithmic work: the VALU lane operations of one node update as
-    issued by the one-step kernel on the 4096^2 cavity (which recomputes
-    nothing; SQ_INSTS_VALU x 64 per node, counted by rocprofv3), times the two
-    updates per node of a launch, over the launch time measured here.  Also
-    reported: the fraction of the issue peak this kernel really uses (its own
-    instruction count, ring recomputation included), the FP64 flop rate
-    against the FP64 vector peak, and the HBM traffic per launch."""
+    Two bounds are evaluated and the one the launch is closer to is reported
+    as `bound`, the other beside it:
+    - VALU issue: peak one wave64 VALU instruction per four cycles on each of
+      the 1024 SIMDs at 2.4 GHz, i.e. 256 x 4 x 16 x 2.4e9 = 39.3e12 lane
+      operations per second.  Algorithmic work: the VALU lane operations of
+      one node update as issued by the one-step kernel of the same storage on
+      the 4096^2 cavity (which recomputes nothing; SQ_INSTS_VALU x 64 per
+      node, counted by rocprofv3), times the two updates per node of a launch.
+    - HBM: one read and one write of the populations per node per launch
+      (bytes_per_lu x nodes) against 8 TB/s.
+    Both over the launch time measured here.  Also reported: the issue
+    fraction of this kernel's own instruction count (ring recomputation
+    included), the FP64 flop rate against the FP64 vector peak, and the
+    measured HBM traffic per launch."""
     launch_s = 2 * step_ms * 1e-3
-    single = profile_record("cavity4096_f32_single") or {}
+    single = profile_record("cavity4096_%s_single" % storage) or {}
     rec = profile_record(key) or {}
-    out = {"bound": "alu", "kernel": "step2_kernel", "steps_per_launch": 2,
-           "kernel_us": round(launch_s * 1e6, 2), "peak": round(VALU_LANE_PEAK / 1e12, 2),
-           "unit": "TOP/s (VALU lane ops)"}
+    alu = hbm = None
+    out = {"kernel": "step2_kernel", "steps_per_launch": 2, "kernel_us": round(launch_s * 1e6, 2)}
     if single.get("valu_instr_per_launch"):
         ops_lu = single["valu_instr_per_launch"] * 64 / single["nodes"]
         achieved = ops_lu * 2 * nodes / launch_s / 1e12
-        out.update(achieved=round(achieved, 2), frac=round(achieved * 1e12 / VALU_LANE_PEAK, 4),
-                   valu_ops_per_node_update=round(ops_lu, 1))
-    else:
-        out.update(achieved=None, frac=None)
+        alu = {"bound": "alu", "achieved": round(achieved, 2),
+               "peak": round(VALU_LANE_PEAK / 1e12, 2), "unit": "TOP/s (VALU lane ops)",
+               "frac": round(achieved * 1e12 / VALU_LANE_PEAK, 4),
+               "valu_ops_per_node_update": round(ops_lu, 1)}
+    gbps = bytes_per_lu * nodes / launch_s / 1e9
+    hbm = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbps / HBM_PEAK_GBS, 4), "bytes_per_node_per_launch": bytes_per_lu}
+    main_, other = (alu, hbm) if alu is not None and alu["frac"] >= hbm["frac"] else (hbm, alu)
+    out.update(main_)
+    if other is not None:
+        out["other_bound"] = other
     out["traffic"] = rec.get("bytes_per_launch")
     if rec.get("bytes_per_launch"):
         out["hbm_GBps"] = round(rec["bytes_per_launch"] / launch_s / 1e9, 1)
@@ -686,7 +699,6 @@ def alu_roofline(key, nodes, step_ms, bytes_per_lu):
         fp64 = flops_lu * 2 * nodes / launch_s / 1e12
         out.update(fp64_tflops=round(fp64, 2), fp64_frac=round(fp64 / FP64_PEAK_TFLOPS, 4),
                    fp64_flops_per_node_update=round(flops_lu, 1))
-    out["bytes_per_node_update_one_step"] = bytes_per_lu
     return out
 
 
@@ -709,7 +721,8 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="grid size (cavity; channel: 2048)")
     ap.add_argument("--count", type=int, default=None,
                     help="domains of the batch (256) or warmstart (500) workload")
-    ap.add_argument("--storage", choices=("f32", "f16", "mixed"), default="f32")
+    ap.add_argument("--storage", choices=("f32", "f32c", "f16", "mixed"), default="f32",
+                    help="f32: FP32 planes, FP64 arithmetic; f32c: FP32 planes, FP32 arithmetic")
     ap.add_argument("--weights", default=None, help="warmstart: network weights (.npz)")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -767,7 +780,7 @@ def main():
     if args.launch:
         s.set_launch(*[int(v) for v in args.launch.split(",")])
     if args.steps_per_launch is None:
-        args.steps_per_launch = 2 if args.storage == "f32" else 1
+        args.steps_per_launch = 2 if args.storage in ("f32", "f32c") else 1
     s.set_steps_per_launch(args.steps_per_launch)
     if args.autotune:
         s.autotune()
@@ -800,13 +813,13 @@ def main():
     bytes_per_lu = BYTES_PER_UPDATE[args.storage] + (4 if cases[0].get("eps") is not None else 0)
     mlups = nodes * K / wall / 1e6
     if args.steps_per_launch == 2:
-        roofline = alu_roofline(key, nodes, kernel_ms, bytes_per_lu)
+        roofline = two_step_roofline(key, args.storage, nodes, kernel_ms, bytes_per_lu)
     else:
         achieved = bytes_per_lu * nodes / (kernel_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(key + "_single" if args.storage == "f32"
-                                                else key),
+                    "traffic": measured_traffic(key + "_single"
+                                                if args.storage in ("f32", "f32c") else key),
                     "kernel": "step_kernel", "kernel_us": round(kernel_ms * 1e3, 2),
                     "bytes_per_node_update": bytes_per_lu}
     out = {
@@ -820,8 +833,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f64 arithmetic, f32 storage", "f16": "f32 arithmetic, f16 storage",
-                  "mixed": "f32 arithmetic, f16 flow / f32 temperature storage"}[args.storage],
+        "dtype": DTYPE[args.storage],
         "data": "synthetic",
         "config": {"workload": desc, "domains": len(cases), "nodes": nodes,
                    "storage": args.storage, "launch_shape": list(shape),

@@ -67,8 +67,11 @@ enum { CLB_WEST = 0, CLB_EAST = 1, CLB_SOUTH = 2, CLB_NORTH = 3 };
  *   CLB_STORE_F32:   14 FP32 planes (112 B per node update), FP64 arithmetic;
  *   CLB_STORE_F16:   14 FP16 planes (56 B), FP32 arithmetic;
  *   CLB_STORE_MIXED: 9 FP16 flow planes and 5 FP32 temperature planes (76 B),
- *                    FP32 arithmetic. */
-enum { CLB_STORE_F32 = 0, CLB_STORE_F16 = 1, CLB_STORE_MIXED = 2 };
+ *                    FP32 arithmetic;
+ *   CLB_STORE_F32C:  14 FP32 planes (112 B), FP32 arithmetic (nothing is
+ *                    narrowed, so nothing is rounded beyond the FP32
+ *                    arithmetic itself). */
+enum { CLB_STORE_F32 = 0, CLB_STORE_F16 = 1, CLB_STORE_MIXED = 2, CLB_STORE_F32C = 3 };
 
 /* Collision operator of a domain.
  *   CLB_MODEL_CASCADED: the paper's method, moments shifted by N(u, phi) and
@@ -277,11 +280,12 @@ clb_status clb_steps_done(clb_ctx *ctx, int64_t *steps);
 clb_status clb_set_launch(clb_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t blocks);
 clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_t *blocks);
 
-/* Time steps per kernel launch: 1, or 2 (FP32 storage only, else
- * CLB_ERR_ARG; 2 is the default for FP32 storage).  With 2, pairs of steps
- * run in one launch while every domain is active: each 64 x 8 tile and a
- * one-node ring around it are collided into LDS, then the tile again from
- * there, so that the populations cross HBM once per two node updates.  The
+/* Time steps per kernel launch: 1, or 2 (FP32 planes only: CLB_STORE_F32 or
+ * CLB_STORE_F32C, else CLB_ERR_ARG; 2 is their default).  With 2, pairs of
+ * steps run in one launch while every domain is active: each tile (128 x 8
+ * nodes when every domain is at least 128 wide, else 64 x 8) and a one-node
+ * ring around it are collided into LDS, then the tile again from there, so
+ * that the populations cross HBM once per two node updates.  The
  * per-node arithmetic and rounding are those of single steps (the results
  * have been bit-identical in every test).  The step that records the residual
  * snapshot, an odd remainder, and any step while a domain is retired run

@@ -16,14 +16,14 @@ LIB_PATH = os.path.join(PKG, "libclb.so")
 OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_DIVERGED, ERR_STATE, NOT_CONVERGED = range(7)
 PERIODIC, WALL_T, WALL_ADIABATIC, INLET, OUTLET = range(5)
 WEST, EAST, SOUTH, NORTH = range(4)
-STORE_F32, STORE_F16, STORE_MIXED = 0, 1, 2
+STORE_F32, STORE_F16, STORE_MIXED, STORE_F32C = 0, 1, 2, 3
 SCALE_CAVITY, SCALE_CHANNEL = 0, 1
 KIND = {"periodic": PERIODIC, "wall_T": WALL_T, "wall_adiabatic": WALL_ADIABATIC,
         "inlet": INLET, "outlet": OUTLET}
-STORAGE = {"f32": STORE_F32, "f16": STORE_F16, "mixed": STORE_MIXED}
+STORAGE = {"f32": STORE_F32, "f16": STORE_F16, "mixed": STORE_MIXED, "f32c": STORE_F32C}
 MODEL = {"clb": 0, "mrt": 1, "bgk": 2}
 # bytes moved per node update (14 populations read and written)
-BYTES_PER_UPDATE = {"f32": 112, "f16": 56, "mixed": 76}
+BYTES_PER_UPDATE = {"f32": 112, "f16": 56, "mixed": 76, "f32c": 112}
 
 
 class CLBError(RuntimeError):
@@ -133,7 +133,7 @@ def make_params(**kw):
     """A Params struct: library defaults, then the given fields.
 
     bc may be given as kind names; eps as an (ny, nx) array; a_rows as an
-    (ny, 2) array of (a_x, a_y) per row; storage as "f32"/"f16"; two-element
+    (ny, 2) array of (a_x, a_y) per row; storage as "f32"/"f16"/"mixed"/"f32c"; two-element
     fields as sequences."""
     p = Params()
     _lib().clb_params_default(C.byref(p))
@@ -317,7 +317,7 @@ class Solver:
         _check(_lib().clb_set_launch(self._ctx, tile_x, tile_y, blocks), "clb_set_launch")
 
     def set_steps_per_launch(self, steps):
-        """1 or 2 time steps per kernel launch (2: FP32 storage only)."""
+        """1 or 2 time steps per kernel launch (2: FP32 planes only, "f32" or "f32c")."""
         _check(_lib().clb_set_steps_per_launch(self._ctx, int(steps)), "clb_set_steps_per_launch")
 
     def get_launch(self):

@@ -48,14 +48,15 @@ bool walled_x(const clb_params &p) { return p.bc[0] != CLB_PERIODIC; }
 bool walled_y(const clb_params &p) { return p.bc[2] != CLB_PERIODIC; }
 
 // Bytes of the 9 D2Q9 planes and of the 5 D2Q5 planes per element.
-int fbytes(int storage) { return storage == CLB_STORE_F32 ? 4 : 2; }
+bool f32_planes(int storage) { return storage == CLB_STORE_F32 || storage == CLB_STORE_F32C; }
+int fbytes(int storage) { return f32_planes(storage) ? 4 : 2; }
 int gbytes(int storage) { return storage == CLB_STORE_F16 ? 2 : 4; }
 // Bytes of one population buffer per plane element (all 14 planes).
 size_t pop_bytes(int storage) { return 9 * (size_t)fbytes(storage) + 5 * (size_t)gbytes(storage); }
 
 // Row pitch in elements: every row starts on a 256-byte boundary.
 int pitch_of(const clb_params &p) {
-  const int per = p.storage == CLB_STORE_F32 ? 64 : 128;
+  const int per = f32_planes(p.storage) ? 64 : 128;
   return (p.nx + per - 1) / per * per;
 }
 
@@ -110,7 +111,8 @@ extern "C" clb_status clb_derive(const clb_params *pp, clb_derived *out) {
   if (p.nx > (1 << 30) || p.ny > (1 << 30)) return CLB_ERR_ARG;
   if ((int64_t)p.ny * pitch_of(p) > (int64_t(1) << 30)) return CLB_ERR_ARG;
   if (p.model < CLB_MODEL_CASCADED || p.model > CLB_MODEL_BGK) return CLB_ERR_ARG;
-  if (p.storage != CLB_STORE_F32 && p.storage != CLB_STORE_F16 && p.storage != CLB_STORE_MIXED)
+  if (p.storage != CLB_STORE_F32 && p.storage != CLB_STORE_F16 && p.storage != CLB_STORE_MIXED &&
+      p.storage != CLB_STORE_F32C)
     return CLB_ERR_ARG;
   if (p.scaling != CLB_SCALE_CAVITY && p.scaling != CLB_SCALE_CHANNEL) return CLB_ERR_ARG;
   if (!p.eps && !(p.phi > 0.0 && p.phi <= 1.0)) return CLB_ERR_ARG;
@@ -515,7 +517,7 @@ clb_status launch_one(clb_ctx *c, int write_snap, hipStream_t s) {
 
 clb_status launch_two(clb_ctx *c, hipStream_t s) {
   const hipError_t e = clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts,
-                                         c->parity, 0, c->raw, c->rows, c->tile2_x, s);
+                                         c->parity, 0, c->storage, c->raw, c->rows, c->tile2_x, s);
   if (e != hipSuccess) return hip_fail(e, "two-step kernel launch");
   return CLB_OK;
 }
@@ -529,7 +531,7 @@ clb_status capture_graph(clb_ctx *c, int p0) {
   const int launches = two ? kGraphSteps / 2 : kGraphSteps;
   for (int k = 0; k < launches && err == hipSuccess; ++k)
     err = two ? clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts, (p0 + k) & 1,
-                                  0, c->raw, c->rows, c->tile2_x, c->cap_stream)
+                                  0, c->storage, c->raw, c->rows, c->tile2_x, c->cap_stream)
               : clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c),
                                  (p0 + k) & 1, 0, c->storage, c->raw, c->rows, c->shape,
                                  c->cap_stream);
@@ -568,7 +570,7 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->count = count;
   c->storage = p[0].storage;
   c->raw = p[0].model != CLB_MODEL_CASCADED;
-  c->fused = p[0].storage == CLB_STORE_F32;  // two steps per launch by default for FP32
+  c->fused = f32_planes(p[0].storage);  // two steps per launch by default for FP32 planes
   // 128-wide two-step tiles (fewer partly used cache lines at the tile
   // edges) when no domain would leave most of such a tile idle
   c->tile2_x = clb::kFusedXWide;
@@ -1038,7 +1040,7 @@ extern "C" clb_status clb_set_launch(clb_ctx *c, int32_t tx, int32_t ty, int32_t
 }
 
 extern "C" clb_status clb_set_steps_per_launch(clb_ctx *c, int32_t k) {
-  if (!c || (k != 1 && k != 2) || (k == 2 && c->storage != CLB_STORE_F32)) return CLB_ERR_ARG;
+  if (!c || (k != 1 && k != 2) || (k == 2 && !f32_planes(c->storage))) return CLB_ERR_ARG;
   drop_graphs(c);
   c->fused = k == 2;
   return CLB_OK;

@@ -107,12 +107,13 @@ hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
                        int32_t grid_tiles, int parity, int write_snap, int storage, int raw,
                        int rows, LaunchShape shape, hipStream_t s);
 // Two steps per launch over a list of tile_x x kFusedY tiles (FP32 planes
-// only), tile_x = kFusedX (64) or kFusedXWide (128; for contexts whose
-// domains are all at least 128 nodes wide); the list may hold padding
-// entries (cav = -1).
+// only: CLB_STORE_F32 or CLB_STORE_F32C), tile_x = kFusedX (64) or
+// kFusedXWide (128; for contexts whose domains are all at least 128 nodes
+// wide); the list may hold padding entries (cav = -1).
 constexpr int kFusedX = 64, kFusedXWide = 128, kFusedY = 8;
 hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
-                        int parity, int write_snap, int raw, int rows, int tile_x, hipStream_t s);
+                        int parity, int write_snap, int storage, int raw, int rows, int tile_x,
+                        hipStream_t s);
 hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int parity,
                        const float *uvth /* 3 dense planes or null */, float th_uniform,
                        int storage, hipStream_t s);

@@ -94,6 +94,7 @@ struct Store {
 using StoreF32 = Store<float, float, double>;        // FP32 planes, FP64 arithmetic
 using StoreF16 = Store<_Float16, _Float16, float>;   // FP16 planes, FP32 arithmetic
 using StoreMix = Store<_Float16, float, float>;      // FP16 flow, FP32 temperature
+using StoreF32C = Store<float, float, float>;        // FP32 planes, FP32 arithmetic
 
 // The domain constants in the arithmetic type R of a kernel.
 template <typename R>
@@ -693,16 +694,22 @@ __device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlan
   }
 }
 
-// The same rounding into FP32 values (the two-step kernel's LDS region at
-// element c), identical to what store_planes writes for FP32 planes.
-template <int TX>
-__device__ __forceinline__ void store_region(const double out[kPlanes], float *lds, int c,
-                                             int idx, uint32_t seed) {
-  uint32_t w = mix32((uint32_t)idx + seed);
+// The values store_planes writes for FP32 planes, into FP32 values (the
+// two-step kernel's LDS region at element c): FP64 results rounded the same
+// way, FP32 results as they are.
+template <int TX, typename R>
+__device__ __forceinline__ void store_region(const R out[kPlanes], float *lds, int c, int idx,
+                                             uint32_t seed) {
+  if constexpr (sizeof(R) == 8) {
+    uint32_t w = mix32((uint32_t)idx + seed);
 #pragma unroll
-  for (int i = 0; i < kPlanes; ++i) {
-    lds[i * Region<TX>::N + c] = round_sr(out[i], (i & 1) ? (w >> 16) : w);
-    if (i & 1) w = next_bits<double>(w);
+    for (int i = 0; i < kPlanes; ++i) {
+      lds[i * Region<TX>::N + c] = round_sr(out[i], (i & 1) ? (w >> 16) : w);
+      if (i & 1) w = next_bits<double>(w);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kPlanes; ++i) lds[i * Region<TX>::N + c] = out[i];
   }
 }
 
@@ -768,12 +775,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) s
 // wrapped neighbours, and ring nodes outside a walled side are neither
 // computed nor read (boundary nodes gather inward).  counts[2 + parity]
 // holds the index of the first step; the kernel passes step + 2 on.
-template <int TX, bool RAW, bool ROWS>
+template <typename P, int TX, bool RAW, bool ROWS>
 __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict__ descs,
                                                        const Tile *__restrict__ tiles, int ntiles,
                                                        int32_t *__restrict__ counts, int parity,
                                                        int write_snap) {
-  using P = StoreF32;
+  using R = typename P::R;
   constexpr int kRegionW = Region<TX>::W, kRegion = Region<TX>::N;
   __shared__ float lds[kPlanes * kRegion];
   const uint32_t step = (uint32_t)counts[2 + parity];
@@ -802,10 +809,10 @@ __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict
           if (wrap_y) y = y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y);
           if (x < 0 || x >= d.nx || y < 0 || y >= d.ny) continue;
         }
-        NodeState<double> st;
+        NodeState<R> st;
         const bool wall =
             node_state<P, ROWS, GlobalSrc<P, EDGE>, EDGE>(d, GlobalSrc<P, EDGE>{A}, x, y, st);
-        double out[kPlanes];
+        R out[kPlanes];
         collide<P, RAW, ROWS>(d, st, wall, out);
         store_region<TX>(out, lds, c, y * d.pitch + x, seed1);
       }
@@ -817,7 +824,7 @@ __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict
         if constexpr (EDGE) {
           if (x >= d.nx || y >= d.ny) continue;
         }
-        NodeState<double> st;
+        NodeState<R> st;
         const bool wall = node_state<P, ROWS, LdsSrc<TX>, EDGE>(d, src, x, y, st);
         const int idx = y * d.pitch + x;
         collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed2);
@@ -1126,8 +1133,10 @@ static void dispatch(int storage, Fn &&f) {
     f(StoreF32{});
   else if (storage == 1)
     f(StoreF16{});
-  else
+  else if (storage == 2)
     f(StoreMix{});
+  else
+    f(StoreF32C{});
 }
 
 hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
@@ -1155,35 +1164,50 @@ hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
 }
 
 namespace {
-template <int TX>
+template <typename P, int TX>
 void launch_step2_tx(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
                      int parity, int write_snap, int raw, int rows, hipStream_t s) {
   const dim3 grid(ntiles), block(TX * 4);
   if (raw && rows)
-    hipLaunchKernelGGL((step2_kernel<TX, true, true>), grid, block, 0, s, descs, tiles, ntiles,
+    hipLaunchKernelGGL((step2_kernel<P, TX, true, true>), grid, block, 0, s, descs, tiles, ntiles,
                        counts, parity, write_snap);
   else if (raw)
-    hipLaunchKernelGGL((step2_kernel<TX, true, false>), grid, block, 0, s, descs, tiles, ntiles,
-                       counts, parity, write_snap);
+    hipLaunchKernelGGL((step2_kernel<P, TX, true, false>), grid, block, 0, s, descs, tiles,
+                       ntiles, counts, parity, write_snap);
   else if (rows)
-    hipLaunchKernelGGL((step2_kernel<TX, false, true>), grid, block, 0, s, descs, tiles, ntiles,
-                       counts, parity, write_snap);
+    hipLaunchKernelGGL((step2_kernel<P, TX, false, true>), grid, block, 0, s, descs, tiles,
+                       ntiles, counts, parity, write_snap);
   else
-    hipLaunchKernelGGL((step2_kernel<TX, false, false>), grid, block, 0, s, descs, tiles, ntiles,
-                       counts, parity, write_snap);
+    hipLaunchKernelGGL((step2_kernel<P, TX, false, false>), grid, block, 0, s, descs, tiles,
+                       ntiles, counts, parity, write_snap);
+}
+
+template <typename P>
+hipError_t launch_step2_p(const CavDesc *descs, const Tile *tiles, int32_t ntiles,
+                          int32_t *counts, int parity, int write_snap, int raw, int rows,
+                          int tile_x, hipStream_t s) {
+  if (tile_x == kFusedXWide)
+    launch_step2_tx<P, kFusedXWide>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
+                                    s);
+  else if (tile_x == kFusedX)
+    launch_step2_tx<P, kFusedX>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows, s);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 }  // namespace
 
 hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
-                        int parity, int write_snap, int raw, int rows, int tile_x, hipStream_t s) {
+                        int parity, int write_snap, int storage, int raw, int rows, int tile_x,
+                        hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (tile_x == kFusedXWide)
-    launch_step2_tx<kFusedXWide>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows, s);
-  else if (tile_x == kFusedX)
-    launch_step2_tx<kFusedX>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows, s);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (storage == 0)  // FP32 planes, FP64 arithmetic
+    return launch_step2_p<StoreF32>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
+                                    tile_x, s);
+  if (storage == 3)  // FP32 planes, FP32 arithmetic
+    return launch_step2_p<StoreF32C>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
+                                     tile_x, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int parity,

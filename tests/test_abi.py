@@ -120,6 +120,12 @@ def test_workspace_bytes():
     assert n.value > 2 * 14 * 4 * (64 * 64 + 128 * 30)
     arr[1].storage = 1
     assert lib.clb_workspace_bytes(arr, 2, C.byref(n)) == B.ERR_ARG  # storage must agree
+    # FP32 planes with FP32 arithmetic: the same planes as FP32 storage
+    arr[1].storage = 0
+    assert lib.clb_workspace_bytes(arr, 2, C.byref(n)) == 0
+    f32 = n.value
+    arr[0].storage = arr[1].storage = B.STORE_F32C
+    assert lib.clb_workspace_bytes(arr, 2, C.byref(n)) == 0 and n.value == f32
 
 
 def test_create_rejects_small_workspace():

@@ -20,8 +20,9 @@ def test_traffic_summary_matches_the_kernel_source():
     import bench
     data = json.load(open(os.path.join(ROOT, "profiles", "step_kernel_traffic.json")))
     h = bench.kernel_source_hash()
-    for key in ("cavity4096_f32", "cavity4096_f32_single", "cavity4096_f16", "cavity4096_mixed",
-                "batch256_f32", "channel2048_f32"):
+    for key in ("cavity4096_f32", "cavity4096_f32_single", "cavity4096_f32c",
+                "cavity4096_f32c_single", "cavity4096_f16", "cavity4096_mixed", "batch256_f32",
+                "channel2048_f32"):
         assert data[key]["kernel_hash"] == h, key
         t = bench.measured_traffic(key)
         # one step per launch: close to the populations read and written once;
@@ -31,7 +32,7 @@ def test_traffic_summary_matches_the_kernel_source():
         assert os.path.exists(os.path.join(ROOT, "profiles", "step_kernel_%s.md" % key))
     # the FP32 records of the default launch mode come from the two-step
     # kernel, the "single" one from the one-step kernel
-    for key in ("cavity4096_f32", "batch256_f32", "channel2048_f32"):
+    for key in ("cavity4096_f32", "cavity4096_f32c", "batch256_f32", "channel2048_f32"):
         assert data[key]["steps_per_launch"] == 2 and "step2_kernel" in data[key]["kernel"], key
     one, two = data["cavity4096_f32_single"], data["cavity4096_f32"]
     assert one["steps_per_launch"] == 1 and "step2_kernel" not in one["kernel"]
@@ -42,6 +43,12 @@ def test_traffic_summary_matches_the_kernel_source():
     per_lu_two = two["valu_instr_per_launch"] / (2 * two["nodes"])
     assert 1.0 < per_lu_two / per_lu_one < 660 / 512 + 0.05
     # the roofline of the measured launch time stays below the issue peak
-    r = bench.alu_roofline("cavity4096_f32", two["nodes"], two["avg_launch_us"] / 2e3, 112)
-    assert 0 < r["frac"] <= r["valu_issued_frac"] < 1
+    r = bench.two_step_roofline("cavity4096_f32", "f32", two["nodes"], two["avg_launch_us"] / 2e3,
+                                112)
+    assert r["bound"] == "alu" and r["other_bound"]["bound"] == "hbm"
+    assert 0 < r["frac"] <= r["valu_issued_frac"] < 1 and r["other_bound"]["frac"] < r["frac"]
     assert r["traffic"] == two["bytes_per_launch"] and 0 < r["fp64_frac"] < 1
+    # FP32 arithmetic: no FP64 work, fewer instructions per node update
+    c1 = data["cavity4096_f32c_single"]
+    assert c1["fp64_flops_per_launch"] == 0
+    assert c1["valu_instr_per_launch"] < one["valu_instr_per_launch"]

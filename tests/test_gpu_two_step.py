@@ -1,12 +1,19 @@
 """GPU: two time steps per launch (clb_set_steps_per_launch(ctx, 2), FP32
-storage) against single steps on the same inputs, over every side kind, the
-porosity field, the per-row acceleration, the raw-moment collision, ragged
-domains narrower and wider than the tiles (64 x 8; 128 x 8 when every domain
-of the context is at least 128 wide), and retirement in clb_run; and against
-the FP64 oracle.  Interior tiles of the 128-wide kernel skip the per-node
-side tests; the wide cases hold both kinds.  Both paths do the same
-arithmetic on the same stored values, so they agree to the last bits
-(asserted within 1e-12 relative; bit equality is logged)."""
+planes with FP64 or FP32 arithmetic) against single steps on the same inputs,
+over every side kind, the porosity field, the per-row acceleration, the
+raw-moment collision, ragged domains narrower and wider than the tiles
+(64 x 8; 128 x 8 when every domain of the context is at least 128 wide), and
+retirement in clb_run; and against the FP64 oracle.  Interior tiles of the
+128-wide kernel skip the per-node side tests; the wide cases hold both kinds.
+
+Both launch modes do the same arithmetic on the same stored values.  With
+FP64 arithmetic the two agree to the last bit (asserted within 1e-12
+relative; bit equality is logged): the stochastic rounding into FP32 absorbs
+the last-place differences that the compiler's separate choices of fused
+multiply-adds in the two kernels can make.  With FP32 arithmetic such a
+difference reaches the stored value, so the two modes are held to the FP32
+tolerance (1e-6) against each other, and to the error that FP32 arithmetic
+reaches against the oracle (5e-6; it misses the 1e-6 target)."""
 import sys
 
 import numpy as np
@@ -90,10 +97,19 @@ def start(s, cases):
         s.set_state(k, T, u, v)
 
 
-@pytest.mark.parametrize("name", CASE_NAMES)
-def test_two_step_launches_match_single_steps(B, name):
-    cases = make_cases(name)
-    log(name)
+# FP32 planes with FP64 arithmetic on every case; with FP32 arithmetic on a
+# subset reaching both tile widths, both tile paths, walls, periodic sides,
+# inlet/outlet, per-row acceleration and MRT
+F32C_CASES = ["cavity 97x70", "periodic narrow 3x17 channel with rows",
+              "inlet/outlet with porosity map", "mrt batch", "wide cavity 300x37 (ragged last tiles)",
+              "wide batch: cavity, channel with rows, inlet/outlet", "mixed widths, mrt"]
+
+
+@pytest.mark.parametrize("name,storage", [(n, "f32") for n in CASE_NAMES] +
+                         [(n, "f32c") for n in F32C_CASES])
+def test_two_step_launches_match_single_steps(B, name, storage):
+    cases = [dict(c, storage=storage) for c in make_cases(name)]
+    log(name, storage)
     runs = []
     for k in (1, 2):
         s = B.Solver(cases)
@@ -110,9 +126,13 @@ def test_two_step_launches_match_single_steps(B, name):
         same = all(np.array_equal(ma[k], mb[k]) for k in ma)
         log("  domain %d (%dx%d): max rel-L2 difference %.2e, bit-identical %s"
             % (i, c["nx"], c["ny"], d, same))
-        assert d <= 1e-12
+        assert d <= (1e-12 if storage == "f32" else 1e-6)
     ra, rb = a.residual_all(), b.residual_all()
-    assert np.allclose(ra[0], rb[0], rtol=1e-9, atol=0) and np.allclose(ra[2], rb[2], rtol=1e-12)
+    if storage == "f32":
+        assert np.allclose(ra[0], rb[0], rtol=1e-9, atol=0)
+        assert np.allclose(ra[2], rb[2], rtol=1e-12)
+    else:
+        assert np.allclose(ra[2], rb[2], rtol=1e-9)  # mass
     assert a.steps_done == b.steps_done == 142
 
 
@@ -126,9 +146,10 @@ ORACLE_CASES = {
 
 
 @pytest.mark.parametrize("name", list(ORACLE_CASES))
-def test_two_step_launches_match_oracle(B, name):
+@pytest.mark.parametrize("storage", ["f32", "f32c"])
+def test_two_step_launches_match_oracle(B, name, storage):
     sizes, k = ORACLE_CASES[name]
-    cases = [cavity(nx, ny=ny, Ra=1e3, Da=1e-2, phi=0.6) for nx, ny in sizes]
+    cases = [cavity(nx, ny=ny, Ra=1e3, Da=1e-2, phi=0.6, storage=storage) for nx, ny in sizes]
     s = B.Solver(cases)
     s.set_steps_per_launch(2)
     for i, (nx, ny) in enumerate(sizes):
@@ -140,9 +161,10 @@ def test_two_step_launches_match_oracle(B, name):
     lat.step(5000)
     g, o = s.macros(k), lat.macros()
     eu, eT = vel_rel_l2(g, o), rel_l2(g["T"], o["T"])
-    log("two-step %s, domain %dx%d, 5000 steps: rel-L2 u %.2e T %.2e"
-        % (name, case["nx"], case["ny"], eu, eT))
-    assert eu <= 1e-6 and eT <= 1e-6
+    log("two-step %s %s, domain %dx%d, 5000 steps: rel-L2 u %.2e T %.2e"
+        % (name, storage, case["nx"], case["ny"], eu, eT))
+    tol = 1e-6 if storage == "f32" else 5e-6  # FP32 arithmetic: see the parity tests
+    assert eu <= tol and eT <= tol
     assert abs(s.nusselt(k, 0) - lat.nusselt(0)) <= 1e-4
 
 
