@@ -2,9 +2,9 @@
 planes with FP64 or FP32 arithmetic) against single steps on the same inputs,
 over every side kind, the porosity field, the per-row acceleration, the
 raw-moment collision, ragged domains narrower and wider than the tiles
-(64 x 8; 128 x 8 when every domain of the context is at least 128 wide), and
-retirement in clb_run; and against the FP64 oracle.  Interior tiles of the
-128-wide kernel skip the per-node side tests; the wide cases hold both kinds.
+(64 x 8; 128 x 8 when every domain of the context is at least 128 wide),
+and retirement in clb_run; and against the FP64 oracle.  Interior tiles of the 128-wide kernel skip the per-node side
+tests; the wide cases hold both kinds.
 
 Both launch modes do the same arithmetic on the same stored values.  With
 FP64 arithmetic the two agree to the last bit (asserted within 1e-12
@@ -136,36 +136,38 @@ def test_two_step_launches_match_single_steps(B, name, storage):
     assert a.steps_done == b.steps_done == 142
 
 
-# (tile width, domains, the domain compared).  The 128-wide compared domain
-# holds both edge tiles and interior tiles (regions clear of every side, run
-# without the per-node side tests).
+# (domains, the domains compared).  The 128-wide compared domain holds both
+# edge tiles and interior tiles (regions clear of every side, run without the
+# per-node side tests).
 ORACLE_CASES = {
-    "64 x 8 tiles": ([(40, 24), (200, 40)], 1),
-    "128 x 8 tiles": ([(260, 40)], 0),
+    "64 x 8 tiles": ([(100, 40)], [0]),
+    "128 x 8 tiles": ([(260, 40)], [0]),
+    "64 x 8 tiles, narrow and wide domain": ([(40, 24), (260, 40)], [0, 1]),
 }
 
 
 @pytest.mark.parametrize("name", list(ORACLE_CASES))
 @pytest.mark.parametrize("storage", ["f32", "f32c"])
 def test_two_step_launches_match_oracle(B, name, storage):
-    sizes, k = ORACLE_CASES[name]
+    sizes, compared = ORACLE_CASES[name]
     cases = [cavity(nx, ny=ny, Ra=1e3, Da=1e-2, phi=0.6, storage=storage) for nx, ny in sizes]
     s = B.Solver(cases)
     s.set_steps_per_launch(2)
     for i, (nx, ny) in enumerate(sizes):
         s.set_state(i, inputs.cavity_initial_T(nx, seed=1, ny=ny))
-    case = cases[k]
-    lat = oracle_lattice(case)
-    lat.init_equilibrium(inputs.cavity_initial_T(sizes[k][0], seed=1, ny=sizes[k][1]))
     s.step(5000)
-    lat.step(5000)
-    g, o = s.macros(k), lat.macros()
-    eu, eT = vel_rel_l2(g, o), rel_l2(g["T"], o["T"])
-    log("two-step %s %s, domain %dx%d, 5000 steps: rel-L2 u %.2e T %.2e"
-        % (name, storage, case["nx"], case["ny"], eu, eT))
     tol = 1e-6 if storage == "f32" else 5e-6  # FP32 arithmetic: see the parity tests
-    assert eu <= tol and eT <= tol
-    assert abs(s.nusselt(k, 0) - lat.nusselt(0)) <= 1e-4
+    for k in compared:
+        case = cases[k]
+        lat = oracle_lattice(case)
+        lat.init_equilibrium(inputs.cavity_initial_T(sizes[k][0], seed=1, ny=sizes[k][1]))
+        lat.step(5000)
+        g, o = s.macros(k), lat.macros()
+        eu, eT = vel_rel_l2(g, o), rel_l2(g["T"], o["T"])
+        log("two-step %s %s, domain %dx%d, 5000 steps: rel-L2 u %.2e T %.2e"
+            % (name, storage, case["nx"], case["ny"], eu, eT))
+        assert eu <= tol and eT <= tol
+        assert abs(s.nusselt(k, 0) - lat.nusselt(0)) <= 1e-4
 
 
 def test_two_step_run_with_retirement_matches(B):
