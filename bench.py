@@ -29,6 +29,7 @@ Other workloads (--workload):
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -42,10 +43,18 @@ HBM_PEAK_GBS = 8000.0
 REDUCE_EVERY = 100
 
 
+def code_only(text):
+    """C++ source with comments removed and whitespace runs collapsed."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
+    """Hash of the step kernels' code (comments and layout ignored)."""
     h = hashlib.sha256()
     for f in ("paper_2110_05943_amd/csrc/clb_kernels.hip", "paper_2110_05943_amd/csrc/clb_internal.h"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        h.update(code_only(open(os.path.join(ROOT, f)).read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -766,10 +766,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) s
 
 // Two time steps of every tile of a two-step tile list (TX x kFusedY nodes,
 // TX = 64 or 128, 4 TX threads: four waves per SIMD either way, as LDS
-// allows) in one launch, FP32 planes.  Step one collides the tile and a
-// one-node ring around it from the source buffer into LDS, rounded exactly as
-// a stored step would be; step two collides the tile again from LDS and
-// stores it to the other buffer.  The populations cross HBM once per two node
+// allows) in one launch, FP32 planes (P: FP64 arithmetic with stochastic
+// rounding, or FP32 arithmetic).  Step one collides the tile and a one-node
+// ring around it from the source buffer into LDS, as FP32 values equal to
+// what a stored step would hold; step two collides the tile again from LDS
+// and stores it to the other buffer.  The populations cross HBM once per two node
 // updates; each ring is recomputed by the neighbouring tiles.  The region is
 // in unwrapped coordinates: the ring of a tile at a periodic side holds the
 // wrapped neighbours, and ring nodes outside a walled side are neither

@@ -52,3 +52,12 @@ def test_traffic_summary_matches_the_kernel_source():
     c1 = data["cavity4096_f32c_single"]
     assert c1["fp64_flops_per_launch"] == 0
     assert c1["valu_instr_per_launch"] < one["valu_instr_per_launch"]
+
+
+def test_kernel_hash_ignores_comments_and_layout():
+    sys.path.insert(0, ROOT)
+    import bench
+    a = "int f(int x) {\n  return x + 1;  // one more\n}\n/* note */"
+    b = "int f(int x) { return x + 1; }"
+    assert bench.code_only(a) == bench.code_only(b)
+    assert bench.code_only(b) != bench.code_only(b.replace("1", "2"))
