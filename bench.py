@@ -847,6 +847,7 @@ def main():
         "config": {"workload": desc, "domains": len(cases), "nodes": nodes,
                    "storage": args.storage, "launch_shape": list(shape),
                    "steps_per_launch": args.steps_per_launch,
+                   "two_step_tile_x": s.get_steps_per_launch()[1],
                    "reductions_every": REDUCE_EVERY},
         "roofline": roofline,
         "state_check": {"res_u_max": float(max(ru)), "res_T_max": float(max(rT)),

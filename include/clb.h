@@ -286,16 +286,28 @@ clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_
  * nodes when every domain is at least 128 wide, else 64 x 8) and a one-node
  * ring around it are collided into LDS, then the tile again from there, so
  * that the populations cross HBM once per two node updates.  The
- * per-node arithmetic and rounding are those of single steps (the results
- * have been bit-identical in every test).  The step that records the residual
+ * per-node arithmetic and rounding are those of single steps: with
+ * CLB_STORE_F32 the results have been bit-identical in every test; with
+ * CLB_STORE_F32C the compiler's separate choices of fused multiply-adds in the
+ * two kernels leave differences at the FP32 rounding level.  The step that records the residual
  * snapshot, an odd remainder, and any step while a domain is retired run
  * singly.  Re-captures the step graphs. */
 clb_status clb_set_steps_per_launch(clb_ctx *ctx, int32_t steps);
 
+/* The launch mode: steps per launch (1 or 2) and the width of the two-step
+ * tiles in nodes (64 or 128; 128 at creation when every domain is at least
+ * that wide, else 64; clb_autotune may change it).  Either pointer may be
+ * NULL. */
+clb_status clb_get_steps_per_launch(clb_ctx *ctx, int32_t *steps, int32_t *tile_x);
+
 /* Time the step kernel over the candidate launch shapes on the live state
- * (which the timing runs advance) and keep the fastest.  When cache_path is
- * non-NULL the choice is read from / appended to that text file, keyed by
- * storage and domain sizes.  Synchronizes. */
+ * (which the timing runs advance) and keep the fastest; with two steps per
+ * launch in effect, also time the two-step kernel with 64-wide tiles and,
+ * when some domain is at least 128 wide, 128-wide tiles, and keep the
+ * faster.  When cache_path is non-NULL the choice is read from / appended to
+ * that text file (one line per context key: key, tile_x, tile_y, blocks and,
+ * when timed, the two-step width), keyed by storage and domain sizes.
+ * Synchronizes. */
 clb_status clb_autotune(clb_ctx *ctx, const char *cache_path);
 
 /* Release the context (not the workspace, which the caller owns). */

@@ -67,6 +67,7 @@ EXPORTS = (
     "clb_macros", "clb_nusselt", "clb_nusselt_all", "clb_residual", "clb_residual_all",
     "clb_set_state", "clb_set_state_device", "clb_set_active", "clb_run", "clb_state_bytes", "clb_get_state", "clb_put_state",
     "clb_steps_done", "clb_set_launch", "clb_get_launch", "clb_set_steps_per_launch",
+    "clb_get_steps_per_launch",
     "clb_autotune", "clb_destroy",
     "clb_strerror",
 )
@@ -104,6 +105,7 @@ def _lib():
             "clb_steps_done": (st, [vp, C.POINTER(C.c_int64)]),
             "clb_set_launch": (st, [vp, C.c_int32, C.c_int32, C.c_int32]),
             "clb_set_steps_per_launch": (st, [vp, C.c_int32]),
+            "clb_get_steps_per_launch": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "clb_get_launch": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]),
             "clb_autotune": (st, [vp, C.c_char_p]),
@@ -319,6 +321,13 @@ class Solver:
     def set_steps_per_launch(self, steps):
         """1 or 2 time steps per kernel launch (2: FP32 planes only, "f32" or "f32c")."""
         _check(_lib().clb_set_steps_per_launch(self._ctx, int(steps)), "clb_set_steps_per_launch")
+
+    def get_steps_per_launch(self):
+        """(steps per launch, two-step tile width in nodes)."""
+        a, b = C.c_int32(), C.c_int32()
+        _check(_lib().clb_get_steps_per_launch(self._ctx, C.byref(a), C.byref(b)),
+               "clb_get_steps_per_launch")
+        return a.value, b.value
 
     def get_launch(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

@@ -1046,6 +1046,24 @@ extern "C" clb_status clb_set_steps_per_launch(clb_ctx *c, int32_t k) {
   return CLB_OK;
 }
 
+extern "C" clb_status clb_get_steps_per_launch(clb_ctx *c, int32_t *steps, int32_t *tile_x) {
+  if (!c) return CLB_ERR_ARG;
+  if (steps) *steps = c->fused ? 2 : 1;
+  if (tile_x) *tile_x = c->tile2_x;
+  return CLB_OK;
+}
+
+namespace {
+// Switch the two-step tiles to width w (64 or 128): rebuild the list and drop
+// the graphs that captured the old one.
+clb_status set_tile2_width(clb_ctx *c, int w) {
+  if (w != clb::kFusedX && w != clb::kFusedXWide) return CLB_ERR_ARG;
+  drop_graphs(c);
+  c->tile2_x = w;
+  return upload_tiles2(c);
+}
+}  // namespace
+
 extern "C" clb_status clb_get_launch(clb_ctx *c, int32_t *tx, int32_t *ty, int32_t *blocks) {
   if (!c) return CLB_ERR_ARG;
   if (tx) *tx = c->shape.tile_x;
@@ -1073,14 +1091,22 @@ extern "C" clb_status clb_autotune(clb_ctx *c, const char *cache_path) {
     std::ifstream in(cache_path);
     std::string line;
     LaunchShape found{0, 0, -1};
+    int found_w = 0;  // two-step tile width; 0: none recorded
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       std::string k;
       LaunchShape s;
-      if (ls >> k >> s.tile_x >> s.tile_y >> s.blocks && k == key && shape_ok(s.tile_x, s.tile_y))
+      if (ls >> k >> s.tile_x >> s.tile_y >> s.blocks && k == key && shape_ok(s.tile_x, s.tile_y)) {
         found = s;
+        int w = 0;
+        found_w = (ls >> w) ? w : 0;
+      }
     }
-    if (found.blocks >= 0) return clb_set_launch(c, found.tile_x, found.tile_y, found.blocks);
+    if (found.blocks >= 0) {
+      const clb_status s = clb_set_launch(c, found.tile_x, found.tile_y, found.blocks);
+      if (s != CLB_OK || found_w == 0) return s;
+      return set_tile2_width(c, found_w);
+    }
   }
   const int shapes[][2] = {{0, 0},   {64, 1},  {64, 2},  {64, 4},  {64, 8}, {128, 1},
                            {128, 2}, {128, 4}, {256, 1}, {256, 2}};
@@ -1120,14 +1146,47 @@ extern "C" clb_status clb_autotune(clb_ctx *c, const char *cache_path) {
       }
     }
   }
+  clb_status s = clb_set_launch(c, best.tile_x, best.tile_y, best.blocks);
+  if (s != CLB_OK) return s;
+  // The two-step tile width, when pairs of steps run per launch: 64, and 128
+  // if some domain is that wide, timed the same way (each launch advances two
+  // steps).
+  int best_w = 0;
+  if (fused_now(c)) {
+    bool wide = false;
+    for (const auto &p : c->p) wide = wide || p.nx >= clb::kFusedXWide;
+    float best2_ms = 1e30f;
+    for (int w : {clb::kFusedX, clb::kFusedXWide}) {
+      if (w == clb::kFusedXWide && !wide) continue;
+      s = set_tile2_width(c, w);
+      if (s != CLB_OK) return s;
+      for (int r = 0; r < 1 + std::max(2, reps / 2); ++r) {
+        if (r == 1) HIPCHK(hipEventRecord(e0, c->stream));  // after one warm-up launch
+        s = launch_two(c, c->stream);
+        if (s != CLB_OK) return s;
+        c->parity ^= 1;
+        c->steps += 2;
+      }
+      HIPCHK(hipEventRecord(e1, c->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best2_ms) {
+        best2_ms = ms;
+        best_w = w;
+      }
+    }
+    s = set_tile2_width(c, best_w);
+    if (s != CLB_OK) return s;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->snap_valid = false;
-  const clb_status s = clb_set_launch(c, best.tile_x, best.tile_y, best.blocks);
-  if (s != CLB_OK) return s;
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << key << " " << best.tile_x << " " << best.tile_y << " " << best.blocks << "\n";
+    o << key << " " << best.tile_x << " " << best.tile_y << " " << best.blocks;
+    if (best_w) o << " " << best_w;
+    o << "\n";
   }
   return CLB_OK;
 }

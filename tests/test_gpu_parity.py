@@ -363,3 +363,34 @@ def test_autotune_picks_a_valid_shape_and_caches_it(Solver, tmp_path):
     s.step(10)
     ru, rT, _ = s.residual(0)
     assert np.isfinite(ru) and np.isfinite(rT)
+    # with two steps per launch the cache line also records the two-step width
+    line = open(cache).read().split()
+    assert len(line) == 5 and int(line[4]) == 64  # no domain is 128 wide
+    assert s.get_steps_per_launch() == (2, 64)
+
+
+def test_autotune_two_step_width_keeps_the_results(Solver, tmp_path):
+    """A wide domain: the tuner times 64- and 128-wide two-step tiles.  Every
+    shape and width gives the same bits (FP32 storage, FP64 arithmetic), so
+    the tuned context matches an untuned one after the same number of steps."""
+    case = cavity(300, ny=72, Ra=1e5, Da=1e-2, phi=0.6)
+    T = inputs.cavity_initial_T(300, seed=2, ny=72)
+    s = Solver(case)
+    s.set_state(0, T)
+    assert s.get_steps_per_launch() == (2, 128)  # the default for a wide context
+    cache = str(tmp_path / "tune.txt")
+    s.autotune(cache)
+    steps, width = s.steps_done, s.get_steps_per_launch()[1]
+    assert width in (64, 128)
+    line = open(cache).read().split()
+    assert len(line) == 5 and int(line[4]) == width
+    s.step(101)
+    ref = Solver(case)
+    ref.set_state(0, T)
+    ref.step(steps + 101)
+    a, b = s.macros(), ref.macros()
+    assert all(np.array_equal(a[k], b[k]) for k in a)
+    # the cached choice applies without timing
+    s2 = Solver(case)
+    s2.autotune(cache)
+    assert s2.steps_done == 0 and s2.get_steps_per_launch()[1] == width
