@@ -232,7 +232,7 @@ Layout make_layout(const clb_params *p, int count) {
   L.tiles_all = take(sizeof(Tile) * L.max_tiles);
   L.tiles_active = take(sizeof(Tile) * (L.max_tiles + 8));
   L.tiles2 = take(sizeof(Tile) * (L.max_tiles2 + 8));
-  L.counts = take(sizeof(int32_t) * 4);
+  L.counts = take(sizeof(int32_t) * 5);
   L.partials = take(sizeof(double) * clb::kRed * L.max_tiles);
   L.gpart = take(sizeof(double) * clb::kRed * L.max_tiles);
   L.results = take(sizeof(double) * clb::kRed * count);
@@ -285,7 +285,10 @@ struct clb_ctx {
   hipStream_t cap_stream = nullptr;
   CavDesc *d_desc = nullptr;
   Tile *d_tiles_all = nullptr, *d_tiles_active = nullptr, *d_tiles2 = nullptr;
-  int32_t ntiles2 = 0;  // length of the XCD-ordered two-step tile list
+  // Grid of the two-step kernel: the XCD-ordered list length over all
+  // domains; the list itself holds the active domains (its length in
+  // counts[4], which the kernel reads, so graphs survive retirement).
+  int32_t ntiles2 = 0;
   int tile2_x = clb::kFusedX;  // two-step tile width: 128 when every domain is that wide
   int32_t *d_counts = nullptr;
   double *d_partials = nullptr, *d_gpart = nullptr, *d_results = nullptr, *d_nu = nullptr,
@@ -455,13 +458,17 @@ clb_status upload_tiles(clb_ctx *c) {
 // computed by both tiles with identical results.
 int tile2_origin(int i, int tile, int n) { return n >= tile ? std::min(i * tile, n - tile) : 0; }
 
-// The two-step tile list: every tile of every domain, laid out for the XCDs
-// like the active list.  It does not change after creation; the two-step
-// kernel runs only while every domain is active.
+// The two-step tile list: every tile of every active domain, laid out for the
+// XCDs like the active list, with its length in counts[4].
 clb_status upload_tiles2(clb_ctx *c) {
   std::vector<Tile> order;
+  size_t all = 0;
   for (int k = 0; k < c->count; ++k) {
     const int nx = c->p[k].nx, ny = c->p[k].ny;
+    const size_t per = (size_t)((nx + c->tile2_x - 1) / c->tile2_x) *
+                       ((ny + clb::kFusedY - 1) / clb::kFusedY);
+    all += per;
+    if (!c->active[k]) continue;
     const int w = c->tile2_x, h = clb::kFusedY;
     const int tx = (nx + w - 1) / w;
     const int ty = (ny + h - 1) / h;
@@ -480,9 +487,12 @@ clb_status upload_tiles2(clb_ctx *c) {
     const size_t t = (b % kXcds) * m + b / kXcds;
     if (t < n) list[b] = order[t];
   }
-  c->ntiles2 = (int32_t)list.size();
-  HIPCHK(hipMemcpyAsync(c->d_tiles2, list.data(), sizeof(Tile) * list.size(),
-                        hipMemcpyHostToDevice, c->stream));
+  c->ntiles2 = (int32_t)((all + kXcds - 1) / kXcds * kXcds);
+  const int32_t n2 = (int32_t)list.size();
+  if (!list.empty())
+    HIPCHK(hipMemcpyAsync(c->d_tiles2, list.data(), sizeof(Tile) * list.size(),
+                          hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_counts + 4, &n2, sizeof(n2), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return CLB_OK;
 }
@@ -490,8 +500,8 @@ clb_status upload_tiles2(clb_ctx *c) {
 bool fused_now(const clb_ctx *c) {
   if (!c->fused) return false;
   for (int k = 0; k < c->count; ++k)
-    if (!c->active[k]) return false;
-  return true;
+    if (c->active[k]) return true;
+  return false;
 }
 
 bool shape_ok(int tx, int ty) {
@@ -887,8 +897,21 @@ extern "C" clb_status clb_set_state_device(clb_ctx *c, int32_t cav, const float 
 
 extern "C" clb_status clb_set_active(clb_ctx *c, const uint8_t *active) {
   if (!c || !active) return CLB_ERR_ARG;
-  for (int k = 0; k < c->count; ++k) c->active[k] = active[k] ? 1 : 0;
-  return upload_tiles(c);
+  for (int k = 0; k < c->count; ++k) {
+    const uint8_t a = active[k] ? 1 : 0;
+    if (c->active[k] && !a) {
+      // A domain that stops keeps its state in both buffers, so that it
+      // reads the same whatever the parity of later steps of the others.
+      const char *src = c->parity ? c->desc[k].B : c->desc[k].A;
+      char *dst = c->parity ? c->desc[k].A : c->desc[k].B;
+      HIPCHK(hipMemcpyAsync(dst, src, (size_t)c->desc[k].plane * pop_bytes(c->storage),
+                            hipMemcpyDeviceToDevice, c->stream));
+    }
+    c->active[k] = a;
+  }
+  clb_status s = upload_tiles(c);
+  if (s == CLB_OK) s = upload_tiles2(c);
+  return s;
 }
 
 // ------------------------------------------------------ run to steady state

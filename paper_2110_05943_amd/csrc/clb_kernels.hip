@@ -774,16 +774,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) s
 // updates; each ring is recomputed by the neighbouring tiles.  The region is
 // in unwrapped coordinates: the ring of a tile at a periodic side holds the
 // wrapped neighbours, and ring nodes outside a walled side are neither
-// computed nor read (boundary nodes gather inward).  counts[2 + parity]
-// holds the index of the first step; the kernel passes step + 2 on.
+// computed nor read (boundary nodes gather inward).  counts[4] holds the
+// length of the tile list (the active domains; the grid may be longer),
+// counts[2 + parity] the index of the first step, and the kernel passes
+// step + 2 on.
 template <typename P, int TX, bool RAW, bool ROWS>
 __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict__ descs,
-                                                       const Tile *__restrict__ tiles, int ntiles,
+                                                       const Tile *__restrict__ tiles,
                                                        int32_t *__restrict__ counts, int parity,
                                                        int write_snap) {
   using R = typename P::R;
   constexpr int kRegionW = Region<TX>::W, kRegion = Region<TX>::N;
   __shared__ float lds[kPlanes * kRegion];
+  const int ntiles = counts[4];  // the list of the active domains
   const uint32_t step = (uint32_t)counts[2 + parity];
   if (blockIdx.x == 0 && threadIdx.x == 0) counts[3 - parity] = (int32_t)(step + 2);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -1170,17 +1173,17 @@ void launch_step2_tx(const CavDesc *descs, const Tile *tiles, int32_t ntiles, in
                      int parity, int write_snap, int raw, int rows, hipStream_t s) {
   const dim3 grid(ntiles), block(TX * 4);
   if (raw && rows)
-    hipLaunchKernelGGL((step2_kernel<P, TX, true, true>), grid, block, 0, s, descs, tiles, ntiles,
-                       counts, parity, write_snap);
+    hipLaunchKernelGGL((step2_kernel<P, TX, true, true>), grid, block, 0, s, descs, tiles, counts,
+                       parity, write_snap);
   else if (raw)
     hipLaunchKernelGGL((step2_kernel<P, TX, true, false>), grid, block, 0, s, descs, tiles,
-                       ntiles, counts, parity, write_snap);
+                       counts, parity, write_snap);
   else if (rows)
     hipLaunchKernelGGL((step2_kernel<P, TX, false, true>), grid, block, 0, s, descs, tiles,
-                       ntiles, counts, parity, write_snap);
+                       counts, parity, write_snap);
   else
     hipLaunchKernelGGL((step2_kernel<P, TX, false, false>), grid, block, 0, s, descs, tiles,
-                       ntiles, counts, parity, write_snap);
+                       counts, parity, write_snap);
 }
 
 template <typename P>
