@@ -227,7 +227,10 @@ clb_status clb_set_state(clb_ctx *ctx, int32_t cavity, const double *u, const do
 clb_status clb_set_state_device(clb_ctx *ctx, int32_t cavity, const float *d_fields,
                                 int64_t stride, double u_scale, double T_offset);
 
-/* Choose which domains clb_step advances (active[i] != 0).  Synchronizes. */
+/* Choose which domains clb_step advances (active[i] != 0).  A domain that
+ * stops has its current state copied into its second buffer, so it reads the
+ * same (and later resumes from the same state) whatever the parity of the
+ * steps the others take meanwhile.  Synchronizes. */
 clb_status clb_set_active(clb_ctx *ctx, const uint8_t *active);
 
 /* Run to steady state with retirement (batched stepping of many domains).
@@ -288,10 +291,11 @@ clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_
  * that the populations cross HBM once per two node updates.  The
  * per-node arithmetic and rounding are those of single steps: with
  * CLB_STORE_F32 the results have been bit-identical in every test; with
- * CLB_STORE_F32C the compiler's separate choices of fused multiply-adds in the
- * two kernels leave differences at the FP32 rounding level.  The step that records the residual
- * snapshot, an odd remainder, and any step while a domain is retired run
- * singly.  Re-captures the step graphs. */
+ * CLB_STORE_F32C the compiler's separate choices of fused multiply-adds in
+ * the two kernels leave differences at the FP32 rounding level.  The step
+ * that records the residual snapshot and an odd remainder run singly; retired
+ * domains simply drop out of the two-step tile list.  Re-captures the step
+ * graphs. */
 clb_status clb_set_steps_per_launch(clb_ctx *ctx, int32_t steps);
 
 /* The launch mode: steps per launch (1 or 2) and the width of the two-step
