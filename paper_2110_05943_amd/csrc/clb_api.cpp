@@ -861,6 +861,20 @@ extern "C" clb_status clb_residual_all(clb_ctx *c, double *res_u, double *res_T,
   return CLB_OK;
 }
 
+namespace {
+// An inactive domain keeps the same state in both buffers (the parity of the
+// others' later steps must not matter): after its state is written, stream-
+// ordered, copy the current buffer into the other one.
+clb_status mirror_if_inactive(clb_ctx *c, int k) {
+  if (c->active[k]) return CLB_OK;
+  const char *src = c->parity ? c->desc[k].B : c->desc[k].A;
+  char *dst = c->parity ? c->desc[k].A : c->desc[k].B;
+  HIPCHK(hipMemcpyAsync(dst, src, (size_t)c->desc[k].plane * pop_bytes(c->storage),
+                        hipMemcpyDeviceToDevice, c->stream));
+  return CLB_OK;
+}
+}  // namespace
+
 extern "C" clb_status clb_set_state(clb_ctx *c, int32_t cav, const double *u, const double *v,
                                     const double *T) {
   if (!c || cav < 0 || cav >= c->count || !T) return CLB_ERR_ARG;
@@ -877,6 +891,8 @@ extern "C" clb_status clb_set_state(clb_ctx *c, int32_t cav, const double *u, co
                         c->stream));
   HIPCHK(clb::launch_init(c->d_desc, cav, p.nx, p.ny, c->parity, c->d_obs, 0.0f, c->storage,
                           c->stream));
+  const clb_status s = mirror_if_inactive(c, cav);
+  if (s != CLB_OK) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
   c->snap_valid = false;
   return CLB_OK;
@@ -892,22 +908,19 @@ extern "C" clb_status clb_set_state_device(clb_ctx *c, int32_t cav, const float 
   HIPCHK(clb::launch_init(c->d_desc, cav, p.nx, p.ny, c->parity, c->d_obs, 0.0f, c->storage,
                           c->stream));
   c->snap_valid = false;
-  return CLB_OK;
+  return mirror_if_inactive(c, cav);
 }
 
 extern "C" clb_status clb_set_active(clb_ctx *c, const uint8_t *active) {
   if (!c || !active) return CLB_ERR_ARG;
   for (int k = 0; k < c->count; ++k) {
     const uint8_t a = active[k] ? 1 : 0;
-    if (c->active[k] && !a) {
-      // A domain that stops keeps its state in both buffers, so that it
-      // reads the same whatever the parity of later steps of the others.
-      const char *src = c->parity ? c->desc[k].B : c->desc[k].A;
-      char *dst = c->parity ? c->desc[k].A : c->desc[k].B;
-      HIPCHK(hipMemcpyAsync(dst, src, (size_t)c->desc[k].plane * pop_bytes(c->storage),
-                            hipMemcpyDeviceToDevice, c->stream));
-    }
+    const bool stops = c->active[k] && !a;
     c->active[k] = a;
+    if (stops) {  // a domain that stops keeps its state in both buffers
+      const clb_status s = mirror_if_inactive(c, k);
+      if (s != CLB_OK) return s;
+    }
   }
   clb_status s = upload_tiles(c);
   if (s == CLB_OK) s = upload_tiles2(c);
@@ -1038,6 +1051,8 @@ extern "C" clb_status clb_put_state(clb_ctx *c, const void *host_buf, size_t byt
     const size_t b = (size_t)c->desc[k].plane * pop_bytes(c->storage);
     char *dst = c->parity ? c->desc[k].B : c->desc[k].A;
     HIPCHK(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, c->stream));
+    const clb_status s = mirror_if_inactive(c, k);
+    if (s != CLB_OK) return s;
     src += b;
   }
   HIPCHK(hipStreamSynchronize(c->stream));

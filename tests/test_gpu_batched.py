@@ -130,6 +130,19 @@ def test_retired_domain_keeps_its_state_under_odd_rounds(B):
     s.close()
 
 
+def test_state_written_to_an_inactive_domain_survives_odd_steps(B):
+    """clb_set_state on a stopped domain, then an odd number of steps of the
+    other: the stopped domain still holds what was written."""
+    s = B.Solver([cavity(24, Ra=1e3), cavity(32, Ra=1e4)])
+    s.set_active([0, 1])
+    s.set_state(0, inputs.cavity_initial_T(24, seed=5, amp=0.1))
+    m0 = s.macros(0)
+    s.step(7)
+    m1 = s.macros(0)
+    assert all(np.array_equal(m0[k], m1[k]) for k in m0)
+    s.close()
+
+
 def test_run_argument_errors(B):
     s = B.Solver(cavity(16, Ra=1e3))
     for kw in (dict(check_every=0), dict(tol=-1.0), dict(tol=float("nan")),
