@@ -140,6 +140,15 @@ def test_state_written_to_an_inactive_domain_survives_odd_steps(B):
     s.step(7)
     m1 = s.macros(0)
     assert all(np.array_equal(m0[k], m1[k]) for k in m0)
+    # likewise a checkpoint restored while the domain is stopped
+    blob = s.get_state()
+    s.set_active([1, 1])
+    s.step(3)
+    s.set_active([0, 1])
+    s.put_state(blob)
+    s.step(5)
+    m2 = s.macros(0)
+    assert all(np.array_equal(m0[k], m2[k]) for k in m0)
     s.close()
 
 
