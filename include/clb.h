@@ -283,8 +283,8 @@ clb_status clb_steps_done(clb_ctx *ctx, int64_t *steps);
 clb_status clb_set_launch(clb_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t blocks);
 clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_t *blocks);
 
-/* Time steps per kernel launch: 1, or 2 (FP32 planes only: CLB_STORE_F32 or
- * CLB_STORE_F32C, else CLB_ERR_ARG; 2 is their default).  With 2, pairs of
+/* Time steps per kernel launch: 1 or 2 (else CLB_ERR_ARG); 2 is the default
+ * for every storage mode but CLB_STORE_F16.  With 2, pairs of
  * steps run in one launch while every domain is active: each tile (128 x 8
  * nodes when every domain is at least 128 wide, else 64 x 8) and a one-node
  * ring around it are collided into LDS, then the tile again from there, so

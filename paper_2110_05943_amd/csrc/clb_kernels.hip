@@ -65,22 +65,30 @@ __device__ __forceinline__ float round_sr(double v, uint32_t r) {
   u &= ~((1ull << 29) - 1ull);
   return (float)__longlong_as_double((long long)u);
 }
-__device__ __forceinline__ void stv(float *p, double v, uint32_t r) {
-  __builtin_nontemporal_store(round_sr(v, r), (gptr<float>)p);
-}
+// The stored value of a post-collision deviation v with random word r; the
+// pointer argument only selects the storage type.
+__device__ __forceinline__ float enc(const float *, double v, uint32_t r) { return round_sr(v, r); }
 // FP32 -> FP16 (scaled) with stochastic rounding: 12 random bits below the
 // FP16 precision (13 bits lie below a normal FP16 significand).
-__device__ __forceinline__ void stv(_Float16 *p, float v, uint32_t r) {
+__device__ __forceinline__ _Float16 enc(const _Float16 *, float v, uint32_t r) {
   uint32_t u = __float_as_uint(v * kF16Scale);
   u += (r & 0xFFFu) << 1;
   u &= 0xFFFFE000u;
-  __builtin_nontemporal_store((_Float16)__uint_as_float(u), (gptr<_Float16>)p);
+  return (_Float16)__uint_as_float(u);
+}
+// FP32 -> FP32: no rounding (FP32 planes computed in FP32).
+__device__ __forceinline__ float enc(const float *, float v, uint32_t) { return v; }
+
+template <typename T, typename R>
+__device__ __forceinline__ void stv(T *p, R v, uint32_t r) {
+  __builtin_nontemporal_store(enc(p, v, r), (gptr<T>)p);
 }
 
-// FP32 -> FP32: no rounding (mixed storage computes the FP32 planes in FP32).
-__device__ __forceinline__ void stv(float *p, float v, uint32_t) {
-  __builtin_nontemporal_store(v, (gptr<float>)p);
-}
+// The deviation a stored value stands for (the inverse scaling of enc).
+template <typename R>
+__device__ __forceinline__ R dec(float v) { return (R)v; }
+template <typename R>
+__device__ __forceinline__ R dec(_Float16 v) { return (R)((float)v * kF16Unscale); }
 
 // Storage policy: element types of the 9 D2Q9 planes (F) and the 5 D2Q5
 // planes (G) and the arithmetic type R.  A population buffer holds the F
@@ -328,39 +336,54 @@ struct Region {
   static constexpr int N = W * (kFusedY + 2);
 };
 
-template <int TX>
+// The LDS region of a two-step tile in the storage types of P: the 9 D2Q9
+// planes (P::F) and then the 5 D2Q5 planes (P::G), Region<TX>::N elements
+// each, holding the values the stored planes would hold.
+template <typename P, int TX>
+struct RegionPlanes {
+  static constexpr int kBytes =
+      Region<TX>::N * (9 * (int)sizeof(typename P::F) + 5 * (int)sizeof(typename P::G));
+  __device__ static typename P::F *f(char *lds) { return (typename P::F *)lds; }
+  __device__ static typename P::G *g(char *lds) {
+    return (typename P::G *)(lds + 9 * Region<TX>::N * sizeof(typename P::F));
+  }
+};
+
+template <typename P, int TX>
 struct LdsSrc {
   static constexpr int kRegionW = Region<TX>::W, kRegion = Region<TX>::N;
-  const float *lds;
+  char *lds;
   int ox, oy;
 
   template <typename R>
   __device__ __forceinline__ void pull(const CavDesc &, int xs, int ys, R f[9], R g[5]) const {
     const int c = (ys - oy) * kRegionW + (xs - ox);
     const int W = kRegionW;
-    f[0] = (R)lds[c];
-    f[1] = (R)lds[kRegion + c - 1];
-    f[2] = (R)lds[2 * kRegion + c - W];
-    f[3] = (R)lds[3 * kRegion + c + 1];
-    f[4] = (R)lds[4 * kRegion + c + W];
-    f[5] = (R)lds[5 * kRegion + c - W - 1];
-    f[6] = (R)lds[6 * kRegion + c - W + 1];
-    f[7] = (R)lds[7 * kRegion + c + W + 1];
-    f[8] = (R)lds[8 * kRegion + c + W - 1];
-    g[0] = (R)lds[9 * kRegion + c];
-    g[1] = (R)lds[10 * kRegion + c - 1];
-    g[2] = (R)lds[11 * kRegion + c - W];
-    g[3] = (R)lds[12 * kRegion + c + 1];
-    g[4] = (R)lds[13 * kRegion + c + W];
+    const typename P::F *F = RegionPlanes<P, TX>::f(lds);
+    const typename P::G *G = RegionPlanes<P, TX>::g(lds);
+    f[0] = dec<R>(F[c]);
+    f[1] = dec<R>(F[kRegion + c - 1]);
+    f[2] = dec<R>(F[2 * kRegion + c - W]);
+    f[3] = dec<R>(F[3 * kRegion + c + 1]);
+    f[4] = dec<R>(F[4 * kRegion + c + W]);
+    f[5] = dec<R>(F[5 * kRegion + c - W - 1]);
+    f[6] = dec<R>(F[6 * kRegion + c - W + 1]);
+    f[7] = dec<R>(F[7 * kRegion + c + W + 1]);
+    f[8] = dec<R>(F[8 * kRegion + c + W - 1]);
+    g[0] = dec<R>(G[c]);
+    g[1] = dec<R>(G[kRegion + c - 1]);
+    g[2] = dec<R>(G[2 * kRegion + c - W]);
+    g[3] = dec<R>(G[3 * kRegion + c + 1]);
+    g[4] = dec<R>(G[4 * kRegion + c + W]);
   }
 
   template <typename R>
   __device__ __forceinline__ R gsum(const CavDesc &, int xs, int ys) const {
     const int c = (ys - oy) * kRegionW + (xs - ox);
     const int W = kRegionW;
-    return (R)lds[9 * kRegion + c] +
-           (((R)lds[10 * kRegion + c - 1] + (R)lds[12 * kRegion + c + 1]) +
-            ((R)lds[11 * kRegion + c - W] + (R)lds[13 * kRegion + c + W]));
+    const typename P::G *G = RegionPlanes<P, TX>::g(lds);
+    return dec<R>(G[c]) + ((dec<R>(G[kRegion + c - 1]) + dec<R>(G[3 * kRegion + c + 1])) +
+                           (dec<R>(G[2 * kRegion + c - W]) + dec<R>(G[4 * kRegion + c + W])));
   }
 };
 
@@ -694,22 +717,23 @@ __device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlan
   }
 }
 
-// The values store_planes writes for FP32 planes, into FP32 values (the
-// two-step kernel's LDS region at element c): FP64 results rounded the same
-// way, FP32 results as they are.
-template <int TX, typename R>
-__device__ __forceinline__ void store_region(const R out[kPlanes], float *lds, int c, int idx,
+// The values store_planes writes (same random words, same rounding) into the
+// two-step kernel's LDS region at element c.
+template <typename P, int TX, typename R = typename P::R>
+__device__ __forceinline__ void store_region(const R out[kPlanes], char *lds, int c, int idx,
                                              uint32_t seed) {
-  if constexpr (sizeof(R) == 8) {
-    uint32_t w = mix32((uint32_t)idx + seed);
+  typename P::F *F = RegionPlanes<P, TX>::f(lds);
+  typename P::G *G = RegionPlanes<P, TX>::g(lds);
+  constexpr int N = Region<TX>::N;
+  uint32_t w = mix32((uint32_t)idx + seed);
 #pragma unroll
-    for (int i = 0; i < kPlanes; ++i) {
-      lds[i * Region<TX>::N + c] = round_sr(out[i], (i & 1) ? (w >> 16) : w);
-      if (i & 1) w = next_bits<double>(w);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < kPlanes; ++i) lds[i * Region<TX>::N + c] = out[i];
+  for (int i = 0; i < kPlanes; ++i) {
+    const uint32_t r = (i & 1) ? (w >> 16) : w;
+    if (i < 9)
+      F[i * N + c] = enc(F, out[i], r);
+    else
+      G[(i - 9) * N + c] = enc(G, out[i], r);
+    if (i & 1) w = next_bits<R>(w);
   }
 }
 
@@ -785,7 +809,7 @@ __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict
                                                        int write_snap) {
   using R = typename P::R;
   constexpr int kRegionW = Region<TX>::W, kRegion = Region<TX>::N;
-  __shared__ float lds[kPlanes * kRegion];
+  __shared__ __attribute__((aligned(16))) char lds[RegionPlanes<P, TX>::kBytes];
   const int ntiles = counts[4];  // the list of the active domains
   const uint32_t step = (uint32_t)counts[2 + parity];
   if (blockIdx.x == 0 && threadIdx.x == 0) counts[3 - parity] = (int32_t)(step + 2);
@@ -818,18 +842,18 @@ __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict
             node_state<P, ROWS, GlobalSrc<P, EDGE>, EDGE>(d, GlobalSrc<P, EDGE>{A}, x, y, st);
         R out[kPlanes];
         collide<P, RAW, ROWS>(d, st, wall, out);
-        store_region<TX>(out, lds, c, y * d.pitch + x, seed1);
+        store_region<P, TX>(out, lds, c, y * d.pitch + x, seed1);
       }
       __syncthreads();
       const uint32_t seed2 = mix32((step + 1) * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
-      const LdsSrc<TX> src{lds, x0 - 1, y0 - 1};
+      const LdsSrc<P, TX> src{lds, x0 - 1, y0 - 1};
       for (int q = threadIdx.x; q < TX * kFusedY; q += blockDim.x) {
         const int x = x0 + q % TX, y = y0 + q / TX;
         if constexpr (EDGE) {
           if (x >= d.nx || y >= d.ny) continue;
         }
         NodeState<R> st;
-        const bool wall = node_state<P, ROWS, LdsSrc<TX>, EDGE>(d, src, x, y, st);
+        const bool wall = node_state<P, ROWS, LdsSrc<P, TX>, EDGE>(d, src, x, y, st);
         const int idx = y * d.pitch + x;
         collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed2);
         if (write_snap) {
@@ -1211,6 +1235,12 @@ hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles,
   if (storage == 3)  // FP32 planes, FP32 arithmetic
     return launch_step2_p<StoreF32C>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
                                      tile_x, s);
+  if (storage == 1)  // FP16 planes
+    return launch_step2_p<StoreF16>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
+                                    tile_x, s);
+  if (storage == 2)  // FP16 flow, FP32 temperature planes
+    return launch_step2_p<StoreMix>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
+                                    tile_x, s);
   return hipErrorInvalidValue;
 }
 

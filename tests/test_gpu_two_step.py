@@ -106,7 +106,8 @@ F32C_CASES = ["cavity 97x70", "periodic narrow 3x17 channel with rows",
 
 
 @pytest.mark.parametrize("name,storage", [(n, "f32") for n in CASE_NAMES] +
-                         [(n, "f32c") for n in F32C_CASES])
+                         [(n, "f32c") for n in F32C_CASES] +
+                         [(n, st) for n in F32C_CASES for st in ("f16", "mixed")])
 def test_two_step_launches_match_single_steps(B, name, storage):
     cases = [dict(c, storage=storage) for c in make_cases(name)]
     log(name, storage)
@@ -126,13 +127,15 @@ def test_two_step_launches_match_single_steps(B, name, storage):
         same = all(np.array_equal(ma[k], mb[k]) for k in ma)
         log("  domain %d (%dx%d): max rel-L2 difference %.2e, bit-identical %s"
             % (i, c["nx"], c["ny"], d, same))
-        assert d <= (1e-12 if storage == "f32" else 1e-6)
+        assert d <= {"f32": 1e-12, "f32c": 1e-6}.get(storage, 1e-3)
     ra, rb = a.residual_all(), b.residual_all()
     if storage == "f32":
         assert np.allclose(ra[0], rb[0], rtol=1e-9, atol=0)
         assert np.allclose(ra[2], rb[2], rtol=1e-12)
-    else:
+    elif storage == "f32c":
         assert np.allclose(ra[2], rb[2], rtol=1e-9)  # mass
+    else:
+        assert np.allclose(ra[2], rb[2], rtol=1e-6)  # mass with FP16 flow planes
     assert a.steps_done == b.steps_done == 142
 
 
@@ -147,7 +150,7 @@ ORACLE_CASES = {
 
 
 @pytest.mark.parametrize("name", list(ORACLE_CASES))
-@pytest.mark.parametrize("storage", ["f32", "f32c"])
+@pytest.mark.parametrize("storage", ["f32", "f32c", "mixed", "f16"])
 def test_two_step_launches_match_oracle(B, name, storage):
     sizes, compared = ORACLE_CASES[name]
     cases = [cavity(nx, ny=ny, Ra=1e3, Da=1e-2, phi=0.6, storage=storage) for nx, ny in sizes]
@@ -156,7 +159,12 @@ def test_two_step_launches_match_oracle(B, name, storage):
     for i, (nx, ny) in enumerate(sizes):
         s.set_state(i, inputs.cavity_initial_T(nx, seed=1, ny=ny))
     s.step(5000)
-    tol = 1e-6 if storage == "f32" else 5e-6  # FP32 arithmetic: see the parity tests
+    # FP32 arithmetic: 5e-6 (see the parity tests); FP16 planes: 1e-3.  The
+    # hot-wall Nusselt number with all-FP16 storage carries the FP16
+    # temperature noise (~1e-4) times the wall gradient's length scale (the
+    # domain width, up to 259 here): 1e-2.
+    tol = {"f32": 1e-6, "f32c": 5e-6}.get(storage, 1e-3)
+    tol_nu = 1e-2 if storage == "f16" else 1e-4
     for k in compared:
         case = cases[k]
         lat = oracle_lattice(case)
@@ -167,7 +175,7 @@ def test_two_step_launches_match_oracle(B, name, storage):
         log("two-step %s %s, domain %dx%d, 5000 steps: rel-L2 u %.2e T %.2e"
             % (name, storage, case["nx"], case["ny"], eu, eT))
         assert eu <= tol and eT <= tol
-        assert abs(s.nusselt(k, 0) - lat.nusselt(0)) <= 1e-4
+        assert abs(s.nusselt(k, 0) - lat.nusselt(0)) <= tol_nu
 
 
 def test_two_step_run_with_retirement_matches(B):
@@ -185,9 +193,10 @@ def test_two_step_run_with_retirement_matches(B):
     assert rel_l2(out[1][1], out[0][1]) <= 1e-12
 
 
-def test_two_steps_need_fp32_storage(B):
-    s = B.Solver(cavity(32, Ra=1e3, storage="f16"))
-    with pytest.raises(B.CLBError):
+def test_steps_per_launch_argument(B):
+    for st in ("f32", "f32c", "f16", "mixed"):
+        s = B.Solver(cavity(32, Ra=1e3, storage=st))
         s.set_steps_per_launch(2)
-    with pytest.raises(B.CLBError):
-        s.set_steps_per_launch(3)
+        s.set_steps_per_launch(1)
+        with pytest.raises(B.CLBError):
+            s.set_steps_per_launch(3)
