@@ -1,5 +1,6 @@
-"""GPU: two time steps per launch (clb_set_steps_per_launch(ctx, 2), FP32
-planes with FP64 or FP32 arithmetic) against single steps on the same inputs,
+"""GPU: two time steps per launch (clb_set_steps_per_launch(ctx, 2); FP32
+planes with FP64 or FP32 arithmetic, FP16 and mixed planes with FP32
+arithmetic) against single steps on the same inputs,
 over every side kind, the porosity field, the per-row acceleration, the
 raw-moment collision, ragged domains narrower and wider than the tiles
 (64 x 8; 128 x 8 when every domain of the context is at least 128 wide),
@@ -13,7 +14,8 @@ the last-place differences that the compiler's separate choices of fused
 multiply-adds in the two kernels can make.  With FP32 arithmetic such a
 difference reaches the stored value, so the two modes are held to the FP32
 tolerance (1e-6) against each other, and to the error that FP32 arithmetic
-reaches against the oracle (5e-6; it misses the 1e-6 target)."""
+reaches against the oracle (5e-6; it misses the 1e-6 target).  FP16 and
+mixed storage are held to 1e-3 between the modes and against the oracle."""
 import sys
 
 import numpy as np
