@@ -733,7 +733,7 @@ def main():
     ap.add_argument("--storage", choices=("f32", "f32c", "f16", "mixed"), default="f32",
                     help="f32: FP32 planes, FP64 arithmetic; f32c: FP32 planes, FP32 arithmetic")
     ap.add_argument("--weights", default=None, help="warmstart: network weights (.npz)")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time launch shapes first")
     ap.add_argument("--launch", type=str, default=None, help="tile_x,tile_y,blocks")
