@@ -91,6 +91,19 @@ enum {
   CLB_SCALE_CHANNEL = 1   /* 1/s_v = 1/2 + J H u_ref/(c_s^2 Re), Ra gives g beta (Section 3.1) */
 };
 
+/* Built-in per-row acceleration of a domain (clb_params.forcing).
+ *   CLB_FORCING_NONE:      none;
+ *   CLB_FORCING_INJECTION: the y-acceleration of Eq. 42 for the porous channel
+ *     with injection of Section 3.1, so that its steady state is that of
+ *     Eqs. 43-44.  On row y (0 .. ny-1, H = ny - 1), with the domain's derived
+ *     nu, K = Da H^2, alpha_e and g beta dT, and u1 = bc_v[CLB_SOUTH] (the
+ *     injection velocity):
+ *       a_y(y) = (nu / K) u1 - g beta dT (exp(y u1 / alpha_e) - 1)
+ *                                       / (exp(H u1 / alpha_e) - 1)
+ *     (the last factor is y / H when u1 = 0).  Needs a uniform medium with
+ *     Da > 0, else CLB_ERR_ARG.  Added to a_rows when both are given. */
+enum { CLB_FORCING_NONE = 0, CLB_FORCING_INJECTION = 1 };
+
 /*
  * Parameters of one domain.  A field left at 0 takes the paper's default or is
  * derived (Section 3: J = 1, varpi = 1/4, s0 = s1 = 1, s3 = 1.2,
@@ -139,6 +152,7 @@ typedef struct clb_params {
                                 a_x, a_y of row y), added to a[] at every node of the
                                 row; e.g. the y-dependent a_y of Eq. 42.  Copied
                                 during clb_create; NULL for none                     */
+  int32_t forcing;           /* CLB_FORCING_*: built-in per-row acceleration          */
 } clb_params;
 
 /* Lattice quantities derived from a clb_params (all lattice units). */
@@ -162,6 +176,14 @@ void clb_params_default(clb_params *p);
  * phi outside (0, 1], sigma <= 0, a relaxation rate outside (0, 2), varpi
  * outside (0, 1), mismatched periodic sides). */
 clb_status clb_derive(const clb_params *p, clb_derived *out);
+
+/* The per-row acceleration a domain will carry (host only): rows[2y] and
+ * rows[2y + 1] receive a_x and a_y of row y (0 .. ny-1), the sum of
+ * p->a_rows and the built-in forcing (clb_params.forcing; Eq. 42 for
+ * CLB_FORCING_INJECTION); zeros for a domain with neither.  rows holds 2*ny
+ * doubles owned by the caller.  Errors: CLB_ERR_ARG as for clb_derive, or
+ * for a NULL pointer. */
+clb_status clb_row_accel(const clb_params *p, double *rows);
 
 /* Device bytes needed for `count` domains.  Pure host function. */
 clb_status clb_workspace_bytes(const clb_params *p, int32_t count, size_t *bytes);
@@ -284,18 +306,19 @@ clb_status clb_set_launch(clb_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t 
 clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_t *blocks);
 
 /* Time steps per kernel launch: 1 or 2 (else CLB_ERR_ARG); 2 is the default
- * for every storage mode but CLB_STORE_F16.  With 2, pairs of
- * steps run in one launch while every domain is active: each tile (128 x 8
- * nodes when every domain is at least 128 wide, else 64 x 8) and a one-node
- * ring around it are collided into LDS, then the tile again from there, so
- * that the populations cross HBM once per two node updates.  The
- * per-node arithmetic and rounding are those of single steps: with
- * CLB_STORE_F32 the results have been bit-identical in every test; with
+ * for every storage mode but CLB_STORE_F16.  With 2, the active domains
+ * advance in pairs of steps per launch (domains that clb_run retires simply
+ * drop out of the launch): each tile (128 x 8 nodes when every domain is at
+ * least 128 wide, else 64 x 8) and a one-node ring around it are collided
+ * into LDS, then the tile again from there, so that the populations cross
+ * HBM once per two node updates.  The per-node arithmetic and rounding are
+ * those of single steps in every storage mode: with CLB_STORE_F32, F16 and
+ * MIXED the results have been bit-identical in every test; with
  * CLB_STORE_F32C the compiler's separate choices of fused multiply-adds in
- * the two kernels leave differences at the FP32 rounding level.  The step
- * that records the residual snapshot and an odd remainder run singly; retired
- * domains simply drop out of the two-step tile list.  Re-captures the step
- * graphs. */
+ * the two kernels leave differences at the FP32 rounding level.  The
+ * residual snapshot of clb_step is written by the last two-step launch; an
+ * odd remainder, and the first step of each clb_run round (which records
+ * that round's snapshot), run singly.  Re-captures the step graphs. */
 clb_status clb_set_steps_per_launch(clb_ctx *ctx, int32_t steps);
 
 /* The launch mode: steps per launch (1 or 2) and the width of the two-step

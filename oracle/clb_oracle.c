@@ -20,9 +20,15 @@
  * consistent forcing, conservation, uniform Darcy-Forchheimer flow, linear
  * decay rates, pure conduction (Nu = 1), the Darcy-Brinkman channel and the
  * paper's mixed-convection channel with second-order convergence, and plane
- * Poiseuille flow between an inlet and an outlet side.
- * Parity unpinned: the corner temperature rule between two Dirichlet sides;
- * nothing printed in the paper and no closed form exercises it.
+ * Poiseuille flow between an inlet and an outlet side.  Boundary nodes
+ * (tests/test_oracle_walls.py): a brute-force step with population-space
+ * reconstruction on small walled lattices over every side kind and every
+ * corner branch, and pure conduction with two Dirichlet sides at every corner
+ * against its Fourier series (second order in the interior and in the far
+ * side's Nusselt number).  The corner temperature between two Dirichlet sides
+ * is a convention (no physical quantity fixes it: it only decides which of
+ * the two sides books the flux of the corner gap); the brute force pins that
+ * the oracle applies the stated one.
  */
 #include "clb_oracle.h"
 

@@ -61,3 +61,14 @@ def channel(ny, Re, Ra, Pr, Da, phi, u_ref, J=1.0, Gamma=1.0, sigma=1.0, varpi=0
                 nu_e=J * nu, nu=nu, alpha=alpha, alpha_e=Gamma * alpha,
                 gbeta_dT=Ra * nu * alpha / H ** 3, K=Da * H * H, phi=phi,
                 sigma=sigma, varpi=varpi)
+
+
+def injection_ay(ny, u1, P):
+    """The y-acceleration of Eq. 42 on rows y = 0 .. ny-1 (H = ny - 1) of the
+    injection channel of Section 3.1, from a channel() parameter set P:
+    (nu/K) u1 - g beta dT (exp(y u1/alpha_e) - 1) / (exp(H u1/alpha_e) - 1)."""
+    H = ny - 1
+    y = np.arange(ny, dtype=np.float64)
+    k = u1 / P["alpha_e"]
+    prof = np.expm1(y * k) / math.expm1(H * k) if k != 0 else y / H
+    return P["nu"] / P["K"] * u1 - P["gbeta_dT"] * prof

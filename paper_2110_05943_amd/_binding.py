@@ -22,6 +22,7 @@ KIND = {"periodic": PERIODIC, "wall_T": WALL_T, "wall_adiabatic": WALL_ADIABATIC
         "inlet": INLET, "outlet": OUTLET}
 STORAGE = {"f32": STORE_F32, "f16": STORE_F16, "mixed": STORE_MIXED, "f32c": STORE_F32C}
 MODEL = {"clb": 0, "mrt": 1, "bgk": 2}
+FORCING = {"none": 0, "injection": 1}
 # bytes moved per node update (14 populations read and written)
 BYTES_PER_UPDATE = {"f32": 112, "f16": 56, "mixed": 76, "f32c": 112}
 
@@ -52,7 +53,7 @@ class Params(C.Structure):
         ("s3", C.c_double), ("s4", C.c_double), ("zeta_a", C.c_double), ("zeta_e", C.c_double),
         ("zeta_nu", C.c_double), ("varpi", C.c_double), ("gbeta", C.c_double),
         ("T_init", C.c_double), ("storage", C.c_int32), ("model", C.c_int32),
-        ("a_rows", C.POINTER(C.c_double)),
+        ("a_rows", C.POINTER(C.c_double)), ("forcing", C.c_int32),
     ]
 
 
@@ -63,7 +64,7 @@ class Derived(C.Structure):
 
 
 EXPORTS = (
-    "clb_params_default", "clb_derive", "clb_workspace_bytes", "clb_create", "clb_step",
+    "clb_params_default", "clb_derive", "clb_row_accel", "clb_workspace_bytes", "clb_create", "clb_step",
     "clb_macros", "clb_nusselt", "clb_nusselt_all", "clb_residual", "clb_residual_all",
     "clb_set_state", "clb_set_state_device", "clb_set_active", "clb_run", "clb_state_bytes", "clb_get_state", "clb_put_state",
     "clb_steps_done", "clb_set_launch", "clb_get_launch", "clb_set_steps_per_launch",
@@ -87,6 +88,7 @@ def _lib():
         sig = {
             "clb_params_default": (None, [P]),
             "clb_derive": (st, [P, D]),
+            "clb_row_accel": (st, [P, dp]),
             "clb_workspace_bytes": (st, [P, C.c_int32, C.POINTER(C.c_size_t)]),
             "clb_create": (st, [P, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "clb_step": (st, [vp, C.c_int64]),
@@ -160,6 +162,8 @@ def make_params(**kw):
             p.storage = STORAGE[v] if isinstance(v, str) else int(v)
         elif k == "model":
             p.model = MODEL[v] if isinstance(v, str) else int(v)
+        elif k == "forcing":
+            p.forcing = FORCING[v] if isinstance(v, str) else int(v)
         elif k == "scaling":
             p.scaling = {"cavity": SCALE_CAVITY, "channel": SCALE_CHANNEL}.get(v, v)
         else:
@@ -174,6 +178,15 @@ def derive(**kw):
     d = Derived()
     _check(_lib().clb_derive(C.byref(p), C.byref(d)), "clb_derive")
     return {n: getattr(d, n) for n, _ in Derived._fields_}
+
+
+def row_accel(**kw):
+    """The per-row acceleration (ny, 2) the library applies to one domain:
+    a_rows plus the built-in forcing (host only)."""
+    p = make_params(**kw)
+    out = np.zeros(2 * p.ny, dtype=np.float64)
+    _check(_lib().clb_row_accel(C.byref(p), _dptr(out)), "clb_row_accel")
+    return out.reshape(p.ny, 2)
 
 
 class Solver:

@@ -116,6 +116,8 @@ extern "C" clb_status clb_derive(const clb_params *pp, clb_derived *out) {
     return CLB_ERR_ARG;
   if (p.scaling != CLB_SCALE_CAVITY && p.scaling != CLB_SCALE_CHANNEL) return CLB_ERR_ARG;
   if (!p.eps && !(p.phi > 0.0 && p.phi <= 1.0)) return CLB_ERR_ARG;
+  if (p.forcing != CLB_FORCING_NONE && p.forcing != CLB_FORCING_INJECTION) return CLB_ERR_ARG;
+  if (p.forcing == CLB_FORCING_INJECTION && (p.eps || !(p.Da > 0.0))) return CLB_ERR_ARG;
   if (p.eps && !(p.dp > 0.0)) return CLB_ERR_ARG;
 
   clb_derived d;
@@ -185,6 +187,39 @@ extern "C" clb_status clb_derive(const clb_params *pp, clb_derived *out) {
   return CLB_OK;
 }
 
+namespace {
+bool has_rows(const clb_params &p) { return p.a_rows || p.forcing != CLB_FORCING_NONE; }
+
+// Per-row acceleration (a_x, a_y) of a domain: the caller's a_rows plus the
+// built-in forcing.  CLB_FORCING_INJECTION: Eq. 42 (Section 3.1) from the
+// derived nu, K, alpha_e and g beta dT, with u1 the injection velocity of the
+// south side.
+std::vector<double> row_accel(const clb_params &p, const clb_derived &d) {
+  const size_t ny = (size_t)p.ny;
+  std::vector<double> h(2 * ny, 0.0);
+  if (p.a_rows) std::copy(p.a_rows, p.a_rows + 2 * ny, h.begin());
+  if (p.forcing == CLB_FORCING_INJECTION) {
+    const double H = p.ny - 1, u1 = p.bc_v[CLB_SOUTH], k = u1 / d.alpha_e;
+    const double gbdT = d.gbeta * d.dT;
+    for (size_t y = 0; y < ny; ++y) {
+      const double prof = k != 0.0 ? std::expm1((double)y * k) / std::expm1(H * k) : y / H;
+      h[2 * y + 1] += d.nu / d.K * u1 - gbdT * prof;
+    }
+  }
+  return h;
+}
+}  // namespace
+
+extern "C" clb_status clb_row_accel(const clb_params *p, double *rows) {
+  if (!p || !rows) return CLB_ERR_ARG;
+  clb_derived d;
+  const clb_status s = clb_derive(p, &d);
+  if (s != CLB_OK) return s;
+  const std::vector<double> h = row_accel(*p, d);
+  std::copy(h.begin(), h.end(), rows);
+  return CLB_OK;
+}
+
 // --------------------------------------------------------------- layout
 
 namespace {
@@ -247,7 +282,7 @@ Layout make_layout(const clb_params *p, int count) {
     L.A.push_back(take(pop));
     L.B.push_back(take(pop));
     L.eps.push_back(p[c].eps ? take(plane * sizeof(float)) : 0);
-    L.arow.push_back(p[c].a_rows ? take(2 * (size_t)p[c].ny * sizeof(double)) : 0);
+    L.arow.push_back(has_rows(p[c]) ? take(2 * (size_t)p[c].ny * sizeof(double)) : 0);
     L.snap.push_back(take(3 * plane * sizeof(float)));
   }
   L.total = off;
@@ -525,9 +560,10 @@ clb_status launch_one(clb_ctx *c, int write_snap, hipStream_t s) {
   return CLB_OK;
 }
 
-clb_status launch_two(clb_ctx *c, hipStream_t s) {
-  const hipError_t e = clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts,
-                                         c->parity, 0, c->storage, c->raw, c->rows, c->tile2_x, s);
+clb_status launch_two(clb_ctx *c, int write_snap, hipStream_t s) {
+  const hipError_t e =
+      clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts, c->parity, write_snap,
+                        c->storage, c->raw, c->rows, c->tile2_x, s);
   if (e != hipSuccess) return hip_fail(e, "two-step kernel launch");
   return CLB_OK;
 }
@@ -591,7 +627,7 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
     if (p[k].nx < clb::kFusedXWide) c->tile2_x = clb::kFusedX;
   c->p.assign(p, p + count);
   for (auto &q : c->p) {  // host arrays are not kept
-    c->rows |= q.a_rows != nullptr;
+    c->rows |= has_rows(q);
     q.eps = nullptr;
     q.a_rows = nullptr;
   }
@@ -618,7 +654,7 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
     c->desc[k].B = c->ws + lay.B[k];
     c->desc[k].eps = p[k].eps ? reinterpret_cast<const float *>(c->ws + lay.eps[k]) : nullptr;
     c->desc[k].arow =
-        p[k].a_rows ? reinterpret_cast<const double *>(c->ws + lay.arow[k]) : nullptr;
+        has_rows(p[k]) ? reinterpret_cast<const double *>(c->ws + lay.arow[k]) : nullptr;
     c->desc[k].snap = reinterpret_cast<float *>(c->ws + lay.snap[k]);
   }
   c->active.assign(count, 1);
@@ -653,9 +689,11 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   }
   // per-row accelerations (FP64, 2 values per row)
   for (int k = 0; k < count; ++k) {
-    if (!p[k].a_rows) continue;
-    const size_t n = 2 * (size_t)p[k].ny;
-    hipError_t e = hipMemcpyAsync(c->ws + lay.arow[k], p[k].a_rows, n * sizeof(double),
+    if (!has_rows(p[k])) continue;
+    const std::vector<double> h = row_accel(p[k], der[k]);
+    for (double v : h)
+      if (!std::isfinite(v)) return fail(CLB_ERR_ARG);
+    hipError_t e = hipMemcpyAsync(c->ws + lay.arow[k], h.data(), h.size() * sizeof(double),
                                   hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(hip_fail(e, "a_rows upload"));
@@ -688,17 +726,9 @@ extern "C" void clb_destroy(clb_ctx *c) {
 }
 
 namespace {
-// Enqueues n >= 1 steps.  One step, launched directly, records the snapshot of
-// (u, v, theta) for the residual: the last one (residual over one step) or,
-// with snap_first, the first one (residual over all n steps).
-clb_status advance(clb_ctx *c, int64_t n, bool snap_first) {
-  if (snap_first) {
-    const clb_status s = launch_one(c, 1, c->stream);
-    if (s != CLB_OK) return s;
-    c->parity ^= 1;
-  }
-  int64_t rest = n - 1;  // steps besides the one that records the snapshot
-  const bool two = fused_now(c);
+// Enqueues `rest` steps without a snapshot: graphs of kGraphSteps steps, then
+// two-step launches (when in effect), then a single step for an odd remainder.
+clb_status advance_plain(clb_ctx *c, int64_t rest, bool two) {
   while (rest > 0) {
     if (rest >= kGraphSteps) {
       hipGraphExec_t &g = two ? c->graph2[c->parity] : c->graph[c->parity];
@@ -709,7 +739,7 @@ clb_status advance(clb_ctx *c, int64_t n, bool snap_first) {
       HIPCHK(hipGraphLaunch(g, c->stream));
       rest -= kGraphSteps;  // an even number of buffer swaps: parity unchanged
     } else if (two && rest >= 2) {
-      const clb_status s = launch_two(c, c->stream);
+      const clb_status s = launch_two(c, 0, c->stream);
       if (s != CLB_OK) return s;
       c->parity ^= 1;
       rest -= 2;
@@ -720,11 +750,35 @@ clb_status advance(clb_ctx *c, int64_t n, bool snap_first) {
       --rest;
     }
   }
-  if (!snap_first) {
-    const clb_status s = launch_one(c, 1, c->stream);
+  return CLB_OK;
+}
+
+// Enqueues n >= 1 steps, one of which records the snapshot of (u, v, theta)
+// for the residual: the last one (residual over one step) or, with
+// snap_first, the first one (residual over all n steps).  With two steps per
+// launch the last step's snapshot is written by the second step of the last
+// two-step launch, so that every step of an even request runs two per
+// launch; an odd request takes one single step first.
+clb_status advance(clb_ctx *c, int64_t n, bool snap_first) {
+  const bool two = fused_now(c);
+  clb_status s = CLB_OK;
+  if (snap_first) {
+    s = launch_one(c, 1, c->stream);
+    if (s != CLB_OK) return s;
+    c->parity ^= 1;
+    s = advance_plain(c, n - 1, two);
+  } else if (two && n >= 2) {
+    s = advance_plain(c, n - 2, two);
+    if (s == CLB_OK) s = launch_two(c, 1, c->stream);
+    if (s != CLB_OK) return s;
+    c->parity ^= 1;
+  } else {
+    s = advance_plain(c, n - 1, two);
+    if (s == CLB_OK) s = launch_one(c, 1, c->stream);
     if (s != CLB_OK) return s;
     c->parity ^= 1;
   }
+  if (s != CLB_OK) return s;
   c->steps += n;
   c->snap_valid = true;
   c->snap_span = snap_first ? n : 1;
@@ -1203,7 +1257,7 @@ extern "C" clb_status clb_autotune(clb_ctx *c, const char *cache_path) {
       if (s != CLB_OK) return s;
       for (int r = 0; r < 1 + std::max(2, reps / 2); ++r) {
         if (r == 1) HIPCHK(hipEventRecord(e0, c->stream));  // after one warm-up launch
-        s = launch_two(c, c->stream);
+        s = launch_two(c, 0, c->stream);
         if (s != CLB_OK) return s;
         c->parity ^= 1;
         c->steps += 2;

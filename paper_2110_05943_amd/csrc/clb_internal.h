@@ -106,11 +106,12 @@ struct LaunchShape {
 hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
                        int32_t grid_tiles, int parity, int write_snap, int storage, int raw,
                        int rows, LaunchShape shape, hipStream_t s);
-// Two steps per launch over a list of tile_x x kFusedY tiles (FP32 planes
-// only: CLB_STORE_F32 or CLB_STORE_F32C), tile_x = kFusedX (64) or
-// kFusedXWide (128; for contexts whose domains are all at least 128 nodes
-// wide); the list may hold padding entries (cav = -1).  ntiles is the grid
+// Two steps per launch over a list of tile_x x kFusedY tiles (any storage
+// mode), tile_x = kFusedX (64) or kFusedXWide (128; the kernel masks the
+// nodes of a domain narrower than the tile); the list holds the tiles of the
+// active domains and may hold padding entries (cav = -1).  ntiles is the grid
 // (workgroups); the kernel reads the list length from counts[4].
+// write_snap records (u, v, theta) of the second step for the residual.
 constexpr int kFusedX = 64, kFusedXWide = 128, kFusedY = 8;
 hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
                         int parity, int write_snap, int storage, int raw, int rows, int tile_x,

@@ -323,9 +323,11 @@ struct GlobalSrc {
       yp = yp >= ny ? yp - ny : yp;
     }
     const typename P::G *G = gplanes<P>(buf, plane);
-    return ldv<R>(G + ys * pitch + xs) +
-           ((ldv<R>(G + plane + ys * pitch + xm) + ldv<R>(G + 3 * plane + ys * pitch + xp)) +
-            (ldv<R>(G + 2 * plane + ym * pitch + xs) + ldv<R>(G + 4 * plane + yp * pitch + xs)));
+    return ldv<R>(at(G, ys * pitch + xs)) +
+           ((ldv<R>(at(G + (size_t)plane, ys * pitch + xm)) +
+             ldv<R>(at(G + (size_t)3 * plane, ys * pitch + xp))) +
+            (ldv<R>(at(G + (size_t)2 * plane, ym * pitch + xs)) +
+             ldv<R>(at(G + (size_t)4 * plane, yp * pitch + xs))));
   }
 };
 
@@ -779,8 +781,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) s
       collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed);
       if (write_snap) {
         d.snap[idx] = (float)st.ux;
-        d.snap[d.plane + idx] = (float)st.uy;
-        d.snap[2 * d.plane + idx] = (float)st.th;
+        d.snap[(size_t)d.plane + idx] = (float)st.uy;
+        d.snap[(size_t)2 * d.plane + idx] = (float)st.th;
       }
     }
   }
@@ -790,18 +792,18 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) s
 
 // Two time steps of every tile of a two-step tile list (TX x kFusedY nodes,
 // TX = 64 or 128, 4 TX threads: four waves per SIMD either way, as LDS
-// allows) in one launch, FP32 planes (P: FP64 arithmetic with stochastic
-// rounding, or FP32 arithmetic).  Step one collides the tile and a one-node
-// ring around it from the source buffer into LDS, as FP32 values equal to
-// what a stored step would hold; step two collides the tile again from LDS
-// and stores it to the other buffer.  The populations cross HBM once per two node
+// allows) in one launch, any storage policy P.  Step one collides the tile
+// and a one-node ring around it from the source buffer into LDS, in the
+// storage types of P and with the values a stored step would hold (the same
+// stochastic rounding); step two collides the tile again from LDS and stores
+// it to the other buffer.  The populations cross HBM once per two node
 // updates; each ring is recomputed by the neighbouring tiles.  The region is
 // in unwrapped coordinates: the ring of a tile at a periodic side holds the
 // wrapped neighbours, and ring nodes outside a walled side are neither
 // computed nor read (boundary nodes gather inward).  counts[4] holds the
-// length of the tile list (the active domains; the grid may be longer),
-// counts[2 + parity] the index of the first step, and the kernel passes
-// step + 2 on.
+// length of the tile list (the tiles of the active domains; the grid may be
+// longer), counts[2 + parity] the index of the first step, and the kernel
+// passes step + 2 on.  write_snap records (u, v, theta) of the second step.
 template <typename P, int TX, bool RAW, bool ROWS>
 __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict__ descs,
                                                        const Tile *__restrict__ tiles,
@@ -858,8 +860,8 @@ __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict
         collide_store<P, RAW, ROWS>(d, st, wall, B, idx, seed2);
         if (write_snap) {
           d.snap[idx] = (float)st.ux;
-          d.snap[d.plane + idx] = (float)st.uy;
-          d.snap[2 * d.plane + idx] = (float)st.th;
+          d.snap[(size_t)d.plane + idx] = (float)st.uy;
+          d.snap[(size_t)2 * d.plane + idx] = (float)st.th;
         }
       }
     };
@@ -930,7 +932,7 @@ __global__ void init_kernel(const CavDesc *__restrict__ descs, int cav, int pari
   char *buf = parity ? d.B : d.A;
   F *A = const_cast<F *>(fplanes<P>(buf));
   G *Gp = const_cast<G *>(gplanes<P>(buf, d.plane));
-  const int n = d.nx * d.ny;
+  const size_t n = (size_t)d.nx * d.ny;
   const double scf = sizeof(F) == 2 ? (double)kF16Scale : 1.0;
   const double scg = sizeof(G) == 2 ? (double)kF16Scale : 1.0;
   for (int i = 0; i < 9; ++i) {
@@ -950,7 +952,7 @@ __global__ void init_kernel(const CavDesc *__restrict__ descs, int cav, int pari
     }
     double ux = 0.0, uy = 0.0, th = th_uniform;
     if (uvth) {
-      const int k = ys * d.nx + xs;
+      const size_t k = (size_t)ys * d.nx + xs;
       ux = uvth[k];
       uy = uvth[n + k];
       th = uvth[2 * n + k];
@@ -958,8 +960,8 @@ __global__ void init_kernel(const CavDesc *__restrict__ descs, int cav, int pari
     double phi, ip, cd, cf;
     medium_at(d, ys * d.pitch + xs, phi, ip, cd, cf);
     const int idx = y * d.pitch + x;
-    A[i * d.plane + idx] = (F)(scf * feq_dev_dir(i, ux, uy, ip));
-    if (i < 5) Gp[i * d.plane + idx] = (G)(scg * geq_dev_dir(d, i, ux, uy, th));
+    A[(size_t)i * d.plane + idx] = (F)(scf * feq_dev_dir(i, ux, uy, ip));
+    if (i < 5) Gp[(size_t)i * d.plane + idx] = (G)(scg * geq_dev_dir(d, i, ux, uy, th));
   }
 }
 
@@ -1012,8 +1014,8 @@ __global__ void __launch_bounds__(512) residual_kernel(const CavDesc *__restrict
     // the snapshot holds FP32 values: compare like with like
     const double ux = (double)(float)st.ux, uy = (double)(float)st.uy, th = (double)(float)st.th;
     const double du = ux - d.snap[idx];
-    const double dv = uy - d.snap[d.plane + idx];
-    const double dth = th - d.snap[2 * d.plane + idx];
+    const double dv = uy - d.snap[(size_t)d.plane + idx];
+    const double dth = th - d.snap[(size_t)2 * d.plane + idx];
     const double T = d.c.T0 + (double)st.th;
     v[0] = du * du + dv * dv;
     v[1] = (double)st.ux * (double)st.ux + (double)st.uy * (double)st.uy;
@@ -1083,7 +1085,7 @@ __global__ void __launch_bounds__(512) macros_kernel(const CavDesc *__restrict__
   const char *A = parity ? d.B : d.A;
   NodeState<R> st;
   node_state<P, true>(d, GlobalSrc<P>{A}, x, y, st);
-  const int n = d.nx * d.ny, k = y * d.nx + x;
+  const size_t n = (size_t)d.nx * d.ny, k = (size_t)y * d.nx + x;
   out[k] = (float)st.dr;
   out[n + k] = (float)st.ux;
   out[2 * n + k] = (float)st.uy;

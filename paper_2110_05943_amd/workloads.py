@@ -10,12 +10,8 @@ inputs of each workload.  The lattice values are derived by the library
   channel:  mixed-convection channel with a parabolic inlet, an outlet, a hot
             bottom and a cold top wall, and a random porosity map;
   paper_channel: the periodic mixed-convection channel with injection of
-            Section 3.1, with its closed-form steady state (Eqs. 43-44).
+            Section 3.1.
 """
-import math
-
-import numpy as np
-
 from . import inputs
 
 CAVITY_BC = ("wall_T", "wall_T", "wall_adiabatic", "wall_adiabatic")
@@ -65,43 +61,20 @@ def paper_channel(ny, Re=5.0, nx=3, u1=0.01, s_v=None, Ra=100.0, Pr=1.0, Da=0.01
     Periodic in x.  The bottom plate (T = 0) is static, the top plate (T = 1)
     moves along x at u0 = u1; fluid enters through the bottom and leaves
     through the top at the normal velocity u1.  Brinkman medium (no
-    Forchheimer term), K = Da H^2.  The y-acceleration of Eq. 42, which makes
-    the steady state that of Eqs. 43-44, is passed per row (a_rows).
+    Forchheimer term), K = Da H^2.  The library adds the y-acceleration of
+    Eq. 42 per row (forcing "injection"), which makes the steady state that
+    of Eqs. 43-44.
 
-    With s_v given (the convergence study of Section 3.1), u1 = Re nu / H
-    follows from it; otherwise u1 is the given injection velocity and s_v
-    follows from Re (the Re family)."""
-    from ._binding import derive
+    With s_v given (the convergence study of Section 3.1), the injection
+    velocity is the one that gives Re at that s_v (Re = H u1 / nu with
+    nu = (1/s_v - 1/2) / 3 / J); otherwise u1 is the given injection velocity
+    and the library derives s_v from Re (the Re family)."""
     H = ny - 1
     J = kw.get("J", 1.0)
     if s_v is not None:
         u1 = Re * (1.0 / s_v - 0.5) / 3.0 / J / H
     c = dict(nx=nx, ny=ny, bc=CHANNEL_BC, bc_u=(0.0, 0.0, 0.0, u1), bc_v=(0.0, 0.0, u1, u1),
              bc_T=(0.0, 0.0, 0.0, 1.0), scaling="channel", Re=Re, u_ref=u1, Pr=Pr, Ra=Ra, Da=Da,
-             phi=phi, F_phi=0.0, T_init=0.5, storage=storage)
+             phi=phi, F_phi=0.0, T_init=0.5, storage=storage, forcing="injection")
     c.update(kw)
-    d = derive(**c)
-    y = np.arange(ny, dtype=np.float64)
-    k = u1 / d["alpha_e"]
-    ay = d["nu"] / d["K"] * u1 - d["gbeta"] * d["dT"] * np.expm1(y * k) / math.expm1(H * k)
-    c["a_rows"] = np.stack([np.zeros(ny), ay], axis=1)
     return c
-
-
-def paper_channel_exact(case):
-    """Closed-form steady state of a paper_channel case (Eqs. 43-44) as row
-    profiles (u_x, u_y, T) over y = 0 .. H."""
-    from ._binding import derive
-    d = derive(**case)
-    ny = case["ny"]
-    H = ny - 1
-    Re, phi, Da = case["Re"], case["phi"], case["Da"]
-    J = case.get("J", 1.0)
-    u0, u1 = case["bc_u"][3], case["bc_v"][2]
-    th1 = Re / (2 * phi * J)
-    th2 = math.sqrt(Re * Re + 4 * phi ** 3 * J / Da) / (2 * phi * J)
-    eta = np.arange(ny, dtype=np.float64) / H
-    ux = u0 * np.exp(th1 * (eta - 1)) * np.sinh(th2 * eta) / math.sinh(th2)
-    pe = d["nu"] / d["alpha_e"] * Re  # Pr_e Re
-    T = np.expm1(pe * eta) / math.expm1(pe)
-    return ux, np.full(ny, u1), T

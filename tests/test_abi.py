@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout(tmp_path):
     # The ctypes mirrors must have the C compiler's size and field offsets.
     fields = ("nx", "bc_u", "inlet_U", "eps", "scaling", "u_ref", "a", "gbeta", "T_init",
-              "storage", "model", "a_rows")
+              "storage", "model", "a_rows", "forcing")
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"clb.h\"\nint main(void) {\n"
                    '  printf("%zu %zu\\n", sizeof(clb_params), sizeof(clb_derived));\n' +

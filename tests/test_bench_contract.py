@@ -44,12 +44,17 @@ def test_traffic_summary_matches_the_kernel_source():
     per_lu_one = one["valu_instr_per_launch"] / one["nodes"]
     per_lu_two = two["valu_instr_per_launch"] / (2 * two["nodes"])
     assert 1.0 < per_lu_two / per_lu_one < 660 / 512 + 0.05
-    # the roofline of the measured launch time stays below the issue peak
+    # the roofline of the measured launch time: algorithmic bytes of two node
+    # updates per node per launch against 8 TB/s; issue and FP64 beside it
     r = bench.two_step_roofline("cavity4096_f32", "f32", two["nodes"], two["avg_launch_us"] / 2e3,
                                 112)
-    assert r["bound"] == "alu" and r["other_bound"]["bound"] == "hbm"
-    assert 0 < r["frac"] <= r["valu_issued_frac"] < 1 and r["other_bound"]["frac"] < r["frac"]
-    assert r["traffic"] == two["bytes_per_launch"] and 0 < r["fp64_frac"] < 1
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    launch_s = two["avg_launch_us"] * 1e-6
+    assert abs(r["achieved"] - 112 * 2 * two["nodes"] / launch_s / 1e9) < 0.1
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4 and 0 < r["frac"] < 1.2
+    assert r["traffic"] == two["bytes_per_launch"]
+    assert abs(r["traffic_frac"] - two["bytes_per_launch"] / launch_s / 8e12) < 1e-4
+    assert 0 < r["valu"]["frac"] <= r["valu"]["issued_frac"] < 1 and 0 < r["fp64"]["frac"] < 1
     # FP32 arithmetic: no FP64 work, fewer instructions per node update
     c1 = data["cavity4096_f32c_single"]
     assert c1["fp64_flops_per_launch"] == 0

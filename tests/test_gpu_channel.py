@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 from paper_2110_05943_amd import inputs, workloads
-from tests.cases import oracle_lattice, oracle_values, rel_l2, sampled_oracle, vel_rel_l2
+from tests.cases import (node_errors, node_tol, oracle_lattice, oracle_values, rel_l2,
+                         sampled_oracle, vel_rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -81,9 +82,11 @@ def test_channel_crop_256_6000_steps(Solver, eps2048, crop_oracle, storage, tol)
     g = s.macros()
     o, nu_o = crop_oracle
     eu, eT = vel_rel_l2(g, o), rel_l2(g["T"], o["T"])
+    nu_, nT = node_errors(g, o)
     nu_g = s.nusselt(0, 2)
-    log("crop 256 %s rel-L2 u=%.3e T=%.3e  Nu(bottom) gpu=%.6f oracle=%.6f"
-        % (storage, eu, eT, nu_g, nu_o))
+    log("crop 256 %s rel-L2 u=%.3e T=%.3e  worst node u=%.3e T=%.3e  Nu(bottom) gpu=%.6f "
+        "oracle=%.6f" % (storage, eu, eT, nu_, nT, nu_g, nu_o))
     assert eu <= tol and eT <= tol
+    assert nu_ <= node_tol(tol) and nT <= node_tol(tol)
     assert abs(nu_g - nu_o) <= (1e-4 if storage == "f32" else 1e-2) * max(1.0, abs(nu_o))
     s.close()

@@ -22,7 +22,7 @@ import numpy as np
 import pytest
 
 from paper_2110_05943_amd import inputs, workloads
-from tests.cases import cavity, oracle_lattice, rel_l2, vel_rel_l2
+from tests.cases import cavity, node_errors, node_tol, oracle_lattice, rel_l2, vel_rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -174,9 +174,11 @@ def test_two_step_launches_match_oracle(B, name, storage):
         lat.step(5000)
         g, o = s.macros(k), lat.macros()
         eu, eT = vel_rel_l2(g, o), rel_l2(g["T"], o["T"])
-        log("two-step %s %s, domain %dx%d, 5000 steps: rel-L2 u %.2e T %.2e"
-            % (name, storage, case["nx"], case["ny"], eu, eT))
+        nu_, nT = node_errors(g, o)
+        log("two-step %s %s, domain %dx%d, 5000 steps: rel-L2 u %.2e T %.2e  worst node u %.2e "
+            "T %.2e" % (name, storage, case["nx"], case["ny"], eu, eT, nu_, nT))
         assert eu <= tol and eT <= tol
+        assert nu_ <= node_tol(tol) and nT <= node_tol(tol)
         assert abs(s.nusselt(k, 0) - lat.nusselt(0)) <= tol_nu
 
 

@@ -3,6 +3,7 @@ the steady-state bookkeeping of the warm-start driver."""
 import math
 
 import numpy as np
+import pytest
 
 from paper_2110_05943_amd import inputs, warmstart, workloads
 
@@ -59,22 +60,39 @@ def test_workload_parameter_sets():
     assert math.isclose(ch["gbeta"] * 31 / ch["inlet_U"] ** 2, 1.0)
 
 
-def test_paper_channel_workload_matches_eq42_and_closed_form():
-    # a_rows against Eq. 42 with the oracle's own derivation of nu, K, alpha_e
-    # and g beta dT; the closed form meets the plate conditions of Fig. 1.
-    from oracle import params as op
-    ny, Re, u1 = 33, 5.0, 0.01
-    c = workloads.paper_channel(ny, Re=Re, u1=u1)
-    P = op.channel(ny, Re=Re, Ra=100.0, Pr=1.0, Da=0.01, phi=0.6, u_ref=u1)
-    H = ny - 1
-    y = np.arange(ny)
-    ay = P["nu"] / P["K"] * u1 - P["gbeta_dT"] * (np.exp(y * u1 / P["alpha_e"]) - 1) / (
-        math.exp(H * u1 / P["alpha_e"]) - 1)
-    assert np.allclose(c["a_rows"][:, 1], ay, rtol=1e-12, atol=0)
-    assert np.all(c["a_rows"][:, 0] == 0)
-    ux, uy, T = workloads.paper_channel_exact(c)
-    assert ux[0] == 0 and math.isclose(ux[-1], u1) and np.all(uy == u1)
-    assert T[0] == 0 and math.isclose(T[-1], 1.0)
+def test_paper_channel_forcing_matches_eq42_and_closed_form():
+    # The library's per-row acceleration (clb_row_accel: Eq. 42 evaluated in
+    # clb_create from its own derivation) against Eq. 42 with the oracle's
+    # derivation of nu, K, alpha_e and g beta dT, on every channel case of
+    # the GPU tests; the closed form meets the plate conditions of Fig. 1.
+    from paper_2110_05943_amd._binding import row_accel
+    from tests.cases import injection_rows
+    from tests.closed_forms import paper_channel_exact
+    cases = [workloads.paper_channel(33, Re=5.0, u1=0.01),
+             workloads.paper_channel(33, nx=8, Re=5.0),
+             workloads.paper_channel(25, nx=40, s_v=1.2, Re=10.0),
+             workloads.paper_channel(32, nx=32, s_v=1.0 / 0.5015, Re=5.0),
+             workloads.paper_channel(32, nx=32, Re=1.0), workloads.paper_channel(32, nx=32, Re=20.0)]
+    cases += [workloads.paper_channel(n, s_v=1.0, Re=5.0) for n in (17, 33, 49, 65, 81, 97)]
+    for c in cases:
+        lib = row_accel(**c)
+        ay = injection_rows(c)
+        assert np.all(lib[:, 0] == 0)
+        assert np.allclose(lib[:, 1], ay, rtol=1e-12, atol=1e-18), c["ny"]
+        ux, uy, T = paper_channel_exact(c)
+        u1 = c["bc_v"][2]
+        assert ux[0] == 0 and math.isclose(ux[-1], c["bc_u"][3]) and np.all(uy == u1)
+        assert T[0] == 0 and math.isclose(T[-1], 1.0)
+    # a_rows given beside the built-in forcing is added to it
+    c = workloads.paper_channel(17, Re=5.0)
+    extra = np.stack([np.full(17, 1e-6), np.full(17, 2e-6)], axis=1)
+    both = row_accel(**dict(c, a_rows=extra))
+    assert np.allclose(both, row_accel(**c) + extra, rtol=0, atol=1e-18)
+    assert np.all(row_accel(**dict(c, forcing="none")) == 0)
     # the convergence-study form: u1 follows from s_v = 1 and Re
     c1 = workloads.paper_channel(17, s_v=1.0, Re=5.0)
     assert math.isclose(c1["u_ref"], 5.0 * (1 / 6) / 16)
+    # Eq. 42 needs a uniform medium with a finite permeability
+    from paper_2110_05943_amd._binding import CLBError
+    with pytest.raises(CLBError):
+        row_accel(**dict(c, Da=0.0))
