@@ -376,6 +376,9 @@ void fill_desc(const clb_params &p, const clb_derived &d, CavDesc &k) {
   const bool drag = std::isfinite(d.K);
   k.c.cd = drag ? (phi * d.nu / d.K) : 0.0;
   k.c.cf = drag ? (phi * d.F_phi / std::sqrt(d.K)) : 0.0;
+  k.c.l0 = 0.5 + 0.25 * k.c.cd;
+  k.c.l0sq = k.c.l0 * k.c.l0;
+  k.c.l1 = 0.5 * k.c.cf;
   if (p.eps) {
     k.c.kc_d = (150.0 * d.nu / (p.dp * p.dp));
     k.c.kc_f = p.F_phi == 0.0 ? 0.0 : (1.75 / p.dp);

@@ -43,10 +43,12 @@ struct Tile {
 //   T0:       storage reference temperature
 //   gbx, gby, ax, ay: body force G = gb theta + a
 //   dT:       temperature difference of the Nusselt number
+//   l0, l0sq, l1: uniform medium: the coefficients of Eq. 23, l0 = 1/2 + cd/4,
+//             its square, and l1 = cf/2
 #define CLB_DOMAIN_SCALARS(X)                                                              \
   X(inlet_U) X(phi) X(ip) X(cd) X(cf) X(kc_d) X(kc_f) X(s1c) X(s1f) X(sp) X(sm) X(svc)   \
   X(s3c) X(s3f) X(s4) X(zac) X(zec) X(znc) X(hv) X(sig) X(isig) X(sig_mv) X(T0) X(gbx)   \
-  X(gby) X(ax) X(ay) X(dT)
+  X(gby) X(ax) X(ay) X(dT) X(l0) X(l0sq) X(l1)
 
 template <typename T>
 struct DomainConsts {

@@ -204,3 +204,30 @@ def test_steps_per_launch_argument(B):
         s.set_steps_per_launch(1)
         with pytest.raises(B.CLBError):
             s.set_steps_per_launch(3)
+
+
+def test_wide_tiles_forced_on_a_narrow_domain(B, tmp_path):
+    """clb_create picks 64-wide two-step tiles when a domain is narrower
+    than 128; a cached tuning choice can still impose 128-wide tiles on such
+    a context.  The narrow domain then sits in one masked 128 x 8 tile per
+    row band; the results must equal single steps bit for bit."""
+    cases = [cavity(40, ny=24, Ra=1e4, sigma=1.1), cavity(260, ny=40, Ra=1e5, Da=1e-3, phi=0.5)]
+    Ts = [inputs.cavity_initial_T(c["nx"], seed=3 + k, ny=c["ny"]) for k, c in enumerate(cases)]
+    nodes = sum(c["nx"] * c["ny"] for c in cases)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("storage=0;n=2;nodes=%d;first=40x24 0 0 0 128\n" % nodes)
+    a = B.Solver(cases)
+    assert a.get_steps_per_launch() == (2, 64)
+    a.autotune(str(cache))
+    assert a.get_steps_per_launch() == (2, 128) and a.steps_done == 0
+    b = B.Solver(cases)
+    b.set_steps_per_launch(1)
+    for s in (a, b):
+        for k, T in enumerate(Ts):
+            s.set_state(k, T)
+        s.step(101)
+    for k in range(len(cases)):
+        ma, mb = a.macros(k), b.macros(k)
+        log("forced 128-wide tiles, domain %d: bit-identical %s" % (
+            k, all(np.array_equal(ma[q], mb[q]) for q in ma)))
+        assert all(np.array_equal(ma[q], mb[q]) for q in ma)
