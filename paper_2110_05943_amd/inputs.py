@@ -98,7 +98,7 @@ def batch_cavities(count=256, seed=3, sizes=(64, 128, 256, 512)):
     return out
 
 
-def warmstart_draws(count, seed, n=128, ell=8.0, Ra=(1e3, 1e6), Da=(1e-5, 1e-1),
+def warmstart_draws(count, seed, n=128, ell=8.0, Ra=(1e3, 1e7), Da=(1e-5, 1e-1),
                     eps=(0.3, 0.95)):
     """Cavities of the learned warm start: for sample i, a generator seeded
     with (seed, i) draws, in this order, Ra log-uniform in Ra, Da log-uniform

@@ -1,12 +1,12 @@
 """Train the warm-start network on solver-generated steady states.
 
-  python -m paper_2110_05943_amd.train_warmstart --train 6000 --epochs 120 \
-      --out paper_2110_05943_amd/data/warmstart_unet.npz
+  python -m paper_2110_05943_amd.train_warmstart --train 4000 --epochs 120 \
+      --max-steps 3000000 --out paper_2110_05943_amd/data/warmstart_unet.npz
 
-(the command that wrote the committed weights; about 13 minutes on one MI355X)
+(the command that wrote the committed weights)
 
 1. Draw `--train` cavities (inputs.warmstart_draws, seed 0): 128^2 nodes,
-   Ra log-uniform [1e3, 1e6], mean Da log-uniform [1e-5, 1e-1], Pr in
+   Ra log-uniform [1e3, 1e7], mean Da log-uniform [1e-5, 1e-1], Pr in
    {0.71, 1, 7}, sigma uniform [0.8, 1.2], Gaussian-random-field porosity map
    (correlation length 8) with uniform marginal on [0.3, 0.95].
 2. Run all of them in one solver context from rest to steady state (relative

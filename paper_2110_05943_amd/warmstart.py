@@ -27,7 +27,7 @@ NGROUPS = 4
 
 def groups_of(d):
     """Normalised dimensionless groups of one draw (network input channels)."""
-    return np.array([(math.log10(d["Ra"]) - 4.5) / 1.5, (math.log10(d["Da"]) + 3.0) / 2.0,
+    return np.array([(math.log10(d["Ra"]) - 5.0) / 2.0, (math.log10(d["Da"]) + 3.0) / 2.0,
                      (math.log10(d["Pr"]) - 0.35) / 0.5, (d["sigma"] - 1.0) / 0.2],
                     dtype=np.float32)
 

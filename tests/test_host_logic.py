@@ -18,7 +18,7 @@ def test_warmstart_draws_are_seeded_and_in_range():
     # sample i does not depend on how many samples are drawn
     assert inputs.warmstart_draws(2, seed=0, n=32)[1]["Da"] == a[1]["Da"]
     for d in a:
-        assert 1e3 <= d["Ra"] <= 1e6 and 1e-5 <= d["Da"] <= 1e-1
+        assert 1e3 <= d["Ra"] <= 1e7 and 1e-5 <= d["Da"] <= 1e-1
         assert d["Pr"] in (0.71, 1.0, 7.0) and 0.8 <= d["sigma"] <= 1.2
         assert d["eps"].min() >= 0.3 and d["eps"].max() <= 0.95
         assert np.array_equal(d["eps"], d["eps"].astype(np.float32).astype(np.float64))
@@ -35,7 +35,7 @@ def test_porosity_map_has_uniform_marginal_and_mean_darcy_number():
 
 def test_groups_normalisation_spans_unit_range():
     lo = warmstart.groups_of(dict(Ra=1e3, Da=1e-5, Pr=0.71, sigma=0.8))
-    hi = warmstart.groups_of(dict(Ra=1e6, Da=1e-1, Pr=7.0, sigma=1.2))
+    hi = warmstart.groups_of(dict(Ra=1e7, Da=1e-1, Pr=7.0, sigma=1.2))
     assert np.allclose(lo, [-1, -1, -1.0, -1], atol=0.05)
     assert np.allclose(hi, [1, 1, 1.0, 1], atol=0.05)
 
