@@ -1,6 +1,6 @@
 """Train the warm-start network on solver-generated steady states.
 
-  python -m paper_2110_05943_amd.train_warmstart --train 4000 --epochs 120 \
+  python -m paper_2110_05943_amd.train_warmstart --train 4000 --epochs 300 --lr 1e-3 \
       --max-steps 3000000 --out paper_2110_05943_amd/data/warmstart_unet.npz
 
 (the command that wrote the committed weights)
