@@ -1007,6 +1007,7 @@ def main():
     if args.workload == "cavity" and not args.no_warmstart:
         # the metric's second half, on the learned warm start's own workload
         out["time_to_steady"] = warmstart_leg()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

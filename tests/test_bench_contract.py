@@ -68,3 +68,14 @@ def test_kernel_hash_ignores_comments_and_layout():
     b = "int f(int x) { return x + 1; }"
     assert bench.code_only(a) == bench.code_only(b)
     assert bench.code_only(b) != bench.code_only(b.replace("1", "2"))
+
+
+def test_main_prints_its_json_line():
+    # The default line is printed at the end of main (a refactor once lost
+    # the print and the bench exited 0 with no output).
+    import ast
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    main = next(n for n in ast.parse(src).body if isinstance(n, ast.FunctionDef) and n.name == "main")
+    last = main.body[-1]
+    assert isinstance(last, ast.Expr) and isinstance(last.value, ast.Call)
+    assert ast.unparse(last.value).startswith("print(json.dumps(out)")
