@@ -56,7 +56,7 @@ def test_trained_network_shortens_time_to_steady_state(torch):
     meta = load_weights(WEIGHTS, sur.net)
     log("weights: trained on %s cavities, %s epochs" % (meta.get("train"), meta.get("epochs")))
     draws = inputs.warmstart_draws(24, seed=1)
-    r = W.evaluate(sur, draws, tol=1e-9, check_every=5000, max_steps=1_500_000, log=log)
+    r = W.evaluate(sur, draws, tol=1e-9, check_every=5000, max_steps=3_000_000, log=log)
     err = np.array(r["pred_rel_l2"])
     sp = np.array([x if x is not None else -1 for x in r["settle_plain"]], dtype=float)
     sw = np.array([x if x is not None else -1 for x in r["settle_warm"]], dtype=float)
