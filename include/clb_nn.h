@@ -59,6 +59,24 @@ clb_status clb_nn_conv3x3_wgrad(const clb_bf16 *dy, const clb_bf16 *x, int32_t b
                                 int32_t w, int32_t cin, int32_t cout, float *dweight,
                                 float *dbias, void *workspace, size_t bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the weight
+ * gradient of clb_nn_conv3x3_wgrad without a workspace argument.  The partial
+ * sums go to a scratch array of clb_nn_wgrad_static_max_bytes() bytes
+ * (32 MiB) that the library holds in each GPU's memory from its first use on
+ * that GPU until the process ends; the call allocates nothing.  Sizes whose
+ * clb_nn_wgrad_workspace_bytes exceeds that maximum return CLB_ERR_WORKSPACE
+ * (nothing enqueued); every layer of the 5-level network at batch 32 on
+ * 128 x 128 images fits (18 MiB at most).  All calls on one GPU share its
+ * scratch array: calls that overlap in time on one GPU (different streams,
+ * or host threads) race and must be serialized by the caller.  Results are
+ * bit-identical to clb_nn_conv3x3_wgrad's.  Other arguments and errors as
+ * clb_nn_conv3x3_wgrad. */
+size_t clb_nn_wgrad_static_max_bytes(void);
+clb_status clb_nn_conv3x3_wgrad_static(const clb_bf16 *dy, const clb_bf16 *x, int32_t batch,
+                                       int32_t h, int32_t w, int32_t cin, int32_t cout,
+                                       float *dweight, float *dbias, void *stream);
+
 /* bfloat16 copies of FP32 master weights (cout, 9, cin): w_fwd in the same
  * layout, w_bwd = the weights of the input-gradient convolution, laid out
  * (cin, 9, cout) with the taps reversed: w_bwd[c, 8 - t, o] = w[o, t, c]. */

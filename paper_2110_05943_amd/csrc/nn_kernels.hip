@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "clb.h"
 #include "clb_nn.h"
@@ -632,6 +633,55 @@ extern "C" clb_status clb_nn_conv3x3_wgrad(const clb_bf16 *dy, const clb_bf16 *x
     hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((cout + 63) / 64)), dim3(256), 0, s,
                        partb, nsplit, (size_t)cout, dbias);
   return launched();
+}
+
+// ----------------------------------------------- weight gradient, no allocation
+
+// Scratch of clb_nn_conv3x3_wgrad_static: the per-chunk partial sums that
+// clb_nn_conv3x3_wgrad keeps in its caller's workspace.  Each GPU the library
+// runs on holds one copy (32 MiB) until the process ends.  Host code never
+// passes this name to a kernel: its device address is looked up per device.
+constexpr size_t kWgradScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) float scratch[kWgradScratchBytes / sizeof(float)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+clb_status scratch_address(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CLB_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CLB_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CLB_OK;
+}
+}  // namespace
+
+extern "C" size_t clb_nn_wgrad_static_max_bytes(void) { return kWgradScratchBytes; }
+
+extern "C" clb_status clb_nn_conv3x3_wgrad_static(const clb_bf16 *dy, const clb_bf16 *x,
+                                                  int32_t batch, int32_t h, int32_t w,
+                                                  int32_t cin, int32_t cout, float *dweight,
+                                                  float *dbias, void *stream) {
+  size_t need = 0;
+  if (clb_nn_wgrad_workspace_bytes(batch, h, w, cin, cout, &need) != CLB_OK || !dy || !x ||
+      !dweight || !aligned16(dy) || !aligned16(x))
+    return CLB_ERR_ARG;
+  if (need > kWgradScratchBytes) return CLB_ERR_WORKSPACE;
+  void *ws = nullptr;
+  const clb_status st = scratch_address(&ws);
+  if (st != CLB_OK) return st;
+  // the same kernels as clb_nn_conv3x3_wgrad; every partial sum they read is
+  // written first by the same call, so nothing needs clearing
+  return clb_nn_conv3x3_wgrad(dy, x, batch, h, w, cin, cout, dweight, dbias, ws, need, stream);
 }
 
 extern "C" clb_status clb_nn_weights_bf16(const float *w32, int32_t cout, int32_t cin,

@@ -27,6 +27,7 @@ NN_EXPORTS = (
     "clb_nn_weights_bf16", "clb_nn_pool2", "clb_nn_pool2_grad", "clb_nn_up2", "clb_nn_up2_grad",
     "clb_nn_concat", "clb_nn_split", "clb_nn_act_grad", "clb_nn_mse_workspace_bytes",
     "clb_nn_mse", "clb_nn_adamw", "clb_nn_features", "clb_nn_gather",
+    "clb_nn_wgrad_static_max_bytes", "clb_nn_conv3x3_wgrad_static",
 )
 
 _ready = False
@@ -42,6 +43,7 @@ def lib():
             "clb_nn_conv3x3": [vp, i32, i32, i32, i32, vp, vp, i32, i32, f32, vp, i32, vp],
             "clb_nn_wgrad_workspace_bytes": [i32, i32, i32, i32, i32, sz],
             "clb_nn_conv3x3_wgrad": [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, C.c_size_t, vp],
+            "clb_nn_conv3x3_wgrad_static": [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp],
             "clb_nn_weights_bf16": [vp, i32, i32, vp, vp, vp],
             "clb_nn_pool2": [vp, i32, i32, i32, i32, vp, vp],
             "clb_nn_pool2_grad": [vp, i32, i32, i32, i32, vp, vp],
@@ -61,6 +63,8 @@ def lib():
             fn = getattr(L, name)
             fn.restype = st
             fn.argtypes = args
+        L.clb_nn_wgrad_static_max_bytes.restype = C.c_size_t
+        L.clb_nn_wgrad_static_max_bytes.argtypes = []
         _ready = True
     return L
 
