@@ -187,3 +187,23 @@ def test_largest_domain_is_accepted_and_one_row_more_rejected():
         B.derive(nx=32768, ny=32769, Ra=1e6, Pr=1.0)
     with pytest.raises(B.CLBError):
         B.derive(nx=2 ** 31 - 1, ny=4, Ra=1e6, Pr=1.0)
+
+
+def test_plane_offsets_are_64_bit_at_the_largest_domain():
+    # The largest accepted FP32 domain has 2^30 elements per plane; the 14
+    # population planes of a buffer then span offsets up to 13 * 2^30, and
+    # the snapshot and observation planes up to 3 * 2^30, beyond INT32_MAX.
+    # Every kernel forms plane offsets in 64-bit arithmetic: each product of
+    # a plane count with `plane` in the kernel source is widened to size_t.
+    d = B.derive(nx=32768, ny=32768, Ra=1e6, Pr=1.0)
+    assert d["L"] == 32767
+    plane = 32768 * 32768
+    assert 13 * plane > 2 ** 31 - 1 and 2 * plane > 2 ** 31 - 1
+    src = open(os.path.join(ROOT, "paper_2110_05943_amd", "csrc", "clb_kernels.hip")).read()
+    src = re.sub(r"//[^\n]*", "", src)
+    for m in re.finditer(r"(\S+)\s*\*\s*(d\.)?plane\b", src):
+        pre = src[max(0, m.start() - 20):m.end()]
+        assert "(size_t)" in pre, pre
+    for m in re.finditer(r"\b(d\.)?plane\s*\+\s*idx", src):
+        pre = src[max(0, m.start() - 20):m.end()]
+        assert "(size_t)" in pre, pre
