@@ -46,6 +46,28 @@ clb_status clb_nn_conv3x3(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w
                           const clb_bf16 *weight, const float *bias, int32_t cout, int32_t act,
                           float slope, void *y, int32_t y_fp32, void *stream);
 
+/* The convolution of clb_nn_conv3x3 on the channel concatenation of a
+ * decoder level, cin = ca + cb: input channels [0, ca) are tensor a,
+ * nearest-neighbour upsampled by 2 when up_a != 0 (a is (batch, h/2, w/2,
+ * ca); h and w even), else a as it is ((batch, h, w, ca)); channels
+ * [ca, cin) are tensor b, (batch, h, w, cb).  The upsampled and the
+ * concatenated tensors are never formed: the operand gather reads a and b.
+ * ca and cb multiples of 16, a and b 16-byte aligned; weight (cout, 9, cin).
+ * Results are bit-identical to clb_nn_conv3x3 on the formed concatenation. */
+clb_status clb_nn_conv3x3_cat(const clb_bf16 *a, int32_t ca, int32_t up_a, const clb_bf16 *b,
+                              int32_t cb, int32_t batch, int32_t h, int32_t w,
+                              const clb_bf16 *weight, const float *bias, int32_t cout,
+                              int32_t act, float slope, void *y, int32_t y_fp32, void *stream);
+
+/* clb_nn_conv3x3 without bias or activation, bfloat16 output split by
+ * channels: output channels [0, split) go to y0 (batch, h, w, split), the
+ * others to y1 (batch, h, w, cout - split); split a multiple of 16 in
+ * (0, cout).  With the w_bwd weights of a concatenated input's convolution
+ * it writes the input gradients of the two parts directly. */
+clb_status clb_nn_conv3x3_split(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w,
+                                int32_t cin, const clb_bf16 *weight, int32_t cout, int32_t split,
+                                clb_bf16 *y0, clb_bf16 *y1, void *stream);
+
 /* Gradients of sum(dy * conv3x3(x)) with respect to the weights and bias:
  *   dweight[o,t,c] = sum_{b,i,j} dy[b,i,j,o] x[b, i+di_t, j+dj_t, c],
  *   dbias[o]       = sum_{b,i,j} dy[b,i,j,o]   (dbias may be NULL),
@@ -76,6 +98,15 @@ size_t clb_nn_wgrad_static_max_bytes(void);
 clb_status clb_nn_conv3x3_wgrad_static(const clb_bf16 *dy, const clb_bf16 *x, int32_t batch,
                                        int32_t h, int32_t w, int32_t cin, int32_t cout,
                                        float *dweight, float *dbias, void *stream);
+
+/* clb_nn_conv3x3_wgrad for the concatenated input of clb_nn_conv3x3_cat
+ * (same a, ca, up_a, b, cb; workspace of clb_nn_wgrad_workspace_bytes with
+ * cin = ca + cb).  Bit-identical to clb_nn_conv3x3_wgrad on the formed
+ * concatenation. */
+clb_status clb_nn_conv3x3_wgrad_cat(const clb_bf16 *dy, const clb_bf16 *a, int32_t ca,
+                                    int32_t up_a, const clb_bf16 *b, int32_t cb, int32_t batch,
+                                    int32_t h, int32_t w, int32_t cout, float *dweight,
+                                    float *dbias, void *workspace, size_t bytes, void *stream);
 
 /* bfloat16 copies of FP32 master weights (cout, 9, cin): w_fwd in the same
  * layout, w_bwd = the weights of the input-gradient convolution, laid out

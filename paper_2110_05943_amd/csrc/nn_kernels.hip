@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "clb.h"
 #include "clb_nn.h"
@@ -34,17 +35,36 @@ __device__ __forceinline__ f4 mfma16(const bf16x8 &a, const bf16x8 &b, const f4 
 // output channels, reduction index k = t * cin + c (tap-major, channels
 // contiguous).  The reduction runs in steps of 32 (one 16x16x32 MFMA per
 // 16-channel column tile); cin is a multiple of 16, so a lane's 8
-// consecutive k lie in one tap and are 16 contiguous bytes of x and of the
-// weight row.  A workgroup (4 waves) computes up to 64 output channels for
-//   - KSPLIT = false: 64 pixels, wave w the pixels 16 w .. +15.  The weight
-//     slice of each step (64 channels x 32 k) is loaded once per workgroup
-//     into LDS (double-buffered) and read by all four waves;
+// consecutive k lie in one tap and are 16 contiguous bytes of the input and
+// of the weight row.  The input is read through a ConvSrc: its first ca
+// channels come from tensor a (at half resolution, nearest-neighbour
+// upsampled, when up != 0), the other cb from tensor b, so the upsampled and
+// the concatenated tensors of a decoder level are never formed.  The output
+// may be split by channels (ConvDst) into two tensors, as the input gradient
+// of such a convolution feeds its two sources.  A workgroup (4 waves)
+// computes up to 64 output channels for
+//   - KSPLIT = false: 64 PT pixels, wave w the pixel tiles 16 (w + 4 p),
+//     p < PT.  The weight slice of each step (64 channels x 32 k) is loaded
+//     once per workgroup into LDS (double-buffered) and read by all four
+//     waves for all PT tiles;
 //   - KSPLIT = true (few pixels, deep layers): 16 pixels, wave w the steps
 //     w, w + 4, ...; the four partial sums are added in wave order through
 //     LDS, which gives four times as many workgroups and a quarter of the
 //     sequential steps per wave.
 // Both load the next step's operands before the current step's MFMAs.
 constexpr int kWRow = 32 + 8;  // LDS row of the weight slice in bf16 (padded)
+
+struct ConvSrc {
+  const bf16 *a;  // first ca channels: (B, H >> up, W >> up, ca)
+  const bf16 *b;  // then cb channels: (B, H, W, cb); null when cb = 0
+  int ca, cb, up;
+};
+
+struct ConvDst {
+  void *y0;  // output channels [0, split): (B, H, W, split)
+  void *y1;  // output channels [split, cout): (B, H, W, cout - split); null when split = cout
+  int split;
+};
 
 struct ConvPixel {
   int n, py, px;
@@ -62,90 +82,128 @@ __device__ __forceinline__ ConvPixel conv_pixel(int m, int M, int H, int W) {
   return p;
 }
 
+// 8 consecutive input channels c .. c + 7 of pixel (n, yy, xx) of the
+// virtual input (zero outside the image).
+__device__ __forceinline__ bf16x8 src_load(const ConvSrc &x, int n, int yy, int xx, int c,
+                                           int H, int W) {
+  bf16x8 v = {};
+  if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+    if (c < x.ca) {
+      const int ha = H >> x.up, wa = W >> x.up;
+      v = *reinterpret_cast<const bf16x8 *>(
+          x.a + ((size_t)(n * ha + (yy >> x.up)) * wa + (xx >> x.up)) * x.ca + c);
+    } else {
+      v = *reinterpret_cast<const bf16x8 *>(x.b + ((size_t)(n * H + yy) * W + xx) * x.cb +
+                                            (c - x.ca));
+    }
+  }
+  return v;
+}
+
 // 8 consecutive k of one pixel (zero outside the image or beyond K).
-__device__ __forceinline__ bf16x8 conv_a(const bf16 *__restrict__ x, const ConvPixel &p, int k,
-                                         int K, int H, int W, int cin) {
+__device__ __forceinline__ bf16x8 conv_a(const ConvSrc &x, const ConvPixel &p, int k, int K,
+                                         int H, int W, int cin) {
   bf16x8 a = {};
   if (k < K && p.ok) {
     const int tap = k / cin, c = k - tap * cin;
-    const int yy = p.py + tap / 3 - 1, xx = p.px + tap % 3 - 1;
-    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-      a = *reinterpret_cast<const bf16x8 *>(x + ((size_t)(p.n * H + yy) * W + xx) * cin + c);
+    a = src_load(x, p.n, p.py + tap / 3 - 1, p.px + tap % 3 - 1, c, H, W);
   }
   return a;
 }
 
-// Bias, activation and store of one wave's 16 pixels x nt column tiles.
+// Bias, activation and store of one wave's 16 pixels x nt (<= NT) column tiles.
+template <int NT>
 __device__ __forceinline__ void conv_store(const f4 *acc, int nt, int m0, int M, int co0,
                                            int lane, const float *__restrict__ bias, int cout,
-                                           int act, float slope, void *__restrict__ y,
+                                           int act, float slope, const ConvDst &dst,
                                            int y_fp32) {
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < NT; ++t) {
     if (t >= nt) continue;
     const int co = co0 + 16 * t + (lane & 15);
     const float bb = bias ? bias[co] : 0.0f;
+    // a column tile of 16 channels lies in one part (split is a multiple of 16)
+    const bool hi = co >= dst.split;
+    void *y = hi ? dst.y1 : dst.y0;
+    const int ld = hi ? cout - dst.split : dst.split, cc = hi ? co - dst.split : co;
     for (int e = 0; e < 4; ++e) {
       const int mm = m0 + 4 * (lane >> 4) + e;
       if (mm >= M) continue;
       float v = acc[t][e] + bb;
       if (act) v = v > 0.0f ? v : v * slope;
       if (y_fp32)
-        static_cast<float *>(y)[(size_t)mm * cout + co] = v;
+        static_cast<float *>(y)[(size_t)mm * ld + cc] = v;
       else
-        static_cast<bf16 *>(y)[(size_t)mm * cout + co] = (bf16)v;
+        static_cast<bf16 *>(y)[(size_t)mm * ld + cc] = (bf16)v;
     }
   }
 }
 
-template <bool KSPLIT>
+template <bool KSPLIT, int PT, int NT>
 __global__ void __launch_bounds__(256) conv3x3_kernel(
-    const bf16 *__restrict__ x, int B, int H, int W, int cin, const bf16 *__restrict__ wt,
-    const float *__restrict__ bias, int cout, int act, float slope, void *__restrict__ y,
-    int y_fp32) {
+    ConvSrc x, int B, int H, int W, const bf16 *__restrict__ wt, const float *__restrict__ bias,
+    int cout, int act, float slope, ConvDst dst, int y_fp32) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cin = x.ca + x.cb;
   const int M = B * H * W, K = 9 * cin, nsteps = (K + 31) / 32;
   const int co0 = blockIdx.y * kCoTile;
-  const int nt = min(4, (cout - co0) >> 4);
+  const int nt = min(NT, (cout - co0) >> 4);  // column tiles of this workgroup (<= NT)
   const int row = lane & 15, kq = 8 * (lane >> 4);
   const bf16x8 zero = {};
-  f4 acc[4];
-  for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
   if constexpr (!KSPLIT) {
     __shared__ __attribute__((aligned(16))) bf16 sw[2][kCoTile * kWRow];
-    const int m0 = blockIdx.x * kPixTile + wave * 16;
-    const ConvPixel px = conv_pixel(m0 + row, M, H, W);
+    f4 acc[PT][4];
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[p][t] = f4{0.f, 0.f, 0.f, 0.f};
+    const int mb = blockIdx.x * kPixTile * PT;
+    ConvPixel px[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) px[p] = conv_pixel(mb + 16 * (wave + 4 * p) + row, M, H, W);
     // weight loading role: channel wo of the slice, k offset 8 wk
     const int wo = threadIdx.x >> 2, wk = 8 * (threadIdx.x & 3);
     const bool wok = co0 + wo < cout;
     const bf16 *wrow = wt + (size_t)(co0 + wo) * K;
-    bf16x8 a = conv_a(x, px, kq, K, H, W, cin);
+    bf16x8 a[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) a[p] = conv_a(x, px[p], kq, K, H, W, cin);
     bf16x8 wv = (wok && wk < K) ? *reinterpret_cast<const bf16x8 *>(wrow + wk) : zero;
     *reinterpret_cast<bf16x8 *>(&sw[0][wo * kWRow + wk]) = wv;
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
       const int cur = s & 1;
       const int kn = 32 * (s + 1);
-      bf16x8 an = zero;
+      bf16x8 an[PT];
+#pragma unroll
+      for (int p = 0; p < PT; ++p) an[p] = zero;
       if (s + 1 < nsteps) {
-        an = conv_a(x, px, kn + kq, K, H, W, cin);
+#pragma unroll
+        for (int p = 0; p < PT; ++p) an[p] = conv_a(x, px[p], kn + kq, K, H, W, cin);
         wv = (wok && kn + wk < K) ? *reinterpret_cast<const bf16x8 *>(wrow + kn + wk) : zero;
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < NT; ++t) {
         if (t < nt) {
           const bf16x8 b =
               *reinterpret_cast<const bf16x8 *>(&sw[cur][(16 * t + row) * kWRow + kq]);
-          acc[t] = mfma16(a, b, acc[t]);
+#pragma unroll
+          for (int p = 0; p < PT; ++p) acc[p][t] = mfma16(a[p], b, acc[p][t]);
         }
       }
       if (s + 1 < nsteps) *reinterpret_cast<bf16x8 *>(&sw[cur ^ 1][wo * kWRow + wk]) = wv;
       __syncthreads();
-      a = an;
+#pragma unroll
+      for (int p = 0; p < PT; ++p) a[p] = an[p];
     }
-    conv_store(acc, nt, m0, M, co0, lane, bias, cout, act, slope, y, y_fp32);
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+      conv_store<NT>(acc[p], nt, mb + 16 * (wave + 4 * p), M, co0, lane, bias, cout, act, slope,
+                     dst, y_fp32);
   } else {
     __shared__ f4 red[3][4][64];
+    f4 acc[4];
+    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
     const int m0 = blockIdx.x * 16;
     const ConvPixel px = conv_pixel(m0 + row, M, H, W);
     const bf16 *wrow = wt + (size_t)(co0 + row) * K;  // column tile t adds 16 t rows
@@ -183,7 +241,7 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(
       for (int w = 0; w < 3; ++w)
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] += red[w][t][lane];
-      conv_store(acc, nt, m0, M, co0, lane, bias, cout, act, slope, y, y_fp32);
+      conv_store<4>(acc, nt, m0, M, co0, lane, bias, cout, act, slope, dst, y_fp32);
     }
   }
 }
@@ -204,11 +262,11 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(
 constexpr int kWgK = 64;  // k columns per workgroup
 
 template <int OB>
-__global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
-                                                     const bf16 *__restrict__ x, int B, int H,
-                                                     int W, int cin, int cout, int chunk,
+__global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy, ConvSrc x,
+                                                     int B, int H, int W, int cout, int chunk,
                                                      float *__restrict__ part,
                                                      float *__restrict__ partb) {
+  const int cin = x.ca + x.cb;
   constexpr int PG = 4 / OB;         // pixel groups
   constexpr int PX = 32 * PG;        // pixels per step
   constexpr int ROW = PX + 8;        // LDS row length in bf16 (padding: fewer bank conflicts)
@@ -250,9 +308,8 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
       const int mm = p + (tid >> 3) + 32 * j;
       if (mm < p1 && k_ok) {
         const int n = mm / HW, r = mm - n * HW;
-        const int py = r / W, yy = py + oy, xx = r - py * W + ox;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          vb[j] = *reinterpret_cast<const bf16x8 *>(x + ((size_t)(n * H + yy) * W + xx) * cin + lc);
+        const int py = r / W;
+        vb[j] = src_load(x, n, py + oy, r - py * W + ox, lc, H, W);
       }
     }
     __syncthreads();  // the previous step's LDS reads are done
@@ -427,6 +484,76 @@ __global__ void __launch_bounds__(256) split_kernel(const bf16 *__restrict__ y, 
     b[p * cb + (c - ca)] = y[i];
 }
 
+// The same layers on groups of 8 channels (16 bytes per load and store) for
+// channel counts that are multiples of 8: grid.y runs over the image rows of
+// the output (batch x height), grid.x over (column, channel group), so each
+// thread needs one 32-bit division.
+__global__ void __launch_bounds__(256) pool2_v8_kernel(const bf16x8 *__restrict__ x, int H, int W,
+                                                       int C8, bf16x8 *__restrict__ y) {
+  const int Wo = W / 2, Ho = H / 2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Wo * C8) return;
+  const int j = i / C8, c = i - j * C8;
+  const int row = blockIdx.y, b = row / Ho, ii = row - b * Ho;  // output row
+  const size_t s = ((size_t)(b * H + 2 * ii) * W + 2 * j) * C8 + c;
+  const size_t dn = (size_t)W * C8;
+  const bf16x8 v0 = x[s], v1 = x[s + C8], v2 = x[s + dn], v3 = x[s + dn + C8];
+  bf16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    o[e] = (bf16)(0.25f * ((float)v0[e] + (float)v1[e] + (float)v2[e] + (float)v3[e]));
+  y[(size_t)row * Wo * C8 + i] = o;
+}
+
+__global__ void __launch_bounds__(256) pool2_grad_v8_kernel(const bf16x8 *__restrict__ dy, int H,
+                                                            int W, int C8,
+                                                            bf16x8 *__restrict__ dx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * C8) return;
+  const int j = i / C8, c = i - j * C8;
+  const int row = blockIdx.y, b = row / H, ii = row - b * H;  // row of dx
+  const bf16x8 v = dy[((size_t)(b * (H / 2) + ii / 2) * (W / 2) + j / 2) * C8 + c];
+  bf16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = (bf16)(0.25f * (float)v[e]);
+  dx[(size_t)row * W * C8 + i] = o;
+}
+
+__global__ void __launch_bounds__(256) up2_grad_v8_kernel(const bf16x8 *__restrict__ dy, int H,
+                                                          int W, int C8, bf16x8 *__restrict__ dx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * C8) return;
+  const int j = i / C8, c = i - j * C8;
+  const int row = blockIdx.y, b = row / H, ii = row - b * H;  // row of dx (H x W)
+  const size_t s = ((size_t)(b * 2 * H + 2 * ii) * 2 * W + 2 * j) * C8 + c;
+  const size_t dn = (size_t)2 * W * C8;
+  const bf16x8 v0 = dy[s], v1 = dy[s + C8], v2 = dy[s + dn], v3 = dy[s + dn + C8];
+  bf16x8 o;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = (bf16)((float)v0[e] + (float)v1[e] + (float)v2[e] + (float)v3[e]);
+  dx[(size_t)row * W * C8 + i] = o;
+}
+
+__global__ void __launch_bounds__(256) act_grad_v8_kernel(const bf16x8 *__restrict__ g0,
+                                                          const bf16x8 *__restrict__ g1,
+                                                          const bf16x8 *__restrict__ out,
+                                                          size_t n8, float slope,
+                                                          bf16x8 *__restrict__ dz) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n8) return;
+  const bf16x8 a = g0[i], o = out[i];
+  bf16x8 b = {};
+  if (g1) b = g1[i];
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    float s = (float)a[e];
+    if (g1) s = (float)(bf16)(s + (float)b[e]);
+    r[e] = (bf16)((float)o[e] > 0.0f ? s : slope * s);
+  }
+  dz[i] = r;
+}
+
 __global__ void __launch_bounds__(256) act_grad_kernel(const bf16 *__restrict__ g0,
                                                        const bf16 *__restrict__ g1,
                                                        const bf16 *__restrict__ out, size_t n,
@@ -566,6 +693,78 @@ bool dims_ok(int32_t b, int32_t h, int32_t w) {
 
 }  // namespace
 
+namespace {
+
+// Launch of the forward kernel: pixel tiles (64 PT pixels per workgroup, the
+// largest PT in {4, 2, 1} that still gives about 1024 workgroups), or the
+// split reduction below that.
+void conv_launch(const ConvSrc &x, int32_t batch, int32_t h, int32_t w, const bf16 *wb,
+                 const float *bias, int32_t cout, int32_t act, float slope, const ConvDst &dst,
+                 int32_t y_fp32, hipStream_t s) {
+  const int64_t M = (int64_t)batch * h * w;
+  const unsigned cot = (unsigned)((cout + kCoTile - 1) / kCoTile);
+  auto blocks = [&](int pix) { return (unsigned)((M + pix - 1) / pix); };
+  // column tiles per workgroup: 16 channels (NT = 1), 32 (2) or up to 64 (4)
+  const int nt = cout >= 64 ? 4 : (cout > 16 ? (cout > 32 ? 4 : 2) : 1);
+  auto go = [&](auto pt_tag, auto nt_tag) {
+    constexpr int PT = decltype(pt_tag)::value, NT = decltype(nt_tag)::value;
+    hipLaunchKernelGGL((conv3x3_kernel<false, PT, NT>), dim3(blocks(PT * kPixTile), cot),
+                       dim3(256), 0, s, x, batch, h, w, wb, bias, cout, act, slope, dst, y_fp32);
+  };
+  auto pick_nt = [&](auto pt_tag) {
+    if (nt == 1)
+      go(pt_tag, std::integral_constant<int, 1>{});
+    else if (nt == 2)
+      go(pt_tag, std::integral_constant<int, 2>{});
+    else
+      go(pt_tag, std::integral_constant<int, 4>{});
+  };
+  if ((int64_t)blocks(4 * kPixTile) * cot >= 1024)
+    pick_nt(std::integral_constant<int, 4>{});
+  else if ((int64_t)blocks(2 * kPixTile) * cot >= 1024)
+    pick_nt(std::integral_constant<int, 2>{});
+  else if ((int64_t)blocks(kPixTile) * cot >= 1024)
+    pick_nt(std::integral_constant<int, 1>{});
+  else
+    hipLaunchKernelGGL((conv3x3_kernel<true, 1, 4>), dim3(blocks(16), cot), dim3(256), 0, s, x,
+                       batch, h, w, wb, bias, cout, act, slope, dst, y_fp32);
+}
+
+bool cat_ok(const void *a, int32_t ca, int32_t up, const void *b, int32_t cb, int32_t h,
+            int32_t w) {
+  return a && b && ca > 0 && ca % 16 == 0 && cb > 0 && cb % 16 == 0 && (up == 0 || up == 1) &&
+         (!up || (h % 2 == 0 && w % 2 == 0)) && aligned16(a) && aligned16(b);
+}
+
+void wgrad_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, int32_t w,
+                  int32_t cout, float *dweight, float *dbias, void *workspace, hipStream_t s) {
+  const int cin = x.ca + x.cb;
+  int nsplit, chunk;
+  const int64_t K = 9LL * cin, M = (int64_t)batch * h * w;
+  wgrad_plan(M, wgrad_tiles(cin, cout), &nsplit, &chunk);
+  float *part = static_cast<float *>(workspace);
+  float *partb = part + (size_t)nsplit * cout * K;
+  const int ob = wgrad_ob(cout);
+  const dim3 grid((unsigned)(cout / (16 * ob)), (unsigned)((K + kWgK - 1) / kWgK), nsplit);
+  if (ob == 4)
+    hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, dyb, x, batch, h, w, cout, chunk,
+                       part, partb);
+  else if (ob == 2)
+    hipLaunchKernelGGL(wgrad_kernel<2>, grid, dim3(256), 0, s, dyb, x, batch, h, w, cout, chunk,
+                       part, partb);
+  else
+    hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, dyb, x, batch, h, w, cout, chunk,
+                       part, partb);
+  const size_t n = (size_t)cout * K;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part,
+                     nsplit, n, dweight);
+  if (dbias)
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((cout + 63) / 64)), dim3(256), 0, s,
+                       partb, nsplit, (size_t)cout, dbias);
+}
+
+}  // namespace
+
 extern "C" clb_status clb_nn_conv3x3(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w,
                                      int32_t cin, const clb_bf16 *weight, const float *bias,
                                      int32_t cout, int32_t act, float slope, void *y,
@@ -573,19 +772,41 @@ extern "C" clb_status clb_nn_conv3x3(const clb_bf16 *x, int32_t batch, int32_t h
   if (!x || !weight || !y || !dims_ok(batch, h, w) || cin <= 0 || cin % 16 || cout <= 0 ||
       cout % 16 || (act != 0 && act != 1) || !aligned16(x) || !aligned16(weight))
     return CLB_ERR_ARG;
-  const int64_t M = (int64_t)batch * h * w;
-  const unsigned cot = (unsigned)((cout + kCoTile - 1) / kCoTile);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const bf16 *xb = reinterpret_cast<const bf16 *>(x), *wb = reinterpret_cast<const bf16 *>(weight);
-  // Pixel tiles while they give at least ~1024 workgroups; split the
-  // reduction over the waves of a workgroup below that.
-  if (((M + kPixTile - 1) / kPixTile) * cot >= 1024)
-    hipLaunchKernelGGL(conv3x3_kernel<false>, dim3((unsigned)((M + kPixTile - 1) / kPixTile), cot),
-                       dim3(256), 0, s, xb, batch, h, w, cin, wb, bias, cout, act, slope, y,
-                       y_fp32);
-  else
-    hipLaunchKernelGGL(conv3x3_kernel<true>, dim3((unsigned)((M + 15) / 16), cot), dim3(256), 0,
-                       s, xb, batch, h, w, cin, wb, bias, cout, act, slope, y, y_fp32);
+  const ConvSrc src{reinterpret_cast<const bf16 *>(x), nullptr, cin, 0, 0};
+  const ConvDst dst{y, nullptr, cout};
+  conv_launch(src, batch, h, w, reinterpret_cast<const bf16 *>(weight), bias, cout, act, slope,
+              dst, y_fp32, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_conv3x3_cat(const clb_bf16 *a, int32_t ca, int32_t up_a,
+                                         const clb_bf16 *b, int32_t cb, int32_t batch, int32_t h,
+                                         int32_t w, const clb_bf16 *weight, const float *bias,
+                                         int32_t cout, int32_t act, float slope, void *y,
+                                         int32_t y_fp32, void *stream) {
+  if (!cat_ok(a, ca, up_a, b, cb, h, w) || !weight || !y || !dims_ok(batch, h, w) || cout <= 0 ||
+      cout % 16 || (act != 0 && act != 1) || !aligned16(weight))
+    return CLB_ERR_ARG;
+  const ConvSrc src{reinterpret_cast<const bf16 *>(a), reinterpret_cast<const bf16 *>(b), ca, cb,
+                    up_a};
+  const ConvDst dst{y, nullptr, cout};
+  conv_launch(src, batch, h, w, reinterpret_cast<const bf16 *>(weight), bias, cout, act, slope,
+              dst, y_fp32, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_conv3x3_split(const clb_bf16 *x, int32_t batch, int32_t h,
+                                           int32_t w, int32_t cin, const clb_bf16 *weight,
+                                           int32_t cout, int32_t split, clb_bf16 *y0,
+                                           clb_bf16 *y1, void *stream) {
+  if (!x || !weight || !y0 || !y1 || !dims_ok(batch, h, w) || cin <= 0 || cin % 16 ||
+      cout <= 0 || cout % 16 || split <= 0 || split >= cout || split % 16 || !aligned16(x) ||
+      !aligned16(weight))
+    return CLB_ERR_ARG;
+  const ConvSrc src{reinterpret_cast<const bf16 *>(x), nullptr, cin, 0, 0};
+  const ConvDst dst{y0, y1, split};
+  conv_launch(src, batch, h, w, reinterpret_cast<const bf16 *>(weight), nullptr, cout, 0, 0.0f,
+              dst, 0, static_cast<hipStream_t>(stream));
   return launched();
 }
 
@@ -608,30 +829,26 @@ extern "C" clb_status clb_nn_conv3x3_wgrad(const clb_bf16 *dy, const clb_bf16 *x
   if (clb_nn_wgrad_workspace_bytes(batch, h, w, cin, cout, &need) != CLB_OK || !dy || !x ||
       !dweight || !workspace || bytes < need || !aligned16(dy) || !aligned16(x))
     return CLB_ERR_ARG;
-  int nsplit, chunk;
-  const int64_t K = 9LL * cin, M = (int64_t)batch * h * w;
-  wgrad_plan(M, wgrad_tiles(cin, cout), &nsplit, &chunk);
-  float *part = static_cast<float *>(workspace);
-  float *partb = part + (size_t)nsplit * cout * K;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int ob = wgrad_ob(cout);
-  const dim3 grid((unsigned)(cout / (16 * ob)), (unsigned)((K + kWgK - 1) / kWgK), nsplit);
-  const bf16 *dyb = reinterpret_cast<const bf16 *>(dy), *xb = reinterpret_cast<const bf16 *>(x);
-  if (ob == 4)
-    hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, dyb, xb, batch, h, w, cin, cout,
-                       chunk, part, partb);
-  else if (ob == 2)
-    hipLaunchKernelGGL(wgrad_kernel<2>, grid, dim3(256), 0, s, dyb, xb, batch, h, w, cin, cout,
-                       chunk, part, partb);
-  else
-    hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, dyb, xb, batch, h, w, cin, cout,
-                       chunk, part, partb);
-  const size_t n = (size_t)cout * K;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part,
-                     nsplit, n, dweight);
-  if (dbias)
-    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((cout + 63) / 64)), dim3(256), 0, s,
-                       partb, nsplit, (size_t)cout, dbias);
+  const ConvSrc src{reinterpret_cast<const bf16 *>(x), nullptr, cin, 0, 0};
+  wgrad_launch(reinterpret_cast<const bf16 *>(dy), src, batch, h, w, cout, dweight, dbias,
+               workspace, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_conv3x3_wgrad_cat(const clb_bf16 *dy, const clb_bf16 *a, int32_t ca,
+                                               int32_t up_a, const clb_bf16 *b, int32_t cb,
+                                               int32_t batch, int32_t h, int32_t w, int32_t cout,
+                                               float *dweight, float *dbias, void *workspace,
+                                               size_t bytes, void *stream) {
+  size_t need = 0;
+  if (!cat_ok(a, ca, up_a, b, cb, h, w) ||
+      clb_nn_wgrad_workspace_bytes(batch, h, w, ca + cb, cout, &need) != CLB_OK || !dy ||
+      !dweight || !workspace || bytes < need || !aligned16(dy))
+    return CLB_ERR_ARG;
+  const ConvSrc src{reinterpret_cast<const bf16 *>(a), reinterpret_cast<const bf16 *>(b), ca, cb,
+                    up_a};
+  wgrad_launch(reinterpret_cast<const bf16 *>(dy), src, batch, h, w, cout, dweight, dbias,
+               workspace, static_cast<hipStream_t>(stream));
   return launched();
 }
 
@@ -697,20 +914,37 @@ extern "C" clb_status clb_nn_weights_bf16(const float *w32, int32_t cout, int32_
 extern "C" clb_status clb_nn_pool2(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w,
                                    int32_t c, clb_bf16 *y, void *stream) {
   if (!x || !y || !dims_ok(batch, h, w) || h % 2 || w % 2 || c <= 0) return CLB_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c % 8 == 0 && aligned16(x) && aligned16(y) && (int64_t)(w / 2) * (c / 8) < (1 << 30) &&
+      (int64_t)batch * (h / 2) < 65536) {
+    const int C8 = c / 8;
+    hipLaunchKernelGGL(pool2_v8_kernel, dim3(blocks_for((size_t)(w / 2) * C8), batch * (h / 2)),
+                       dim3(256), 0, s, reinterpret_cast<const bf16x8 *>(x), h, w, C8,
+                       reinterpret_cast<bf16x8 *>(y));
+    return launched();
+  }
   const size_t n = (size_t)batch * (h / 2) * (w / 2) * c;
-  hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for(n)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(x), batch,
-                     h, w, c, reinterpret_cast<bf16 *>(y));
+  hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for(n)), dim3(256), 0, s,
+                     reinterpret_cast<const bf16 *>(x), batch, h, w, c, reinterpret_cast<bf16 *>(y));
   return launched();
 }
 
 extern "C" clb_status clb_nn_pool2_grad(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w,
                                         int32_t c, clb_bf16 *dx, void *stream) {
   if (!dy || !dx || !dims_ok(batch, h, w) || h % 2 || w % 2 || c <= 0) return CLB_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c % 8 == 0 && aligned16(dy) && aligned16(dx) && (int64_t)w * (c / 8) < (1 << 30) &&
+      (int64_t)batch * h < 65536) {
+    const int C8 = c / 8;
+    hipLaunchKernelGGL(pool2_grad_v8_kernel, dim3(blocks_for((size_t)w * C8), batch * h),
+                       dim3(256), 0, s, reinterpret_cast<const bf16x8 *>(dy), h, w, C8,
+                       reinterpret_cast<bf16x8 *>(dx));
+    return launched();
+  }
   const size_t n = (size_t)batch * h * w * c;
-  hipLaunchKernelGGL(pool2_grad_kernel, dim3(blocks_for(n)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(dy), batch,
-                     h, w, c, reinterpret_cast<bf16 *>(dx));
+  hipLaunchKernelGGL(pool2_grad_kernel, dim3(blocks_for(n)), dim3(256), 0, s,
+                     reinterpret_cast<const bf16 *>(dy), batch, h, w, c,
+                     reinterpret_cast<bf16 *>(dx));
   return launched();
 }
 
@@ -727,10 +961,19 @@ extern "C" clb_status clb_nn_up2(const clb_bf16 *x, int32_t batch, int32_t h, in
 extern "C" clb_status clb_nn_up2_grad(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w,
                                       int32_t c, clb_bf16 *dx, void *stream) {
   if (!dy || !dx || !dims_ok(batch, 2 * h, 2 * w) || c <= 0) return CLB_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c % 8 == 0 && aligned16(dy) && aligned16(dx) && (int64_t)w * (c / 8) < (1 << 30) &&
+      (int64_t)batch * h < 65536) {
+    const int C8 = c / 8;
+    hipLaunchKernelGGL(up2_grad_v8_kernel, dim3(blocks_for((size_t)w * C8), batch * h), dim3(256),
+                       0, s, reinterpret_cast<const bf16x8 *>(dy), h, w, C8,
+                       reinterpret_cast<bf16x8 *>(dx));
+    return launched();
+  }
   const size_t n = (size_t)batch * h * w * c;
-  hipLaunchKernelGGL(up2_grad_kernel, dim3(blocks_for(n)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(dy), batch,
-                     h, w, c, reinterpret_cast<bf16 *>(dx));
+  hipLaunchKernelGGL(up2_grad_kernel, dim3(blocks_for(n)), dim3(256), 0, s,
+                     reinterpret_cast<const bf16 *>(dy), batch, h, w, c,
+                     reinterpret_cast<bf16 *>(dx));
   return launched();
 }
 
@@ -759,10 +1002,18 @@ extern "C" clb_status clb_nn_act_grad(const clb_bf16 *g0, const clb_bf16 *g1,
                                       const clb_bf16 *out, int64_t n, float slope, clb_bf16 *dz,
                                       void *stream) {
   if (!g0 || !out || !dz || n <= 0) return CLB_ERR_ARG;
-  hipLaunchKernelGGL(act_grad_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), reinterpret_cast<const bf16 *>(g0),
-                     reinterpret_cast<const bf16 *>(g1), reinterpret_cast<const bf16 *>(out),
-                     (size_t)n, slope, reinterpret_cast<bf16 *>(dz));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n % 8 == 0 && aligned16(g0) && (!g1 || aligned16(g1)) && aligned16(out) && aligned16(dz)) {
+    hipLaunchKernelGGL(act_grad_v8_kernel, dim3(blocks_for((size_t)n / 8)), dim3(256), 0, s,
+                       reinterpret_cast<const bf16x8 *>(g0), reinterpret_cast<const bf16x8 *>(g1),
+                       reinterpret_cast<const bf16x8 *>(out), (size_t)n / 8, slope,
+                       reinterpret_cast<bf16x8 *>(dz));
+    return launched();
+  }
+  hipLaunchKernelGGL(act_grad_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s,
+                     reinterpret_cast<const bf16 *>(g0), reinterpret_cast<const bf16 *>(g1),
+                     reinterpret_cast<const bf16 *>(out), (size_t)n, slope,
+                     reinterpret_cast<bf16 *>(dz));
   return launched();
 }
 

@@ -27,7 +27,8 @@ NN_EXPORTS = (
     "clb_nn_weights_bf16", "clb_nn_pool2", "clb_nn_pool2_grad", "clb_nn_up2", "clb_nn_up2_grad",
     "clb_nn_concat", "clb_nn_split", "clb_nn_act_grad", "clb_nn_mse_workspace_bytes",
     "clb_nn_mse", "clb_nn_adamw", "clb_nn_features", "clb_nn_gather",
-    "clb_nn_wgrad_static_max_bytes", "clb_nn_conv3x3_wgrad_static",
+    "clb_nn_wgrad_static_max_bytes", "clb_nn_conv3x3_wgrad_static", "clb_nn_conv3x3_cat",
+    "clb_nn_conv3x3_split", "clb_nn_conv3x3_wgrad_cat",
 )
 
 _ready = False
@@ -44,6 +45,11 @@ def lib():
             "clb_nn_wgrad_workspace_bytes": [i32, i32, i32, i32, i32, sz],
             "clb_nn_conv3x3_wgrad": [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, C.c_size_t, vp],
             "clb_nn_conv3x3_wgrad_static": [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp],
+            "clb_nn_conv3x3_cat": [vp, i32, i32, vp, i32, i32, i32, i32, vp, vp, i32, i32, f32,
+                                   vp, i32, vp],
+            "clb_nn_conv3x3_split": [vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp],
+            "clb_nn_conv3x3_wgrad_cat": [vp, vp, i32, i32, vp, i32, i32, i32, i32, i32, vp, vp,
+                                         vp, C.c_size_t, vp],
             "clb_nn_weights_bf16": [vp, i32, i32, vp, vp, vp],
             "clb_nn_pool2": [vp, i32, i32, i32, i32, vp, vp],
             "clb_nn_pool2_grad": [vp, i32, i32, i32, i32, vp, vp],
@@ -134,6 +140,19 @@ class UNet:
                 self.convs.append((st["out"], self.ch[a]))
                 self.ch.append(st["out"])
                 self.lv.append(self.lv[a])
+        # A decoder convolution reads [up(deep), skip] through the fused
+        # gather: fused[i] = (deep, up tensor, skip) for such a convolution
+        # step i; the up and cat steps it absorbs are not computed (virtual).
+        self.fused, self.virtual = {}, set()
+        for i, st in enumerate(self.steps):
+            if st["op"] != "conv":
+                continue
+            a = st["ins"][0]
+            cat = self.steps[a - 1] if a > 0 else None
+            if cat and cat["op"] == "cat" and self.steps[cat["ins"][0] - 1]["op"] == "up":
+                t_up, t_skip = cat["ins"]
+                self.fused[i] = (self.steps[t_up - 1]["ins"][0], t_up, t_skip)
+                self.virtual |= {a - 1, t_up - 1}
         self.offsets = []
         n = 0
         for o, c in self.convs:
@@ -200,6 +219,9 @@ class UNet:
         for t, (c, lv) in enumerate(zip(self.ch, self.lv)):
             n = batch * (h >> lv) * (w >> lv) * c
             last = t == len(self.ch) - 1
+            if t > 0 and t - 1 in self.virtual:
+                self.vals.append(None)  # never formed
+                continue
             self.vals.append(torch.empty(n, dtype=torch.float32, device=self.device)
                              if last else torch.empty(n, **bf))
         # gradient storage: per tensor up to two contributions, plus the
@@ -208,6 +230,8 @@ class UNet:
         self.dz = [None] * len(self.ch)
         for t, (c, lv) in enumerate(zip(self.ch, self.lv)):
             n = batch * (h >> lv) * (w >> lv) * c
+            if t > 0 and self.steps[t - 1]["op"] == "cat" and t - 1 in self.virtual:
+                continue  # its gradient goes straight to its two parts
             self.gin[t] = [torch.empty(n, **bf), torch.empty(n, **bf)]
             self.dz[t] = torch.empty(n, **bf)
         ws = 0
@@ -237,7 +261,17 @@ class UNet:
         for i, st in enumerate(self.steps):
             t, a = i + 1, st["ins"][0]
             ha, wa = h >> self.lv[a], w >> self.lv[a]
-            if st["op"] == "conv":
+            if i in self.virtual:
+                continue
+            if st["op"] == "conv" and i in self.fused:
+                k = st["k"]
+                w0, b0 = self.offsets[k]
+                deep, t_up, skip = self.fused[i]
+                call("clb_nn_conv3x3_cat", ptr(vals[deep]), self.ch[deep], 1, ptr(vals[skip]),
+                     self.ch[skip], batch, ha, wa, ptr(self.wf[k]),
+                     C.c_void_p(self.p.data_ptr() + 4 * b0), st["out"], 1 if st["act"] else 0,
+                     SLOPE, ptr(vals[t]), 0 if st["act"] else 1, s)
+            elif st["op"] == "conv":
                 k = st["k"]
                 w0, b0 = self.offsets[k]
                 call("clb_nn_conv3x3", ptr(vals[a]), batch, ha, wa, self.ch[a], ptr(self.wf[k]),
@@ -288,6 +322,17 @@ class UNet:
                 else:
                     dz = g0
                 w0, b0 = self.offsets[k]
+                if i in self.fused:
+                    deep, t_up, skip = self.fused[i]
+                    call("clb_nn_conv3x3_wgrad_cat", ptr(dz), ptr(vals[deep]), self.ch[deep], 1,
+                         ptr(vals[skip]), self.ch[skip], batch, ha, wa, st["out"],
+                         C.c_void_p(self.g.data_ptr() + 4 * w0),
+                         C.c_void_p(self.g.data_ptr() + 4 * b0), ptr(self.ws), self.ws.numel(), s)
+                    # input gradient written straight to its two parts
+                    call("clb_nn_conv3x3_split", ptr(dz), batch, ha, wa, st["out"],
+                         ptr(self.wb[k]), self.ch[a], self.ch[t_up], ptr(contrib(t_up)),
+                         ptr(contrib(skip)), s)
+                    continue
                 call("clb_nn_conv3x3_wgrad", ptr(dz), ptr(vals[a]), batch, ha, wa, self.ch[a],
                      st["out"], C.c_void_p(self.g.data_ptr() + 4 * w0),
                      C.c_void_p(self.g.data_ptr() + 4 * b0), ptr(self.ws), self.ws.numel(), s)

@@ -279,3 +279,80 @@ def test_unet_loss_and_gradients_match_oracle(nn):
     assert abs(loss.item() - rl) <= 1e-3 * rl
     assert max(errs) <= 1e-2
     torch.cuda.synchronize()
+
+
+# Decoder-level shapes (batch, h, w, ca, cb, cout): the deep tensor a at half
+# resolution (ca channels), the skip tensor b at full resolution.  The second
+# has over 1024 tiles of 64 pixels (pixel-tiled path with a ragged last tile);
+# the first splits the reduction over the waves.
+CAT_SHAPES = [(2, 8, 12, 32, 16, 16), (2, 96, 64, 32, 32, 32), (1, 16, 16, 128, 64, 64)]
+
+
+@pytest.mark.parametrize("shape", CAT_SHAPES)
+def test_fused_decoder_convolution(nn, shape):
+    """clb_nn_conv3x3_cat reads [up2(a), b] without forming it: bit-identical
+    to clb_nn_up2 + clb_nn_concat + clb_nn_conv3x3, and within the FP32 bound
+    of the oracle's convolution of the formed tensor.  Its weight gradient
+    (clb_nn_conv3x3_wgrad_cat) and the split input gradient
+    (clb_nn_conv3x3_split) match the formed path bit for bit as well."""
+    import torch
+    Bn, H, W, ca, cb, co = shape
+    ci = ca + cb
+    r = rng(31 + sum(shape))
+    a = N.round_bf16(r.standard_normal((Bn, H // 2, W // 2, ca)))
+    b = N.round_bf16(r.standard_normal((Bn, H, W, cb)))
+    w = N.round_bf16(r.standard_normal((co, 9, ci)) / np.sqrt(9 * ci))
+    bias = r.standard_normal(co).astype(np.float32).astype(np.float64)
+    x = np.concatenate([N.up2(a), b], axis=3)
+    ref = N.conv3x3(x, w, bias)
+    bound = N.conv3x3(np.abs(x), np.abs(w), np.abs(bias)) * 1e-5 + 1e-30
+    da, db_, dw, dbias = dev_bf16(a), dev_bf16(b), dev_bf16(w), dev_f32(bias)
+    # the formed path
+    up = empty(Bn * H * W * ca)
+    cat = empty(Bn * H * W * ci)
+    nn.call("clb_nn_up2", nn.ptr(da), Bn, H // 2, W // 2, ca, nn.ptr(up), None)
+    nn.call("clb_nn_concat", nn.ptr(up), ca, nn.ptr(db_), cb, Bn * H * W, nn.ptr(cat), None)
+    for fp32 in (1, 0):
+        y_ref = empty(ref.size, "f32" if fp32 else "bf16")
+        y = empty(ref.size, "f32" if fp32 else "bf16")
+        nn.call("clb_nn_conv3x3", nn.ptr(cat), Bn, H, W, ci, nn.ptr(dw), nn.ptr(dbias), co,
+                1 - fp32, nn.SLOPE, nn.ptr(y_ref), fp32, None)
+        nn.call("clb_nn_conv3x3_cat", nn.ptr(da), ca, 1, nn.ptr(db_), cb, Bn, H, W, nn.ptr(dw),
+                nn.ptr(dbias), co, 1 - fp32, nn.SLOPE, nn.ptr(y), fp32, None)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_ref)
+        if fp32:
+            err = np.abs(host(y).reshape(ref.shape) - ref)
+            log("fused conv %s fp32 max err / bound %.3f" % (shape, (err / bound).max()))
+            assert np.all(err <= bound)
+    # weight gradient on the same input
+    dy = N.round_bf16(r.standard_normal((Bn, H, W, co)))
+    ddy = dev_bf16(dy)
+    nb = C.c_size_t()
+    nn.call("clb_nn_wgrad_workspace_bytes", Bn, H, W, ci, co, C.byref(nb))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    gw_ref, gb_ref = empty(w.size, "f32"), empty(co, "f32")
+    gw, gb = empty(w.size, "f32"), empty(co, "f32")
+    nn.call("clb_nn_conv3x3_wgrad", nn.ptr(ddy), nn.ptr(cat), Bn, H, W, ci, co, nn.ptr(gw_ref),
+            nn.ptr(gb_ref), nn.ptr(ws), nb.value, None)
+    nn.call("clb_nn_conv3x3_wgrad_cat", nn.ptr(ddy), nn.ptr(da), ca, 1, nn.ptr(db_), cb, Bn, H, W,
+            co, nn.ptr(gw), nn.ptr(gb), nn.ptr(ws), nb.value, None)
+    torch.cuda.synchronize()
+    assert torch.equal(gw, gw_ref) and torch.equal(gb, gb_ref)
+    rw, _ = N.conv3x3_grad_weight(dy, x)
+    bw = N.conv3x3_grad_weight(np.abs(dy), np.abs(x))[0] * 1e-5 + 1e-30
+    assert np.all(np.abs(host(gw).reshape(rw.shape) - rw) <= bw)
+    # input gradient split into the two parts
+    wf, wb = empty(w.size), empty(w.size)
+    tw = dev_f32(w)
+    nn.call("clb_nn_weights_bf16", nn.ptr(tw), co, ci, nn.ptr(wf), nn.ptr(wb), None)
+    gx = empty(x.size)
+    nn.call("clb_nn_conv3x3", nn.ptr(ddy), Bn, H, W, co, nn.ptr(wb), None, ci, 0, 0.0,
+            nn.ptr(gx), 0, None)
+    ga_ref, gb2_ref = empty(Bn * H * W * ca), empty(Bn * H * W * cb)
+    nn.call("clb_nn_split", nn.ptr(gx), ca, cb, Bn * H * W, nn.ptr(ga_ref), nn.ptr(gb2_ref), None)
+    ga, gb2 = empty(Bn * H * W * ca), empty(Bn * H * W * cb)
+    nn.call("clb_nn_conv3x3_split", nn.ptr(ddy), Bn, H, W, co, nn.ptr(wb), ci, ca, nn.ptr(ga),
+            nn.ptr(gb2), None)
+    torch.cuda.synchronize()
+    assert torch.equal(ga, ga_ref) and torch.equal(gb2, gb2_ref)
