@@ -2,8 +2,9 @@
 
 Default (the headline line): natural convection in a square porous cavity,
 4096 x 4096 nodes, Ra = 1e6, Da = 1e-4, porosity 0.4, Pr = 1, J = sigma = 1,
-Ergun F_phi, FP32 deviation storage (--storage f16 / mixed for the narrow
-modes).  One "step" is one time step of the whole path for every domain:
+Ergun F_phi, FP32 deviation storage with FP32 arithmetic (--storage f32 for
+FP64 arithmetic, f16 / mixed for the narrow modes); FP64 is used only in the
+reductions.  One "step" is one time step of the whole path for every domain:
 pull streaming + macroscopic values + boundary reconstruction + D2Q9 and
 D2Q5 collisions + store, with the FP64 residual, mass and Nusselt reductions
 every 100 steps (their cost is inside the timed region).  Populations are
@@ -308,7 +309,7 @@ def table1_bench(args):
     out = {"metric": "Table 1 steady mean Nusselt number, deviation from the paper's values",
            "value": round(float(np.median(dev)), 3) if dev.size else None,
            "unit": "% (median |deviation| over steady cases)", "higher_is_better": False,
-           "n_gpus": 1, "data": "synthetic", "dtype": "f64 arithmetic, %s storage" % args.storage,
+           "n_gpus": 1, "data": "synthetic", "dtype": DTYPE[args.storage],
            "config": {"workload": "%d porous cavities of Table 1 in one context" % len(cases),
                       "tol": tol, "check_every": every, "max_steps": cap, "init": args.init},
            "wall_s": round(wall, 1), "steady": int((status == OK).sum()),
@@ -876,8 +877,9 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="grid size (cavity; channel: 2048)")
     ap.add_argument("--count", type=int, default=None,
                     help="domains of the batch (256) or warmstart (500) workload")
-    ap.add_argument("--storage", choices=("f32", "f32c", "f16", "mixed"), default="f32",
-                    help="f32: FP32 planes, FP64 arithmetic; f32c: FP32 planes, FP32 arithmetic")
+    ap.add_argument("--storage", choices=("f32", "f32c", "f16", "mixed"), default=None,
+                    help="f32c: FP32 planes, FP32 arithmetic (default of the cavity workload); "
+                         "f32: FP32 planes, FP64 arithmetic (default of the others)")
     ap.add_argument("--weights", default=None, help="warmstart: network weights (.npz)")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -890,6 +892,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
+    if args.storage is None:
+        args.storage = "f32c" if args.workload == "cavity" else "f32"
     if args.workload == "oracle-timing":
         return oracle_timing()
     if args.gpus != 1:

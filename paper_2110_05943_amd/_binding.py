@@ -332,7 +332,7 @@ class Solver:
         _check(_lib().clb_set_launch(self._ctx, tile_x, tile_y, blocks), "clb_set_launch")
 
     def set_steps_per_launch(self, steps):
-        """1 or 2 time steps per kernel launch (2: FP32 planes only, "f32" or "f32c")."""
+        """1 or 2 time steps per kernel launch (any storage mode)."""
         _check(_lib().clb_set_steps_per_launch(self._ctx, int(steps)), "clb_set_steps_per_launch")
 
     def get_steps_per_launch(self):

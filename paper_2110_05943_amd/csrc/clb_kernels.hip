@@ -106,6 +106,37 @@ using StoreF16 = Store<_Float16, _Float16, float>;   // FP16 planes, FP32 arithm
 using StoreMix = Store<_Float16, float, float>;      // FP16 flow, FP32 temperature
 using StoreF32C = Store<float, float, float>;        // FP32 planes, FP32 arithmetic
 
+// With FP32 arithmetic and FP32 planes every stored value is the
+// round-to-nearest result of its last operation, a rounding that repeats at a
+// node step after step.  Where such a repeated rounding changes a conserved
+// quantity, the slow dynamics integrate it: here the node's heat, i.e. the
+// sum of the incoming D2Q5 populations and the rest population that closes
+// it after the collision (which holds most of the heat).  That policy
+// therefore carries the exact errors of those additions (compensated
+// arithmetic, all in FP32) and rounds the compensated rest population
+// stochastically; the other planes keep round-to-nearest.
+template <typename P>
+constexpr bool kCompensatedRest = std::is_same<P, StoreF32C>::value;
+
+// s = a + b rounded to nearest, and its exact error e (a + b = s + e):
+// Knuth's TwoSum, six FP32 additions with no assumption on |a| and |b|.
+__device__ __forceinline__ float two_sum(float a, float b, float &e) {
+  const float s = a + b;
+  const float bv = s - a, av = s - bv;
+  e = (a - av) + (b - bv);
+  return s;
+}
+
+// s + e (s a rounded value, |e| at most half its last place) rounded
+// stochastically to one of the two FP32 neighbours of s + e: with du uniform
+// in [-1/2, 1/2) (16 bits of r), s + (e + du ulp(s)) rounded to nearest is
+// s + ulp(s) floor(e / ulp(s) + du + 1/2), whose mean is s + e.
+__device__ __forceinline__ float round_pair_sr(float s, float e, uint32_t r) {
+  const float ulp = __uint_as_float(__float_as_uint(s) & 0x7F800000u) * 0x1p-23f;
+  const float du = __uint_as_float(((r & 0xFFFFu) << 7) | 0x3F800000u) - 1.5f;
+  return s + __builtin_fmaf(du, ulp, e);
+}
+
 // The domain constants in the arithmetic type R of a kernel.
 template <typename R>
 __device__ __forceinline__ const DomainConsts<R> &cst(const CavDesc &d);
@@ -208,6 +239,7 @@ struct NodeState {
   R dr, jx, jy, k20, k02, k11, k21, k12, k22;
   R n1, n2, n3, n4;
   R sg;                 // sigma theta = sum of the D2Q5 deviations (conserved)
+  R sg_lo;              // rounding error of sg (kCompensatedRest policy only)
   R th;                 // theta = T - T0
   R rho, ux, uy, umag;
   R phi, ip, cd, cf;    // medium at this node
@@ -418,9 +450,21 @@ __device__ __forceinline__ void gather_moments(const CavDesc &d, const Src &src,
   // D2Q5 raw moments (Eq. 24); theta from Eq. 36
   st.n1 = g1 - g3;
   st.n2 = g2 - g4;
-  st.n3 = g1 + g3;
-  st.n4 = g2 + g4;
-  st.sg = g0 + (st.n3 + st.n4);
+  if constexpr (kCompensatedRest<P>) {
+    // the heat sum and the exact error of its four roundings, which the
+    // collision returns to the rest population (heat is then conserved
+    // without a rounding bias)
+    R e3, e4, e5, e6;
+    st.n3 = two_sum(g1, g3, e3);
+    st.n4 = two_sum(g2, g4, e4);
+    const R s = two_sum(st.n3, st.n4, e5);
+    st.sg = two_sum(g0, s, e6);
+    st.sg_lo = (e3 + e4) + (e5 + e6);
+  } else {
+    st.n3 = g1 + g3;
+    st.n4 = g2 + g4;
+    st.sg = g0 + (st.n3 + st.n4);
+  }
   st.th = st.sg * cst<R>(d).isig;
 
   medium_at(d, r0 + xs, st.phi, st.ip, st.cd, st.cf);
@@ -547,6 +591,7 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const Src &A, int x
     st.n3 += (hv * thb + ubx * ubx * Tb) - (hv * thf + uxf * uxf * Tf);
     st.n4 += (hv * thb + uby * uby * Tb) - (hv * thf + uyf * uyf * Tf);
     st.sg = cst<R>(d).sig * thb;
+    st.sg_lo = R(0);
     st.th = thb;
     st.rho = R(1) + st.dr;
     st.ux = ubx;
@@ -560,7 +605,7 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const Src &A, int x
 // MRT form with N = N_T = I): the 14 post-collision deviations, D2Q9 first.
 template <typename P, bool RAW, bool ROWS, typename R = typename P::R>
 __device__ __forceinline__ void collide(const CavDesc &d, const NodeState<R> &st, bool wall,
-                                        R out[kPlanes]) {
+                                        R out[kPlanes], R &rest_err) {
   const R rho = st.rho, ux = st.ux, uy = st.uy, ip = st.ip, dr = st.dr;
   const R jx = st.jx, jy = st.jy;
   const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
@@ -693,7 +738,17 @@ __device__ __forceinline__ void collide(const CavDesc &d, const NodeState<R> &st
   const R g4 = half * (ay_ - by_);
   // rest population from heat conservation (equal to
   // (sigma - varpi) theta - |u|^2 T - 2 u.q - e3 - e4)
-  const R g0 = st.sg - ((g1 + g3) + (g2 + g4));
+  R g0;
+  if constexpr (kCompensatedRest<P>) {
+    // g0 + rest_err = (sg + sg_lo) - ((g1 + g3) + (g2 + g4)) with only the
+    // two pair sums rounded
+    R e1, e2;
+    const R gs = two_sum(g1 + g3, g2 + g4, e1);
+    g0 = two_sum(st.sg, -gs, e2);
+    rest_err = (e2 - e1) + st.sg_lo;
+  } else {
+    g0 = st.sg - ((g1 + g3) + (g2 + g4));
+  }
 
   out[0] = f0;
   out[1] = f1;
@@ -712,9 +767,10 @@ __device__ __forceinline__ void collide(const CavDesc &d, const NodeState<R> &st
 }
 
 // Store post-collision deviations to the planes of `buf` at element offset
-// idx, stochastically rounded with random words of (idx, seed).
+// idx, stochastically rounded with random words of (idx, seed); rest_err is
+// the rounding error of the D2Q5 rest population (kCompensatedRest).
 template <typename P, typename R = typename P::R>
-__device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlanes],
+__device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlanes], R rest_err,
                                              char *__restrict__ buf, int idx, uint32_t seed) {
   const int plane = d.plane;
   typename P::F *of = const_cast<typename P::F *>(fplanes<P>(buf));
@@ -726,6 +782,8 @@ __device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlan
   for (int i = 0; i < kPlanes; ++i) {
     if (i < 9)
       stv(at(uniform_base(of + (size_t)i * plane), uidx), out[i], (i & 1) ? (w >> 16) : w);
+    else if (i == 9 && kCompensatedRest<P>)
+      stv(at(uniform_base(og), uidx), round_pair_sr(out[9], rest_err, w >> 16), 0u);
     else
       stv(at(uniform_base(og + (size_t)(i - 9) * plane), uidx), out[i],
           (i & 1) ? (w >> 16) : w);
@@ -736,8 +794,8 @@ __device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlan
 // The values store_planes writes (same random words, same rounding) into the
 // two-step kernel's LDS region at element c.
 template <typename P, int TX, typename R = typename P::R>
-__device__ __forceinline__ void store_region(const R out[kPlanes], char *lds, int c, int idx,
-                                             uint32_t seed) {
+__device__ __forceinline__ void store_region(const R out[kPlanes], R rest_err, char *lds, int c,
+                                             int idx, uint32_t seed) {
   typename P::F *F = RegionPlanes<P, TX>::f(lds);
   typename P::G *G = RegionPlanes<P, TX>::g(lds);
   constexpr int N = Region<TX>::N;
@@ -747,6 +805,8 @@ __device__ __forceinline__ void store_region(const R out[kPlanes], char *lds, in
     const uint32_t r = (i & 1) ? (w >> 16) : w;
     if (i < 9)
       F[i * N + c] = enc(F, out[i], r);
+    else if (i == 9 && kCompensatedRest<P>)
+      G[c] = round_pair_sr(out[9], rest_err, r);
     else
       G[(i - 9) * N + c] = enc(G, out[i], r);
     if (i & 1) w = next_bits<R>(w);
@@ -756,9 +816,9 @@ __device__ __forceinline__ void store_region(const R out[kPlanes], char *lds, in
 template <typename P, bool RAW, bool ROWS, typename R = typename P::R>
 __device__ __forceinline__ void collide_store(const CavDesc &d, const NodeState<R> &st, bool wall,
                                               char *__restrict__ buf, int idx, uint32_t seed) {
-  R out[kPlanes];
-  collide<P, RAW, ROWS>(d, st, wall, out);
-  store_planes<P>(d, out, buf, idx, seed);
+  R out[kPlanes], rest_err = 0;
+  collide<P, RAW, ROWS>(d, st, wall, out, rest_err);
+  store_planes<P>(d, out, rest_err, buf, idx, seed);
 }
 
 // ------------------------------------------------------------ step kernel
@@ -856,9 +916,9 @@ __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict
         NodeState<R> st;
         const bool wall =
             node_state<P, ROWS, GlobalSrc<P, EDGE>, EDGE>(d, GlobalSrc<P, EDGE>{A}, x, y, st);
-        R out[kPlanes];
-        collide<P, RAW, ROWS>(d, st, wall, out);
-        store_region<P, TX>(out, lds, c, y * d.pitch + x, seed1);
+        R out[kPlanes], rest_err = 0;
+        collide<P, RAW, ROWS>(d, st, wall, out, rest_err);
+        store_region<P, TX>(out, rest_err, lds, c, y * d.pitch + x, seed1);
       }
       __syncthreads();
       const uint32_t seed2 = mix32((step + 1) * 0x9E3779B9u + (uint32_t)cav * 0x85EBCA6Bu);
