@@ -114,6 +114,18 @@ clb_status clb_nn_conv3x3_wgrad_cat(const clb_bf16 *dy, const clb_bf16 *a, int32
 clb_status clb_nn_weights_bf16(const float *w32, int32_t cout, int32_t cin, clb_bf16 *w_fwd,
                                clb_bf16 *w_bwd, void *stream);
 
+/* clb_nn_weights_bf16 for the nlayers convolutions of one flat parameter
+ * array, in one launch: layer l has cout[l] x 9 x cin[l] weights starting at
+ * element offset[l] of w32, and its two bfloat16 copies start at the same
+ * element offset of w_fwd and w_bwd (arrays as long as w32; elements outside
+ * the layers' weights are left unchanged).  cout, cin and offset are host
+ * arrays of nlayers entries, 1 <= nlayers <= CLB_NN_MAX_LAYERS; the layers
+ * must not overlap. */
+#define CLB_NN_MAX_LAYERS 64
+clb_status clb_nn_weights_bf16_layers(const float *w32, int32_t nlayers, const int32_t *cout,
+                                      const int32_t *cin, const int64_t *offset,
+                                      clb_bf16 *w_fwd, clb_bf16 *w_bwd, void *stream);
+
 /* 2x2 average pooling of x (batch, h, w, c) into (batch, h/2, w/2, c), h and w
  * even; and its gradient dx[b,i,j,c] = dy[b,i/2,j/2,c] / 4. */
 clb_status clb_nn_pool2(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w, int32_t c,

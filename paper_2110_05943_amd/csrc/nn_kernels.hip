@@ -246,6 +246,88 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(
   }
 }
 
+// Forward 3x3 convolution over bands of image rows, for inputs small enough
+// to stage in LDS: a workgroup computes the R W = 64 PT pixels of R rows of
+// one image for 16 NT output channels.  It copies the input rows band - 1 ..
+// band + R with a zero column on each side ((R + 2) x (W + 2) pixels x cin
+// channels, through the ConvSrc, so the upsampled and concatenated decoder
+// inputs work as in conv3x3_kernel) and the 16 NT weight rows into LDS once;
+// every tap then reads its shifted pixels from LDS (channels contiguous: a
+// lane's 8 k are 16 aligned bytes).  The GEMM is that of conv3x3_kernel
+// (rows = pixels, columns = output channels, k = tap x channel in steps of
+// 32); wave w takes the pixel tiles 16 (w + 4 p), p < PT.
+template <int PT, int NT>
+__global__ void __launch_bounds__(256) conv3x3_rows_kernel(
+    ConvSrc x, int B, int H, int W, const bf16 *__restrict__ wt, const float *__restrict__ bias,
+    int cout, int act, float slope, ConvDst dst, int y_fp32, int R) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cin = x.ca + x.cb, K = 9 * cin, KP = K + 8, nsteps = (K + 31) / 32;
+  const int WP = W + 2;
+  bf16 *sin = reinterpret_cast<bf16 *>(lds_raw);   // [R + 2][W + 2][cin]
+  bf16 *sw = sin + (size_t)(R + 2) * WP * cin;      // [16 NT][K + 8]
+  const int bands_img = H / R;
+  const int n = blockIdx.x / bands_img, y0 = (blockIdx.x - n * bands_img) * R;
+  const int co0 = blockIdx.y * kCoTile;
+  const int nt = min(NT, (cout - co0) >> 4);
+  const int row = lane & 15, kq = 8 * (lane >> 4);
+  // input rows y0 - 1 .. y0 + R, columns -1 .. W (zero outside the image)
+  const int cg = cin / 8, nvec = (R + 2) * WP * cg;
+  for (int v = threadIdx.x; v < nvec; v += 256) {
+    const int c8 = v % cg, pix = v / cg;
+    const int r = pix / WP, cc = pix - r * WP;
+    const bf16x8 val = src_load(x, n, y0 - 1 + r, cc - 1, 8 * c8, H, W);
+    *reinterpret_cast<bf16x8 *>(sin + (size_t)pix * cin + 8 * c8) = val;
+  }
+  // the weight rows of this workgroup's output channels
+  const int kv = K / 8;
+  for (int v = threadIdx.x; v < 16 * NT * kv; v += 256) {
+    const int o = v / kv, k8 = v - o * kv;
+    bf16x8 val = {};
+    if (o < 16 * nt) val = *reinterpret_cast<const bf16x8 *>(wt + (size_t)(co0 + o) * K + 8 * k8);
+    *reinterpret_cast<bf16x8 *>(sw + o * KP + 8 * k8) = val;
+  }
+  __syncthreads();
+  f4 acc[PT][NT];
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[p][t] = f4{0.f, 0.f, 0.f, 0.f};
+  int base[PT];  // LDS pixel index of each tile's pixel at tap (0, 0), i.e. (y - 1, x - 1)
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int m = 16 * (wave + 4 * p) + row;
+    const int r = m / W, c = m - r * W;
+    base[p] = r * WP + c;
+  }
+  const bf16x8 zero = {};
+  for (int s = 0; s < nsteps; ++s) {
+    const int k = 32 * s + kq;
+    const bool kok = k < K;
+    const int tap = kok ? k / cin : 0, c = k - tap * cin;
+    const int toff = (tap / 3) * WP + tap % 3;
+    bf16x8 a[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+      a[p] = kok ? *reinterpret_cast<const bf16x8 *>(sin + (size_t)(base[p] + toff) * cin + c)
+                 : zero;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t < nt) {
+        const bf16x8 b = kok ? *reinterpret_cast<const bf16x8 *>(sw + (16 * t + row) * KP + k)
+                             : zero;
+#pragma unroll
+        for (int p = 0; p < PT; ++p) acc[p][t] = mfma16(a[p], b, acc[p][t]);
+      }
+    }
+  }
+  const int mb = ((n * H) + y0) * W;
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+    conv_store<NT>(acc[p], nt, mb + 16 * (wave + 4 * p), B * H * W, co0, lane, bias, cout, act,
+                   slope, dst, y_fp32);
+}
+
 // Weight gradient as a GEMM: rows = output channels o, columns = k = t*cin + c,
 // reduction over the pixels of one chunk.  A workgroup (4 waves) computes a
 // (16 OB) x 64 tile of (o, k), OB = 1, 2 or 4 output blocks of 16 channels;
@@ -365,24 +447,226 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
   }
 }
 
-// Sum of `nsplit` partial arrays of length n in a fixed order: block b adds
-// outputs [64 b, 64 b + 64); wave w of the block takes the splits w, w + 4,
-// w + 8, ... in increasing order (64 consecutive outputs per load: coalesced),
-// and the four wave sums are added in wave order.
+// Weight gradient over bands of image rows (W a multiple of 8, at most 256):
+// a workgroup owns 16 OB output channels x 16 CB input channels for all nine
+// taps and runs over bands of R rows of one image (P = R W pixels, R =
+// min(H, 256 / W)).  Per band it loads dy[band, o tile] and the input rows
+// band - 1 .. band + R of its channel tile; each thread takes blocks of 8
+// pixels x 8 channels (eight 16-byte loads), transposes them in registers
+// (v_perm) and stores 8 pixel-contiguous 16-byte rows to LDS.  Every tap then
+// reads the same LDS rows: the row shift of a tap is a row offset, the column
+// shift comes from two aligned 16-byte reads joined by v_alignbyte.  The four
+// waves take every fourth 32-pixel reduction step of the band and add their
+// sums in wave order at the end.  Partial sums per chunk of bands go to
+// `part` (bias partial sums, for the first channel tile, to `partb`), laid
+// out as for wgrad_kernel.
+constexpr int kRowPix = 256;             // pixels per band at most
+constexpr int kDyPitch = kRowPix + 8;    // LDS row of dy^T in bf16
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+// Row r of an 8 x 8 block in registers (8 pixels x 8 channels, pixel-major)
+// into 8 channel rows of 8 pixels: channel 2k takes the low halves of dword
+// k of the pixels, channel 2k + 1 the high halves.
+__device__ __forceinline__ void transpose8(const u4 in[8], u4 out[8]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      out[2 * k][j] = __builtin_amdgcn_perm(in[2 * j + 1][k], in[2 * j][k], 0x05040100u);
+      out[2 * k + 1][j] = __builtin_amdgcn_perm(in[2 * j + 1][k], in[2 * j][k], 0x07060302u);
+    }
+}
+
+// The 8 bf16 that start 2 bytes before (sh = -1) or after (sh = +1) the
+// aligned block b of a row whose neighbours are a (before) and c (after).
+__device__ __forceinline__ u4 shift_left1(const u4 &a, const u4 &b) {  // a[7], b[0..6]
+  return u4{__builtin_amdgcn_alignbyte(b[0], a[3], 2), __builtin_amdgcn_alignbyte(b[1], b[0], 2),
+            __builtin_amdgcn_alignbyte(b[2], b[1], 2), __builtin_amdgcn_alignbyte(b[3], b[2], 2)};
+}
+__device__ __forceinline__ u4 shift_right1(const u4 &b, const u4 &c) {  // b[1..7], c[0]
+  return u4{__builtin_amdgcn_alignbyte(b[1], b[0], 2), __builtin_amdgcn_alignbyte(b[2], b[1], 2),
+            __builtin_amdgcn_alignbyte(b[3], b[2], 2), __builtin_amdgcn_alignbyte(c[0], b[3], 2)};
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const u4 &v) {
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
+template <int OB, int CB>
+__global__ void __launch_bounds__(256) wgrad_rows_kernel(const bf16 *__restrict__ dy, ConvSrc x,
+                                                          int B, int H, int W, int cout, int R,
+                                                          int bands_per_chunk,
+                                                          float *__restrict__ part,
+                                                          float *__restrict__ partb) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  constexpr int NO = 16 * OB, NC = 16 * CB;
+  const int cin = x.ca + x.cb, K = 9 * cin;
+  const int XP = W + 16;                 // LDS input row: 8 zeros, W pixels, 8 zeros
+  const int P = R * W, ksteps = P / 32;  // pixels and 32-pixel steps of a band
+  bf16 *sdy = reinterpret_cast<bf16 *>(lds_raw);            // [NO][kDyPitch]
+  bf16 *sx = sdy + NO * kDyPitch;                          // [NC][R + 2][XP]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int o0 = blockIdx.x * NO, c0 = blockIdx.y * NC;
+  const int bands_img = H / R, nbands = B * bands_img;
+  const int b0 = blockIdx.z * bands_per_chunk, b1 = min(nbands, b0 + bands_per_chunk);
+  const bool bias = partb && blockIdx.y == 0;
+  // the zero columns left and right of every input row
+  for (int i = tid; i < NC * (R + 2); i += 256) {
+    *reinterpret_cast<u4 *>(sx + i * XP) = u4{0, 0, 0, 0};
+    *reinterpret_cast<u4 *>(sx + i * XP + W + 8) = u4{0, 0, 0, 0};
+  }
+  f4 acc[OB][9][CB];
+#pragma unroll
+  for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[ob][t][cb] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum[OB];
+#pragma unroll
+  for (int ob = 0; ob < OB; ++ob) bsum[ob] = 0.0f;
+  const int row = lane & 15, g8 = 8 * (lane >> 4);
+  const int dy_units = (P / 8) * (NO / 8), x_units = (R + 2) * (W / 8) * (NC / 8);
+  for (int band = b0; band < b1; ++band) {
+    const int n = band / bands_img, y0 = (band - n * bands_img) * R;
+    const size_t m0 = ((size_t)n * H + y0) * W;
+    __syncthreads();  // the previous band's LDS reads are done
+    for (int u = tid; u < dy_units + x_units; u += 256) {
+      u4 in[8], tr[8];
+      if (u < dy_units) {  // 8 pixels x 8 output channels of dy
+        const int pb = u / (NO / 8), cg = u - pb * (NO / 8);
+        const bf16 *src = dy + (m0 + 8 * pb) * cout + o0 + 8 * cg;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) in[i] = *reinterpret_cast<const u4 *>(src + (size_t)i * cout);
+        transpose8(in, tr);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          *reinterpret_cast<u4 *>(sdy + (8 * cg + c) * kDyPitch + 8 * pb) = tr[c];
+      } else {  // 8 pixels x 8 input channels of input row y0 - 1 + r
+        const int v = u - dy_units;
+        const int cg = v % (NC / 8), rest = v / (NC / 8);
+        const int xb = rest % (W / 8), r = rest / (W / 8);
+        const int yy = y0 - 1 + r;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const bf16x8 t = src_load(x, n, yy, 8 * xb + i, c0 + 8 * cg, H, W);
+          __builtin_memcpy(&in[i], &t, 16);
+        }
+        transpose8(in, tr);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          *reinterpret_cast<u4 *>(sx + ((8 * cg + c) * (R + 2) + r) * XP + 8 + 8 * xb) = tr[c];
+      }
+    }
+    __syncthreads();
+    for (int ks = wave; ks < ksteps; ks += 4) {
+      const int p = 32 * ks + g8;  // this lane's 8 pixels: row pr, columns px .. px + 7
+      const int pr = p / W, px = p - pr * W;
+      bf16x8 a[OB];
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) {
+        a[ob] = *reinterpret_cast<const bf16x8 *>(sdy + (16 * ob + row) * kDyPitch + p);
+        if (bias)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bsum[ob] += (float)a[ob][e];
+      }
+#pragma unroll
+      for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const bf16 *xr = sx + ((16 * cb + row) * (R + 2) + pr + ty) * XP + px;
+          const u4 lo = *reinterpret_cast<const u4 *>(xr);       // columns px - 8 .. px - 1
+          const u4 mid = *reinterpret_cast<const u4 *>(xr + 8);  // px .. px + 7
+          const u4 hi = *reinterpret_cast<const u4 *>(xr + 16);  // px + 8 .. px + 15
+          const bf16x8 bl = as_bf16x8(shift_left1(lo, mid)), bm = as_bf16x8(mid),
+                       bh = as_bf16x8(shift_right1(mid, hi));
+#pragma unroll
+          for (int ob = 0; ob < OB; ++ob) {
+            acc[ob][3 * ty][cb] = mfma16(a[ob], bl, acc[ob][3 * ty][cb]);
+            acc[ob][3 * ty + 1][cb] = mfma16(a[ob], bm, acc[ob][3 * ty + 1][cb]);
+            acc[ob][3 * ty + 2][cb] = mfma16(a[ob], bh, acc[ob][3 * ty + 2][cb]);
+          }
+        }
+    }
+  }
+  // add the four waves' sums in wave order through LDS, one tile at a time
+  f4 *red = reinterpret_cast<f4 *>(lds_raw);  // [3][64]
+  float *redb = reinterpret_cast<float *>(red + 3 * 64);  // [3][OB][64]
+  __syncthreads();
+  if (wave > 0)
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) redb[((wave - 1) * OB + ob) * 64 + lane] = bsum[ob];
+#pragma unroll
+  for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (wave > 0) red[(wave - 1) * 64 + lane] = acc[ob][t][cb];
+        __syncthreads();
+        if (wave == 0) acc[ob][t][cb] = ((acc[ob][t][cb] + red[lane]) + red[64 + lane]) +
+                                        red[128 + lane];
+        __syncthreads();
+      }
+  if (wave != 0) return;
+  // D: lane holds input channel c0 + 16 cb + row, output channels
+  // o0 + 16 ob + 4 (lane / 16) + e
+  const size_t base = (size_t)blockIdx.z * cout * K;
+#pragma unroll
+  for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int o = o0 + 16 * ob + 4 * (lane >> 4) + e;
+          part[base + (size_t)o * K + t * cin + c0 + 16 * cb + row] = acc[ob][t][cb][e];
+        }
+  if (bias)
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+      float b = ((bsum[ob] + redb[ob * 64 + lane]) + redb[(OB + ob) * 64 + lane]) +
+                redb[(2 * OB + ob) * 64 + lane];
+      b += __shfl_xor(b, 16, 64);
+      b += __shfl_xor(b, 32, 64);
+      if (lane < 16) partb[(size_t)blockIdx.z * cout + o0 + 16 * ob + lane] = b;
+    }
+}
+
+// Sums of `nsplit` partial arrays in a fixed order, for two arrays at once:
+// outputs i < n add part[z n + i] into out[i], outputs n <= i < n + nb add
+// partb[z nb + i - n] into outb[i - n].  Block b adds outputs [64 b, 64 b +
+// 64); wave w of the block takes the splits w, w + 4, w + 8, ... in
+// increasing order (64 consecutive outputs per load: coalesced), and the four
+// wave sums are added in wave order.
 __global__ void __launch_bounds__(256) sum_parts_kernel(const float *__restrict__ part,
                                                         int nsplit, size_t n,
-                                                        float *__restrict__ out) {
+                                                        float *__restrict__ out,
+                                                        const float *__restrict__ partb,
+                                                        size_t nb, float *__restrict__ outb) {
   __shared__ float lds[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const size_t i = (size_t)blockIdx.x * 64 + lane;
+  const bool second = i >= n;
+  const float *src = second ? partb + (i - n) : part + i;
+  const size_t stride = second ? nb : n;
   float s = 0.0f;
-  if (i < n) {
+  if (i < n + nb) {
 #pragma unroll 8
-    for (int z = w; z < nsplit; z += 4) s += part[(size_t)z * n + i];
+    for (int z = w; z < nsplit; z += 4) s += src[(size_t)z * stride];
   }
   lds[w][lane] = s;
   __syncthreads();
-  if (w == 0 && i < n) out[i] = ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane];
+  if (w == 0 && i < n + nb) {
+    const float v = ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane];
+    if (second)
+      outb[i - n] = v;
+    else
+      out[i] = v;
+  }
 }
 
 __global__ void __launch_bounds__(256) weights_kernel(const float *__restrict__ w32, int cout,
@@ -394,6 +678,31 @@ __global__ void __launch_bounds__(256) weights_kernel(const float *__restrict__ 
   const bf16 v = (bf16)w32[i];
   wf[i] = v;
   wb[((size_t)c * 9 + (8 - t)) * cout + o] = v;
+}
+
+// The layer table of weights_layers_kernel: the workgroups of layer l are
+// [block0[l], block0[l + 1]).
+struct WeightLayers {
+  int n;
+  int cout[CLB_NN_MAX_LAYERS], cin[CLB_NN_MAX_LAYERS];
+  long long offset[CLB_NN_MAX_LAYERS];
+  int block0[CLB_NN_MAX_LAYERS + 1];
+};
+
+__global__ void __launch_bounds__(256) weights_layers_kernel(const float *__restrict__ w32,
+                                                             WeightLayers L,
+                                                             bf16 *__restrict__ wf,
+                                                             bf16 *__restrict__ wb) {
+  int l = 0;
+  while (l + 1 < L.n && (int)blockIdx.x >= L.block0[l + 1]) ++l;
+  const int cout = L.cout[l], cin = L.cin[l];
+  const int i = (blockIdx.x - L.block0[l]) * blockDim.x + threadIdx.x;
+  if (i >= cout * 9 * cin) return;
+  const int o = i / (9 * cin), r = i - o * 9 * cin, t = r / cin, c = r - t * cin;
+  const size_t base = (size_t)L.offset[l];
+  const bf16 v = (bf16)w32[base + i];
+  wf[base + i] = v;
+  wb[base + ((size_t)c * 9 + (8 - t)) * cout + o] = v;
 }
 
 __global__ void __launch_bounds__(256) pool2_kernel(const bf16 *__restrict__ x, int B, int H,
@@ -574,18 +883,21 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ out,
   __shared__ double lds[4];
   const double scale = 2.0 / ((double)npix * nch);
   double s = 0.0;
-  const size_t n = npix * ldo;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const size_t p = i / ldo;
-    const int c = i - p * ldo;
-    float g = 0.0f;
-    if (c < nch) {
-      const float d = out[i] - tgt[p * nch + c];
-      s += (double)d * d;
-      g = (float)(scale * d);
+  // one pixel (its ldo channels) per thread and iteration
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix;
+       p += (size_t)gridDim.x * blockDim.x) {
+    const float *o = out + p * ldo;
+    const float *t = tgt + p * nch;
+    bf16 *g = dout + p * ldo;
+    for (int c = 0; c < ldo; ++c) {
+      float v = 0.0f;
+      if (c < nch) {
+        const float d = o[c] - t[c];
+        s += (double)d * d;
+        v = (float)(scale * d);
+      }
+      g[c] = (bf16)v;
     }
-    dout[i] = (bf16)g;
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
@@ -698,6 +1010,13 @@ namespace {
 // Launch of the forward kernel: pixel tiles (64 PT pixels per workgroup, the
 // largest PT in {4, 2, 1} that still gives about 1024 workgroups), or the
 // split reduction below that.
+// LDS bytes of conv3x3_rows_kernel for bands of r rows, or 0 if it exceeds
+// 64 KiB.
+size_t conv_rows_lds(int r, int w, int cin, int nt) {
+  const size_t b = sizeof(bf16) * ((size_t)(r + 2) * (w + 2) * cin + (size_t)16 * nt * (9 * cin + 8));
+  return b <= 65536 ? b : 0;
+}
+
 void conv_launch(const ConvSrc &x, int32_t batch, int32_t h, int32_t w, const bf16 *wb,
                  const float *bias, int32_t cout, int32_t act, float slope, const ConvDst &dst,
                  int32_t y_fp32, hipStream_t s) {
@@ -706,6 +1025,38 @@ void conv_launch(const ConvSrc &x, int32_t batch, int32_t h, int32_t w, const bf
   auto blocks = [&](int pix) { return (unsigned)((M + pix - 1) / pix); };
   // column tiles per workgroup: 16 channels (NT = 1), 32 (2) or up to 64 (4)
   const int nt = cout >= 64 ? 4 : (cout > 16 ? (cout > 32 ? 4 : 2) : 1);
+  const int cin = x.ca + x.cb;
+  // Bands of rows staged in LDS: 64 PT pixels per workgroup (PT = 4, 2, 1),
+  // whole rows, bands tiling the image height, at least 256 workgroups.
+  for (int pt = 4; pt >= 1; pt /= 2) {
+    const int pix = 64 * pt;
+    if (pix % w || h % (pix / w)) continue;
+    const int r = pix / w;
+    const size_t lds = conv_rows_lds(r, w, cin, nt);
+    const int64_t wgs = (int64_t)batch * (h / r) * cot;
+    if (!lds || wgs < 256) continue;
+    const dim3 grid((unsigned)(batch * (h / r)), cot);
+    auto go = [&](auto pt_tag, auto nt_tag) {
+      constexpr int PT = decltype(pt_tag)::value, NT = decltype(nt_tag)::value;
+      hipLaunchKernelGGL((conv3x3_rows_kernel<PT, NT>), grid, dim3(256), lds, s, x, batch, h, w,
+                         wb, bias, cout, act, slope, dst, y_fp32, r);
+    };
+    auto pick = [&](auto pt_tag) {
+      if (nt == 1)
+        go(pt_tag, std::integral_constant<int, 1>{});
+      else if (nt == 2)
+        go(pt_tag, std::integral_constant<int, 2>{});
+      else
+        go(pt_tag, std::integral_constant<int, 4>{});
+    };
+    if (pt == 4)
+      pick(std::integral_constant<int, 4>{});
+    else if (pt == 2)
+      pick(std::integral_constant<int, 2>{});
+    else
+      pick(std::integral_constant<int, 1>{});
+    return;
+  }
   auto go = [&](auto pt_tag, auto nt_tag) {
     constexpr int PT = decltype(pt_tag)::value, NT = decltype(nt_tag)::value;
     hipLaunchKernelGGL((conv3x3_kernel<false, PT, NT>), dim3(blocks(PT * kPixTile), cot),
@@ -736,6 +1087,29 @@ bool cat_ok(const void *a, int32_t ca, int32_t up, const void *b, int32_t cb, in
          (!up || (h % 2 == 0 && w % 2 == 0)) && aligned16(a) && aligned16(b);
 }
 
+// Rows per band of the row-band weight gradient, or 0 where it does not
+// apply (the width must be a multiple of 8 and at most 256, the bands must
+// tile the image height, and a band must hold whole 32-pixel steps).
+int wgrad_rows(int32_t h, int32_t w) {
+  if (w % 8 || w > kRowPix) return 0;
+  const int r = std::min<int>(h, kRowPix / w);
+  return (h % r == 0 && (r * w) % 32 == 0) ? r : 0;
+}
+
+template <int OB, int CB>
+void wgrad_rows_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, int32_t w,
+                       int32_t cout, int r, int nsplit_max, float *part, float *partb,
+                       int *nsplit, hipStream_t s) {
+  const int cin = x.ca + x.cb;
+  const int nbands = batch * (h / r);
+  const int bpc = (nbands + std::min(nbands, nsplit_max) - 1) / std::min(nbands, nsplit_max);
+  *nsplit = (nbands + bpc - 1) / bpc;
+  const size_t lds = sizeof(bf16) * ((size_t)16 * OB * kDyPitch + (size_t)16 * CB * (r + 2) * (w + 16));
+  const dim3 grid((unsigned)(cout / (16 * OB)), (unsigned)(cin / (16 * CB)), (unsigned)*nsplit);
+  hipLaunchKernelGGL((wgrad_rows_kernel<OB, CB>), grid, dim3(256), lds, s, dyb, x, batch, h, w,
+                     cout, r, bpc, part, partb);
+}
+
 void wgrad_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, int32_t w,
                   int32_t cout, float *dweight, float *dbias, void *workspace, hipStream_t s) {
   const int cin = x.ca + x.cb;
@@ -746,7 +1120,18 @@ void wgrad_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, i
   float *partb = part + (size_t)nsplit * cout * K;
   const int ob = wgrad_ob(cout);
   const dim3 grid((unsigned)(cout / (16 * ob)), (unsigned)((K + kWgK - 1) / kWgK), nsplit);
-  if (ob == 4)
+  const int r = wgrad_rows(h, w);
+  if (r) {
+    // partb stays where the workspace size puts it; the row-band launch uses
+    // at most nsplit chunks
+    const int cap = nsplit;
+    if (cout % 32 == 0)
+      wgrad_rows_launch<2, 1>(dyb, x, batch, h, w, cout, r, cap, part, partb, &nsplit, s);
+    else if (cin % 32 == 0)
+      wgrad_rows_launch<1, 2>(dyb, x, batch, h, w, cout, r, cap, part, partb, &nsplit, s);
+    else
+      wgrad_rows_launch<1, 1>(dyb, x, batch, h, w, cout, r, cap, part, partb, &nsplit, s);
+  } else if (ob == 4)
     hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, dyb, x, batch, h, w, cout, chunk,
                        part, partb);
   else if (ob == 2)
@@ -755,12 +1140,9 @@ void wgrad_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, i
   else
     hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, dyb, x, batch, h, w, cout, chunk,
                        part, partb);
-  const size_t n = (size_t)cout * K;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, part,
-                     nsplit, n, dweight);
-  if (dbias)
-    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((cout + 63) / 64)), dim3(256), 0, s,
-                       partb, nsplit, (size_t)cout, dbias);
+  const size_t n = (size_t)cout * K, nb = dbias ? (size_t)cout : 0;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + nb + 63) / 64)), dim3(256), 0, s,
+                     part, nsplit, n, dweight, partb, nb, dbias);
 }
 
 }  // namespace
@@ -911,6 +1293,34 @@ extern "C" clb_status clb_nn_weights_bf16(const float *w32, int32_t cout, int32_
   return launched();
 }
 
+extern "C" clb_status clb_nn_weights_bf16_layers(const float *w32, int32_t nlayers,
+                                                 const int32_t *cout, const int32_t *cin,
+                                                 const int64_t *offset, clb_bf16 *w_fwd,
+                                                 clb_bf16 *w_bwd, void *stream) {
+  if (!w32 || !w_fwd || !w_bwd || !cout || !cin || !offset || nlayers < 1 ||
+      nlayers > CLB_NN_MAX_LAYERS)
+    return CLB_ERR_ARG;
+  WeightLayers L{};
+  L.n = nlayers;
+  int64_t blocks = 0;
+  for (int l = 0; l < nlayers; ++l) {
+    if (cout[l] <= 0 || cin[l] <= 0 || offset[l] < 0 ||
+        (int64_t)cout[l] * 9 * cin[l] >= (1LL << 31))
+      return CLB_ERR_ARG;
+    L.cout[l] = cout[l];
+    L.cin[l] = cin[l];
+    L.offset[l] = offset[l];
+    L.block0[l] = (int)blocks;
+    blocks += ((int64_t)cout[l] * 9 * cin[l] + 255) / 256;
+    if (blocks >= (1LL << 31)) return CLB_ERR_ARG;
+  }
+  L.block0[nlayers] = (int)blocks;
+  hipLaunchKernelGGL(weights_layers_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), w32, L, reinterpret_cast<bf16 *>(w_fwd),
+                     reinterpret_cast<bf16 *>(w_bwd));
+  return launched();
+}
+
 extern "C" clb_status clb_nn_pool2(const clb_bf16 *x, int32_t batch, int32_t h, int32_t w,
                                    int32_t c, clb_bf16 *y, void *stream) {
   if (!x || !y || !dims_ok(batch, h, w) || h % 2 || w % 2 || c <= 0) return CLB_ERR_ARG;
@@ -1030,7 +1440,7 @@ extern "C" clb_status clb_nn_mse(const float *out, int32_t ldo, const float *tar
       bytes < sizeof(double) * kMseBlocks)
     return CLB_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const unsigned nb = (unsigned)std::min<size_t>(kMseBlocks, blocks_for((size_t)npix * ldo));
+  const unsigned nb = (unsigned)std::min<size_t>(kMseBlocks, blocks_for((size_t)npix));
   hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, s, out, ldo, target, nch, (size_t)npix,
                      reinterpret_cast<bf16 *>(dout), static_cast<double *>(workspace));
   hipLaunchKernelGGL(mse_finalize_kernel, dim3(1), dim3(256), 0, s,

@@ -28,7 +28,7 @@ NN_EXPORTS = (
     "clb_nn_concat", "clb_nn_split", "clb_nn_act_grad", "clb_nn_mse_workspace_bytes",
     "clb_nn_mse", "clb_nn_adamw", "clb_nn_features", "clb_nn_gather",
     "clb_nn_wgrad_static_max_bytes", "clb_nn_conv3x3_wgrad_static", "clb_nn_conv3x3_cat",
-    "clb_nn_conv3x3_split", "clb_nn_conv3x3_wgrad_cat",
+    "clb_nn_conv3x3_split", "clb_nn_conv3x3_wgrad_cat", "clb_nn_weights_bf16_layers",
 )
 
 _ready = False
@@ -51,6 +51,7 @@ def lib():
             "clb_nn_conv3x3_wgrad_cat": [vp, vp, i32, i32, vp, i32, i32, i32, i32, i32, vp, vp,
                                          vp, C.c_size_t, vp],
             "clb_nn_weights_bf16": [vp, i32, i32, vp, vp, vp],
+            "clb_nn_weights_bf16_layers": [vp, i32, vp, vp, vp, vp, vp, vp],
             "clb_nn_pool2": [vp, i32, i32, i32, i32, vp, vp],
             "clb_nn_pool2_grad": [vp, i32, i32, i32, i32, vp, vp],
             "clb_nn_up2": [vp, i32, i32, i32, i32, vp, vp],
@@ -164,9 +165,15 @@ class UNet:
         self.g = torch.zeros(n, **f32)
         self.m = torch.zeros(n, **f32)
         self.v = torch.zeros(n, **f32)
-        self.wf = [torch.empty(o * 9 * c, dtype=torch.bfloat16, device=self.device)
-                   for o, c in self.convs]
-        self.wb = [torch.empty_like(w) for w in self.wf]
+        # bfloat16 copies of the weights (forward and input-gradient layouts)
+        # at the parameters' offsets, refreshed in one launch
+        self.wf_flat = torch.zeros(n, dtype=torch.bfloat16, device=self.device)
+        self.wb_flat = torch.zeros(n, dtype=torch.bfloat16, device=self.device)
+        self.wf = [self.wf_flat[w0:b0] for w0, b0 in self.offsets]
+        self.wb = [self.wb_flat[w0:b0] for w0, b0 in self.offsets]
+        self._layer_tab = (np.array([o for o, _ in self.convs], dtype=np.int32),
+                           np.array([c for _, c in self.convs], dtype=np.int32),
+                           np.array([w0 for w0, _ in self.offsets], dtype=np.int64))
         self.t = 0
         self.set_params(self.init_params(seed))
         self._shape = None
@@ -202,10 +209,11 @@ class UNet:
                 for (o, c), (w0, b0) in zip(self.convs, self.offsets)]
 
     def _refresh_bf16(self):
-        s = C.c_void_p(self.stream.cuda_stream)
-        for k, ((o, c), (w0, _)) in enumerate(zip(self.convs, self.offsets)):
-            call("clb_nn_weights_bf16", C.c_void_p(self.p.data_ptr() + 4 * w0), o, c,
-                 ptr(self.wf[k]), ptr(self.wb[k]), s)
+        co, ci, off = self._layer_tab
+        call("clb_nn_weights_bf16_layers", ptr(self.p), len(self.convs),
+             co.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+             off.ctypes.data_as(C.c_void_p), ptr(self.wf_flat), ptr(self.wb_flat),
+             C.c_void_p(self.stream.cuda_stream))
 
     # --------------------------------------------------------------- buffers
     def _buffers(self, batch, h, w):

@@ -6,6 +6,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from oracle import params as oparams
@@ -167,6 +168,12 @@ def test_network_calls_validate_arguments_on_the_host():
     assert lib.clb_nn_conv3x3_wgrad(a16, a16, 2, 16, 16, 16, 32, a16, None, a16, n.value - 4,
                                     None) == B.ERR_ARG  # workspace too small
     assert lib.clb_set_state_device(None, 0, a16, 16, 1.0, 0.0) == B.ERR_ARG
+    co, ci = np.array([16, 0], dtype=np.int32), np.array([16, 16], dtype=np.int32)
+    off = np.array([0, 4096], dtype=np.int64)
+    tab = [t.ctypes.data_as(vp) for t in (co, ci, off)]
+    assert lib.clb_nn_weights_bf16_layers(a16, 0, *tab, a16, a16, None) == B.ERR_ARG
+    assert lib.clb_nn_weights_bf16_layers(a16, 65, *tab, a16, a16, None) == B.ERR_ARG
+    assert lib.clb_nn_weights_bf16_layers(a16, 2, *tab, a16, a16, None) == B.ERR_ARG  # cout 0
 
 
 def test_bgk_derivation_uses_one_rate_per_lattice():

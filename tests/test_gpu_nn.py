@@ -81,11 +81,14 @@ def check_bf16(got, ref, what, frac=1e-3, bound=None):
         assert np.all(np.abs(got - ref)[~sel] <= 2.0 ** -7 * np.abs(ref[~sel]) + bound[~sel])
 
 
-# The last shape has over 1024 tiles of 64 pixels: the convolution takes its
-# pixel-tiled path there (the others split the reduction over the waves), with
-# a ragged last tile and a partial column tile.
+# (batch, h, w, cin, cout).  (1, 255, 259, 32, 48) has over 1024 tiles of 64
+# pixels: the convolution takes its pixel-tiled path there (the small shapes
+# split the reduction over the waves), with a ragged last tile and a partial
+# column tile.  The last two stage bands of whole rows in LDS (at least 256
+# bands), the second of them with a partial column tile; the weight gradient
+# runs over bands of rows wherever the width is a multiple of 8.
 CONV_SHAPES = [(2, 9, 13, 16, 16), (1, 5, 7, 48, 80), (2, 8, 8, 384, 128), (3, 16, 16, 16, 32),
-               (1, 255, 259, 32, 48)]
+               (1, 255, 259, 32, 48), (4, 128, 128, 16, 16), (16, 64, 64, 32, 48)]
 
 
 @pytest.mark.parametrize("shape", CONV_SHAPES)
@@ -153,6 +156,44 @@ def test_conv3x3_input_and_weight_gradients(nn, shape):
     nn.call("clb_nn_conv3x3_wgrad", nn.ptr(ddy), nn.ptr(tx), Bn, H, W, ci, co,
             nn.ptr(gw2), None, nn.ptr(ws), nb.value, None)
     assert torch.equal(gw, gw2)
+
+
+def test_weights_bf16_layers_matches_per_layer_calls(nn):
+    """One launch for the layers of a flat parameter array gives the bits of
+    the per-layer conversion and leaves the elements between layers alone."""
+    import torch
+    r = rng(19)
+    layers = [(16, 16), (32, 48), (16, 272)]  # (cout, cin)
+    offs, n = [], 0
+    for o, c in layers:
+        offs.append(n)
+        n += o * 9 * c + o + 32  # weights, a bias and a gap
+    w32 = dev_f32(r.standard_normal(n).astype(np.float32))
+    sentinel = torch.full((n,), 7.0, dtype=torch.bfloat16, device="cuda")
+    wf, wb = sentinel.clone(), sentinel.clone()
+    co = np.array([o for o, _ in layers], dtype=np.int32)
+    ci = np.array([c for _, c in layers], dtype=np.int32)
+    off = np.array(offs, dtype=np.int64)
+    nn.call("clb_nn_weights_bf16_layers", nn.ptr(w32), len(layers), co.ctypes.data_as(C.c_void_p),
+            ci.ctypes.data_as(C.c_void_p), off.ctypes.data_as(C.c_void_p), nn.ptr(wf), nn.ptr(wb),
+            None)
+    torch.cuda.synchronize()
+    covered = torch.zeros(n, dtype=torch.bool, device="cuda")
+    for (o, c), w0 in zip(layers, offs):
+        m = o * 9 * c
+        rf, rb = empty(m), empty(m)
+        nn.call("clb_nn_weights_bf16", C.c_void_p(w32.data_ptr() + 4 * w0), o, c, nn.ptr(rf),
+                nn.ptr(rb), None)
+        assert torch.equal(wf[w0:w0 + m].view(torch.int16), rf.view(torch.int16))
+        assert torch.equal(wb[w0:w0 + m].view(torch.int16), rb.view(torch.int16))
+        covered[w0:w0 + m] = True
+    assert torch.equal(wf[~covered], sentinel[~covered])
+    assert torch.equal(wb[~covered], sentinel[~covered])
+    bad = np.array([0], dtype=np.int32)
+    assert nn.lib().clb_nn_weights_bf16_layers(nn.ptr(w32), 1, bad.ctypes.data_as(C.c_void_p),
+                                               ci.ctypes.data_as(C.c_void_p),
+                                               off.ctypes.data_as(C.c_void_p), nn.ptr(wf),
+                                               nn.ptr(wb), None) != 0
 
 
 def test_elementwise_layers(nn):
@@ -284,8 +325,11 @@ def test_unet_loss_and_gradients_match_oracle(nn):
 # Decoder-level shapes (batch, h, w, ca, cb, cout): the deep tensor a at half
 # resolution (ca channels), the skip tensor b at full resolution.  The second
 # has over 1024 tiles of 64 pixels (pixel-tiled path with a ragged last tile);
-# the first splits the reduction over the waves.
-CAT_SHAPES = [(2, 8, 12, 32, 16, 16), (2, 96, 64, 32, 32, 32), (1, 16, 16, 128, 64, 64)]
+# the first splits the reduction over the waves; the last stages bands of
+# whole rows in LDS (the level-0 decoder convolution of the warm-start
+# network at batch 4).
+CAT_SHAPES = [(2, 8, 12, 32, 16, 16), (2, 96, 64, 32, 32, 32), (1, 16, 16, 128, 64, 64),
+              (4, 128, 128, 32, 16, 16)]
 
 
 @pytest.mark.parametrize("shape", CAT_SHAPES)
