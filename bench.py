@@ -167,7 +167,7 @@ def warmstart_bench(args):
         print(*a, file=sys.stderr, flush=True)
 
     max_steps = args.max_steps if args.max_steps != 10_000_000 else 3_000_000
-    r = W.evaluate(sur, draws, tol=1e-9, check_every=5000, max_steps=max_steps, log=log)
+    r = W.evaluate(sur, draws, tol=WS_TOL, check_every=5000, max_steps=max_steps, log=log)
     summ = warmstart_summary(r, draws, max_steps)
     out = {
         "metric": "time-to-steady-state (Nu err<=1e-4): plain vs learned warm start",
@@ -177,12 +177,21 @@ def warmstart_bench(args):
         "n_gpus": 1, "data": "synthetic", "dtype": "f64 arithmetic, f32 storage; bf16 network",
         "config": {"workload": "%d held-out porous cavities 128x128, Ra 1e3..1e7, Da 1e-5..1e-1, "
                                "Pr {0.71,1,7}, sigma 0.8..1.2, random porosity maps (seed 1)"
-                               % count, "tol": 1e-9, "check_every": 5000},
+                               % count, "tol": WS_TOL, "check_every": 5000},
         "training": {k: meta[k] for k in ("train", "epochs", "train_s", "datagen_s")
                      if k in meta},
     }
     out.update(summ)
     print(json.dumps(out), flush=True)
+
+
+# Round residual at which the warm-start comparisons stop a run.  The
+# reference steady Nusselt number is the final value of the run from rest; at
+# 1e-9 a run whose slowest thermal mode decays slowly can stop with its
+# Nusselt number still about 1e-4 from steady (the per-step change is then
+# below the tolerance), so two runs of one cavity may disagree by more than
+# the 1e-4 the comparison resolves.  At 1e-10 they agree within 6e-5.
+WS_TOL = 1e-10
 
 
 def warmstart_summary(r, draws, max_steps):
@@ -229,7 +238,7 @@ def warmstart_summary(r, draws, max_steps):
 def warmstart_leg(count=24, max_steps=2_000_000):
     """The bounded time-to-steady-state leg of the default line: the first
     `count` held-out cavities (128^2, seed 1, the batched sweep's parameter
-    ranges) run to a round residual of 1e-9 from rest and from the trained
+    ranges) run to a round residual of 1e-10 (WS_TOL) from rest and from the trained
     network's prediction."""
     from paper_2110_05943_amd import inputs
     from paper_2110_05943_amd import warmstart as W
@@ -243,7 +252,7 @@ def warmstart_leg(count=24, max_steps=2_000_000):
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
-    r = W.evaluate(sur, draws, tol=1e-9, check_every=5000, max_steps=max_steps, log=log)
+    r = W.evaluate(sur, draws, tol=WS_TOL, check_every=5000, max_steps=max_steps, log=log)
     out = {"metric": "time-to-steady-state (Nu err<=1e-4) plain vs learned",
            "workload": "%d held-out porous cavities 128x128, Ra 1e3..1e7, Da 1e-5..1e-1, "
                        "Pr {0.71,1,7}, sigma 0.8..1.2, random porosity maps (seed 1)" % count}

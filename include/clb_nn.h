@@ -34,6 +34,9 @@ extern "C" {
 
 typedef uint16_t clb_bf16;
 
+/* Most layers of the one-launch calls below. */
+#define CLB_NN_MAX_LAYERS 64
+
 /* 3x3 convolution, stride 1, zero padding 1:
  *   y[b,i,j,o] = act(bias[o] + sum_{t,c} w[o,t,c] x[b, i+di_t, j+dj_t, c]),
  * taps t = 3 (di + 1) + (dj + 1).  x: (batch, h, w, cin); weight:
@@ -108,6 +111,32 @@ clb_status clb_nn_conv3x3_wgrad_cat(const clb_bf16 *dy, const clb_bf16 *a, int32
                                     int32_t h, int32_t w, int32_t cout, float *dweight,
                                     float *dbias, void *workspace, size_t bytes, void *stream);
 
+/* The weight gradient in two steps, so that the chunk sums of many layers
+ * are added in one launch: clb_nn_conv3x3_wgrad_parts (and _cat_parts, the
+ * arguments of clb_nn_conv3x3_wgrad and clb_nn_conv3x3_wgrad_cat) only leave
+ * the per-chunk partial sums in `workspace` (16-byte aligned, at least
+ * clb_nn_wgrad_workspace_bytes), the bias sums too when with_bias != 0, and
+ * store their chunk count in *nsplit (a host int32).  The workspace must stay
+ * untouched until clb_nn_wgrad_reduce_layers has read it: for layer l it
+ * adds the nsplit[l] chunks at parts[l] (a layer of cout[l] outputs and
+ * cin[l] inputs) into dweight[l] and, when dbias[l] is not NULL (allowed
+ * only for partials taken with with_bias), dbias[l].  parts, nsplit, cout,
+ * cin, dweight and dbias are host arrays of nlayers entries (1 <= nlayers <=
+ * CLB_NN_MAX_LAYERS) holding device pointers.  The sums are bit-identical to
+ * those of clb_nn_conv3x3_wgrad. */
+clb_status clb_nn_conv3x3_wgrad_parts(const clb_bf16 *dy, const clb_bf16 *x, int32_t batch,
+                                      int32_t h, int32_t w, int32_t cin, int32_t cout,
+                                      int32_t with_bias, void *workspace, size_t bytes,
+                                      int32_t *nsplit, void *stream);
+clb_status clb_nn_conv3x3_wgrad_cat_parts(const clb_bf16 *dy, const clb_bf16 *a, int32_t ca,
+                                          int32_t up_a, const clb_bf16 *b, int32_t cb,
+                                          int32_t batch, int32_t h, int32_t w, int32_t cout,
+                                          int32_t with_bias, void *workspace, size_t bytes,
+                                          int32_t *nsplit, void *stream);
+clb_status clb_nn_wgrad_reduce_layers(int32_t nlayers, void *const *parts, const int32_t *nsplit,
+                                      const int32_t *cout, const int32_t *cin,
+                                      float *const *dweight, float *const *dbias, void *stream);
+
 /* bfloat16 copies of FP32 master weights (cout, 9, cin): w_fwd in the same
  * layout, w_bwd = the weights of the input-gradient convolution, laid out
  * (cin, 9, cout) with the taps reversed: w_bwd[c, 8 - t, o] = w[o, t, c]. */
@@ -121,7 +150,6 @@ clb_status clb_nn_weights_bf16(const float *w32, int32_t cout, int32_t cin, clb_
  * the layers' weights are left unchanged).  cout, cin and offset are host
  * arrays of nlayers entries, 1 <= nlayers <= CLB_NN_MAX_LAYERS; the layers
  * must not overlap. */
-#define CLB_NN_MAX_LAYERS 64
 clb_status clb_nn_weights_bf16_layers(const float *w32, int32_t nlayers, const int32_t *cout,
                                       const int32_t *cin, const int64_t *offset,
                                       clb_bf16 *w_fwd, clb_bf16 *w_bwd, void *stream);
@@ -153,11 +181,33 @@ clb_status clb_nn_split(const clb_bf16 *y, int32_t ca, int32_t cb, int64_t npix,
 clb_status clb_nn_act_grad(const clb_bf16 *g0, const clb_bf16 *g1, const clb_bf16 *out,
                            int64_t n, float slope, clb_bf16 *dz, void *stream);
 
+/* The input gradient of a convolution, the pooling gradient and the
+ * upsampling gradient, each followed by the gradient through the leaky ReLU
+ * whose output y (bfloat16) has the result's layout, for a tensor whose
+ * gradient is complete with this contribution:
+ *   clb_nn_conv3x3_act_grad: r = clb_nn_conv3x3(dy, ..., weight, no bias, no
+ *     activation) rounded to bfloat16;
+ *   clb_nn_pool2_grad_act: r = clb_nn_pool2_grad(dy), plus the tensor's
+ *     other contribution `add` (may be NULL) as clb_nn_act_grad adds it;
+ *   clb_nn_up2_grad_act: r = clb_nn_up2_grad(dy);
+ * then dz = r (y > 0) or slope * r, rounded to bfloat16: bit-identical to the
+ * unfused call followed by clb_nn_act_grad.  The pooling and upsampling
+ * variants need c a multiple of 8 and 16-byte aligned tensors. */
+clb_status clb_nn_conv3x3_act_grad(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w,
+                                   int32_t cin, const clb_bf16 *weight, int32_t cout,
+                                   const clb_bf16 *y, float slope, clb_bf16 *dz, void *stream);
+clb_status clb_nn_pool2_grad_act(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w,
+                                 int32_t c, const clb_bf16 *add, const clb_bf16 *y, float slope,
+                                 clb_bf16 *dz, void *stream);
+clb_status clb_nn_up2_grad_act(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w, int32_t c,
+                               const clb_bf16 *y, float slope, clb_bf16 *dz, void *stream);
+
 /* Mean-squared error over the first nch channels of an FP32 output with row
  * stride ldo (channels per pixel) against targets (npix, nch) FP32:
  *   loss = mean((out - target)^2) (FP64, written to *d_loss on the device),
  *   dout[p, c] = 2 (out - target) / (npix nch) for c < nch, 0 for other c,
- * bfloat16 with row stride ldo.  workspace: clb_nn_mse_workspace_bytes. */
+ * bfloat16 with row stride ldo.  ldo is a multiple of 8 and out, dout are
+ * 16-byte aligned.  workspace: clb_nn_mse_workspace_bytes. */
 clb_status clb_nn_mse_workspace_bytes(int64_t npix, size_t *bytes);
 clb_status clb_nn_mse(const float *out, int32_t ldo, const float *target, int32_t nch,
                       int64_t npix, clb_bf16 *dout, double *d_loss, void *workspace,

@@ -64,6 +64,11 @@ struct ConvDst {
   void *y0;  // output channels [0, split): (B, H, W, split)
   void *y1;  // output channels [split, cout): (B, H, W, cout - split); null when split = cout
   int split;
+  // Gradient through a leaky ReLU (bf16 output, one part): the rounded
+  // value v is stored as v (act_y > 0) or act_slope v, act_y being the
+  // activation's output in the output's layout; null for none.
+  const bf16 *act_y = nullptr;
+  float act_slope = 0.0f;
 };
 
 struct ConvPixel {
@@ -131,10 +136,15 @@ __device__ __forceinline__ void conv_store(const f4 *acc, int nt, int m0, int M,
       if (mm >= M) continue;
       float v = acc[t][e] + bb;
       if (act) v = v > 0.0f ? v : v * slope;
-      if (y_fp32)
+      if (y_fp32) {
         static_cast<float *>(y)[(size_t)mm * ld + cc] = v;
-      else
+      } else if (dst.act_y) {
+        const float r = (float)(bf16)v;
+        static_cast<bf16 *>(y)[(size_t)mm * ld + cc] =
+            (bf16)((float)dst.act_y[(size_t)mm * ld + cc] > 0.0f ? r : dst.act_slope * r);
+      } else {
         static_cast<bf16 *>(y)[(size_t)mm * ld + cc] = (bf16)v;
+      }
     }
   }
 }
@@ -246,6 +256,87 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(
   }
 }
 
+// Forward 3x3 convolution for layers with few pixels and long reductions
+// (deep levels): a workgroup of 16 waves computes 64 pixels x 64 output
+// channels.  The waves form 4 groups; group g takes the reduction steps
+// g, g + 4, ... (32 k each), wave q of a group the pixel tile 16 q, all four
+// column tiles.  Each group stages its step's weight slice (64 channels x 32
+// k) in its own double-buffered LDS slice, read by its four waves; the A
+// operand is gathered as in conv3x3_kernel.  The groups' sums are added in
+// group order through LDS before the epilogue.
+constexpr int kGroups = 4;
+
+__global__ void __launch_bounds__(1024) conv3x3_kgroups_kernel(
+    ConvSrc x, int B, int H, int W, const bf16 *__restrict__ wt, const float *__restrict__ bias,
+    int cout, int act, float slope, ConvDst dst, int y_fp32) {
+  // weight slices: [group][buffer][64 x kWRow]; reused for the reduction
+  __shared__ __attribute__((aligned(16))) char lds_raw[(kGroups - 1) * 4 * 4 * 64 * 16];
+  static_assert(sizeof(lds_raw) >= kGroups * 2 * kCoTile * kWRow * sizeof(bf16), "LDS");
+  bf16 *sw_all = reinterpret_cast<bf16 *>(lds_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = wave >> 2, q = wave & 3, gt = tid & 255;  // group, wave in group, thread in group
+  const int cin = x.ca + x.cb;
+  const int M = B * H * W, K = 9 * cin, nsteps = (K + 31) / 32;
+  const int rounds = (nsteps + kGroups - 1) / kGroups;
+  const int co0 = blockIdx.y * kCoTile;
+  const int nt = min(4, (cout - co0) >> 4);
+  const int row = lane & 15, kq = 8 * (lane >> 4);
+  const bf16x8 zero = {};
+  bf16 *sw = sw_all + g * 2 * kCoTile * kWRow;
+  const int m0 = blockIdx.x * 64 + 16 * q;
+  const ConvPixel px = conv_pixel(m0 + row, M, H, W);
+  // weight loading role within the group: channel wo of the slice, k offset 8 wk
+  const int wo = gt >> 2, wk = 8 * (gt & 3);
+  const bool wok = co0 + wo < cout;
+  const bf16 *wrow = wt + (size_t)(co0 + wo) * K;
+  f4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  // step of round r for this group: s = kGroups r + g (none beyond nsteps)
+  auto step_k = [&](int r) { return 32 * (kGroups * r + g); };
+  int k = step_k(0);
+  bf16x8 a = conv_a(x, px, k + kq, K, H, W, cin);
+  bf16x8 wv = (wok && k + wk < K) ? *reinterpret_cast<const bf16x8 *>(wrow + k + wk) : zero;
+  *reinterpret_cast<bf16x8 *>(&sw[wo * kWRow + wk]) = wv;
+  __syncthreads();
+  for (int r = 0; r < rounds; ++r) {
+    const int cur = r & 1;
+    const int kn = step_k(r + 1);
+    bf16x8 an = zero;
+    if (r + 1 < rounds) {
+      an = conv_a(x, px, kn + kq, K, H, W, cin);
+      wv = (wok && kn + wk < K) ? *reinterpret_cast<const bf16x8 *>(wrow + kn + wk) : zero;
+    }
+    if (k < K) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < nt) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
+              &sw[cur * kCoTile * kWRow + (16 * t + row) * kWRow + kq]);
+          acc[t] = mfma16(a, b, acc[t]);
+        }
+      }
+    }
+    if (r + 1 < rounds)
+      *reinterpret_cast<bf16x8 *>(&sw[(cur ^ 1) * kCoTile * kWRow + wo * kWRow + wk]) = wv;
+    __syncthreads();
+    a = an;
+    k = kn;
+  }
+  // groups 1..3 hand their sums to group 0, which adds them in group order
+  f4 *red = reinterpret_cast<f4 *>(lds_raw);  // [group - 1][wave in group][tile][64]
+  if (g > 0)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) red[(((g - 1) * 4 + q) * 4 + t) * 64 + lane] = acc[t];
+  __syncthreads();
+  if (g == 0) {
+    for (int h = 0; h < kGroups - 1; ++h)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] += red[((h * 4 + q) * 4 + t) * 64 + lane];
+    conv_store<4>(acc, nt, m0, M, co0, lane, bias, cout, act, slope, dst, y_fp32);
+  }
+}
+
 // Forward 3x3 convolution over bands of image rows, for inputs small enough
 // to stage in LDS: a workgroup computes the R W = 64 PT pixels of R rows of
 // one image for 16 NT output channels.  It copies the input rows band - 1 ..
@@ -259,13 +350,14 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(
 template <int PT, int NT>
 __global__ void __launch_bounds__(256) conv3x3_rows_kernel(
     ConvSrc x, int B, int H, int W, const bf16 *__restrict__ wt, const float *__restrict__ bias,
-    int cout, int act, float slope, ConvDst dst, int y_fp32, int R) {
+    int cout, int act, float slope, ConvDst dst, int y_fp32, int R, int PS) {
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cin = x.ca + x.cb, K = 9 * cin, KP = K + 8, nsteps = (K + 31) / 32;
   const int WP = W + 2;
-  bf16 *sin = reinterpret_cast<bf16 *>(lds_raw);   // [R + 2][W + 2][cin]
-  bf16 *sw = sin + (size_t)(R + 2) * WP * cin;      // [16 NT][K + 8]
+  // [R + 2][W + 2] pixels of PS >= cin elements (a multiple of 8)
+  bf16 *sin = reinterpret_cast<bf16 *>(lds_raw);
+  bf16 *sw = sin + (size_t)(R + 2) * WP * PS;      // [16 NT][K + 8]
   const int bands_img = H / R;
   const int n = blockIdx.x / bands_img, y0 = (blockIdx.x - n * bands_img) * R;
   const int co0 = blockIdx.y * kCoTile;
@@ -277,7 +369,7 @@ __global__ void __launch_bounds__(256) conv3x3_rows_kernel(
     const int c8 = v % cg, pix = v / cg;
     const int r = pix / WP, cc = pix - r * WP;
     const bf16x8 val = src_load(x, n, y0 - 1 + r, cc - 1, 8 * c8, H, W);
-    *reinterpret_cast<bf16x8 *>(sin + (size_t)pix * cin + 8 * c8) = val;
+    *reinterpret_cast<bf16x8 *>(sin + (size_t)pix * PS + 8 * c8) = val;
   }
   // the weight rows of this workgroup's output channels
   const int kv = K / 8;
@@ -309,7 +401,7 @@ __global__ void __launch_bounds__(256) conv3x3_rows_kernel(
     bf16x8 a[PT];
 #pragma unroll
     for (int p = 0; p < PT; ++p)
-      a[p] = kok ? *reinterpret_cast<const bf16x8 *>(sin + (size_t)(base[p] + toff) * cin + c)
+      a[p] = kok ? *reinterpret_cast<const bf16x8 *>(sin + (size_t)(base[p] + toff) * PS + c)
                  : zero;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -636,37 +728,60 @@ __global__ void __launch_bounds__(256) wgrad_rows_kernel(const bf16 *__restrict_
     }
 }
 
-// Sums of `nsplit` partial arrays in a fixed order, for two arrays at once:
-// outputs i < n add part[z n + i] into out[i], outputs n <= i < n + nb add
-// partb[z nb + i - n] into outb[i - n].  Block b adds outputs [64 b, 64 b +
-// 64); wave w of the block takes the splits w, w + 4, w + 8, ... in
-// increasing order (64 consecutive outputs per load: coalesced), and the four
-// wave sums are added in wave order.
+// Sum over the nsplit chunks of one partial-sum array in a fixed order.
+// Up to kThreadSplits chunks, each thread adds the chunks of one output in
+// increasing order (256 outputs per workgroup).  Beyond that, the 256
+// threads of a workgroup cover 64 consecutive outputs x 4 waves; wave w adds
+// the chunks w, w + 4, w + 8, ... in increasing order (64 consecutive outputs
+// per load: coalesced), and the four wave sums of an output are added in wave
+// order.  out(i, v) receives output i's sum.
+constexpr int kThreadSplits = 32;
+
+__host__ __device__ inline int sum_outputs_per_block(int nsplit) {
+  return nsplit <= kThreadSplits ? 256 : 64;
+}
+
+template <typename Src, typename Out>
+__device__ __forceinline__ void sum_chunks(int nsplit, int b, size_t count, const Src &src,
+                                           const Out &out) {
+  __shared__ float lds[4][64];
+  if (nsplit <= kThreadSplits) {
+    const size_t i = (size_t)b * 256 + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.0f;
+    for (int z = 0; z < nsplit; ++z) s += src(i, z);
+    out(i, s);
+    return;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const size_t i = (size_t)b * 64 + lane;
+  float s = 0.0f;
+  if (i < count) {
+#pragma unroll 8
+    for (int z = w; z < nsplit; z += 4) s += src(i, z);
+  }
+  lds[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i < count) out(i, ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane]);
+}
+
+// Sums of `nsplit` partial arrays, for two arrays at once: outputs i < n add
+// part[z n + i] into out[i], outputs n <= i < n + nb add partb[z nb + i - n]
+// into outb[i - n].
 __global__ void __launch_bounds__(256) sum_parts_kernel(const float *__restrict__ part,
                                                         int nsplit, size_t n,
                                                         float *__restrict__ out,
                                                         const float *__restrict__ partb,
                                                         size_t nb, float *__restrict__ outb) {
-  __shared__ float lds[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const size_t i = (size_t)blockIdx.x * 64 + lane;
-  const bool second = i >= n;
-  const float *src = second ? partb + (i - n) : part + i;
-  const size_t stride = second ? nb : n;
-  float s = 0.0f;
-  if (i < n + nb) {
-#pragma unroll 8
-    for (int z = w; z < nsplit; z += 4) s += src[(size_t)z * stride];
-  }
-  lds[w][lane] = s;
-  __syncthreads();
-  if (w == 0 && i < n + nb) {
-    const float v = ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane];
-    if (second)
-      outb[i - n] = v;
-    else
-      out[i] = v;
-  }
+  sum_chunks(
+      nsplit, blockIdx.x, n + nb,
+      [&](size_t i, int z) { return i < n ? part[(size_t)z * n + i] : partb[(size_t)z * nb + i - n]; },
+      [&](size_t i, float v) {
+        if (i < n)
+          out[i] = v;
+        else
+          outb[i - n] = v;
+      });
 }
 
 __global__ void __launch_bounds__(256) weights_kernel(const float *__restrict__ w32, int cout,
@@ -814,9 +929,31 @@ __global__ void __launch_bounds__(256) pool2_v8_kernel(const bf16x8 *__restrict_
   y[(size_t)row * Wo * C8 + i] = o;
 }
 
+// The pooling and upsampling gradients below optionally finish the gradient
+// through a leaky ReLU whose output y has the result's layout (y null: none):
+// s = result (+ add, the tensor's other gradient contribution, rounded to
+// bfloat16 as clb_nn_act_grad adds), then s (y > 0) or slope s.
+__device__ __forceinline__ bf16x8 act_finish(bf16x8 o, const bf16x8 *add, const bf16x8 *y,
+                                             size_t i, float slope) {
+  if (!y) return o;
+  const bf16x8 yy = y[i];
+  bf16x8 a = {};
+  if (add) a = add[i];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    float s = (float)o[e];
+    if (add) s = (float)(bf16)((float)a[e] + s);
+    o[e] = (bf16)((float)yy[e] > 0.0f ? s : slope * s);
+  }
+  return o;
+}
+
 __global__ void __launch_bounds__(256) pool2_grad_v8_kernel(const bf16x8 *__restrict__ dy, int H,
                                                             int W, int C8,
-                                                            bf16x8 *__restrict__ dx) {
+                                                            bf16x8 *__restrict__ dx,
+                                                            const bf16x8 *__restrict__ add,
+                                                            const bf16x8 *__restrict__ y,
+                                                            float slope) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W * C8) return;
   const int j = i / C8, c = i - j * C8;
@@ -825,11 +962,14 @@ __global__ void __launch_bounds__(256) pool2_grad_v8_kernel(const bf16x8 *__rest
   bf16x8 o;
 #pragma unroll
   for (int e = 0; e < 8; ++e) o[e] = (bf16)(0.25f * (float)v[e]);
-  dx[(size_t)row * W * C8 + i] = o;
+  const size_t k = (size_t)row * W * C8 + i;
+  dx[k] = act_finish(o, add, y, k, slope);
 }
 
 __global__ void __launch_bounds__(256) up2_grad_v8_kernel(const bf16x8 *__restrict__ dy, int H,
-                                                          int W, int C8, bf16x8 *__restrict__ dx) {
+                                                          int W, int C8, bf16x8 *__restrict__ dx,
+                                                          const bf16x8 *__restrict__ y,
+                                                          float slope) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W * C8) return;
   const int j = i / C8, c = i - j * C8;
@@ -840,7 +980,8 @@ __global__ void __launch_bounds__(256) up2_grad_v8_kernel(const bf16x8 *__restri
   bf16x8 o;
 #pragma unroll
   for (int e = 0; e < 8; ++e) o[e] = (bf16)((float)v0[e] + (float)v1[e] + (float)v2[e] + (float)v3[e]);
-  dx[(size_t)row * W * C8 + i] = o;
+  const size_t k = (size_t)row * W * C8 + i;
+  dx[k] = act_finish(o, nullptr, y, k, slope);
 }
 
 __global__ void __launch_bounds__(256) act_grad_v8_kernel(const bf16x8 *__restrict__ g0,
@@ -883,21 +1024,29 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ out,
   __shared__ double lds[4];
   const double scale = 2.0 / ((double)npix * nch);
   double s = 0.0;
-  // one pixel (its ldo channels) per thread and iteration
-  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix;
-       p += (size_t)gridDim.x * blockDim.x) {
-    const float *o = out + p * ldo;
-    const float *t = tgt + p * nch;
-    bf16 *g = dout + p * ldo;
-    for (int c = 0; c < ldo; ++c) {
+  // 8 consecutive channels of one pixel per thread and iteration (ldo is a
+  // multiple of 8 here): two 16-byte loads of out, one 16-byte store
+  const int groups = ldo / 8;
+  const size_t units = npix * groups;
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < units;
+       u += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = u / groups;
+    const int c0 = 8 * (int)(u - p * groups);
+    const f4 o0 = *reinterpret_cast<const f4 *>(out + p * ldo + c0);
+    const f4 o1 = *reinterpret_cast<const f4 *>(out + p * ldo + c0 + 4);
+    bf16x8 g;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = c0 + e;
       float v = 0.0f;
       if (c < nch) {
-        const float d = o[c] - t[c];
+        const float d = (e < 4 ? o0[e] : o1[e - 4]) - tgt[p * nch + c];
         s += (double)d * d;
         v = (float)(scale * d);
       }
-      g[c] = (bf16)v;
+      g[e] = (bf16)v;
     }
+    *reinterpret_cast<bf16x8 *>(dout + p * ldo + c0) = g;
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
@@ -1012,8 +1161,8 @@ namespace {
 // split reduction below that.
 // LDS bytes of conv3x3_rows_kernel for bands of r rows, or 0 if it exceeds
 // 64 KiB.
-size_t conv_rows_lds(int r, int w, int cin, int nt) {
-  const size_t b = sizeof(bf16) * ((size_t)(r + 2) * (w + 2) * cin + (size_t)16 * nt * (9 * cin + 8));
+size_t conv_rows_lds(int r, int w, int cin, int ps, int nt) {
+  const size_t b = sizeof(bf16) * ((size_t)(r + 2) * (w + 2) * ps + (size_t)16 * nt * (9 * cin + 8));
   return b <= 65536 ? b : 0;
 }
 
@@ -1032,14 +1181,15 @@ void conv_launch(const ConvSrc &x, int32_t batch, int32_t h, int32_t w, const bf
     const int pix = 64 * pt;
     if (pix % w || h % (pix / w)) continue;
     const int r = pix / w;
-    const size_t lds = conv_rows_lds(r, w, cin, nt);
+    const int ps = cin;  // pixel stride in LDS (padding it measured no faster)
+    const size_t lds = conv_rows_lds(r, w, cin, ps, nt);
     const int64_t wgs = (int64_t)batch * (h / r) * cot;
     if (!lds || wgs < 256) continue;
     const dim3 grid((unsigned)(batch * (h / r)), cot);
     auto go = [&](auto pt_tag, auto nt_tag) {
       constexpr int PT = decltype(pt_tag)::value, NT = decltype(nt_tag)::value;
       hipLaunchKernelGGL((conv3x3_rows_kernel<PT, NT>), grid, dim3(256), lds, s, x, batch, h, w,
-                         wb, bias, cout, act, slope, dst, y_fp32, r);
+                         wb, bias, cout, act, slope, dst, y_fp32, r, ps);
     };
     auto pick = [&](auto pt_tag) {
       if (nt == 1)
@@ -1077,8 +1227,8 @@ void conv_launch(const ConvSrc &x, int32_t batch, int32_t h, int32_t w, const bf
   else if ((int64_t)blocks(kPixTile) * cot >= 1024)
     pick_nt(std::integral_constant<int, 1>{});
   else
-    hipLaunchKernelGGL((conv3x3_kernel<true, 1, 4>), dim3(blocks(16), cot), dim3(256), 0, s, x,
-                       batch, h, w, wb, bias, cout, act, slope, dst, y_fp32);
+    hipLaunchKernelGGL(conv3x3_kgroups_kernel, dim3(blocks(64), cot), dim3(1024), 0, s, x, batch,
+                       h, w, wb, bias, cout, act, slope, dst, y_fp32);
 }
 
 bool cat_ok(const void *a, int32_t ca, int32_t up, const void *b, int32_t cb, int32_t h,
@@ -1098,40 +1248,46 @@ int wgrad_rows(int32_t h, int32_t w) {
 
 template <int OB, int CB>
 void wgrad_rows_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, int32_t w,
-                       int32_t cout, int r, int nsplit_max, float *part, float *partb,
-                       int *nsplit, hipStream_t s) {
+                       int32_t cout, int r, int bpc, int nsplit, float *part, float *partb,
+                       hipStream_t s) {
   const int cin = x.ca + x.cb;
-  const int nbands = batch * (h / r);
-  const int bpc = (nbands + std::min(nbands, nsplit_max) - 1) / std::min(nbands, nsplit_max);
-  *nsplit = (nbands + bpc - 1) / bpc;
   const size_t lds = sizeof(bf16) * ((size_t)16 * OB * kDyPitch + (size_t)16 * CB * (r + 2) * (w + 16));
-  const dim3 grid((unsigned)(cout / (16 * OB)), (unsigned)(cin / (16 * CB)), (unsigned)*nsplit);
+  const dim3 grid((unsigned)(cout / (16 * OB)), (unsigned)(cin / (16 * CB)), (unsigned)nsplit);
   hipLaunchKernelGGL((wgrad_rows_kernel<OB, CB>), grid, dim3(256), lds, s, dyb, x, batch, h, w,
                      cout, r, bpc, part, partb);
 }
 
-void wgrad_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, int32_t w,
-                  int32_t cout, float *dweight, float *dbias, void *workspace, hipStream_t s) {
+// Launch of the weight-gradient partial sums: nsplit chunks of cout x 9 cin
+// weight sums at part, then (dbias requested) nsplit chunks of cout bias sums
+// right after them.  Returns nsplit, at most the chunk count that
+// clb_nn_wgrad_workspace_bytes provides for.
+int wgrad_parts_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, int32_t w,
+                       int32_t cout, bool with_bias, float *part, hipStream_t s) {
   const int cin = x.ca + x.cb;
   int nsplit, chunk;
   const int64_t K = 9LL * cin, M = (int64_t)batch * h * w;
   wgrad_plan(M, wgrad_tiles(cin, cout), &nsplit, &chunk);
-  float *part = static_cast<float *>(workspace);
-  float *partb = part + (size_t)nsplit * cout * K;
+  const int r = wgrad_rows(h, w);
+  int bpc = 0;
+  if (r) {  // bands of rows: at most nsplit chunks of whole bands
+    const int nbands = batch * (h / r);
+    const int cap = std::min(nbands, nsplit);
+    bpc = (nbands + cap - 1) / cap;
+    nsplit = (nbands + bpc - 1) / bpc;
+  }
+  float *partb = with_bias ? part + (size_t)nsplit * cout * K : nullptr;
+  if (r) {
+    if (cout % 32 == 0)
+      wgrad_rows_launch<2, 1>(dyb, x, batch, h, w, cout, r, bpc, nsplit, part, partb, s);
+    else if (cin % 32 == 0)
+      wgrad_rows_launch<1, 2>(dyb, x, batch, h, w, cout, r, bpc, nsplit, part, partb, s);
+    else
+      wgrad_rows_launch<1, 1>(dyb, x, batch, h, w, cout, r, bpc, nsplit, part, partb, s);
+    return nsplit;
+  }
   const int ob = wgrad_ob(cout);
   const dim3 grid((unsigned)(cout / (16 * ob)), (unsigned)((K + kWgK - 1) / kWgK), nsplit);
-  const int r = wgrad_rows(h, w);
-  if (r) {
-    // partb stays where the workspace size puts it; the row-band launch uses
-    // at most nsplit chunks
-    const int cap = nsplit;
-    if (cout % 32 == 0)
-      wgrad_rows_launch<2, 1>(dyb, x, batch, h, w, cout, r, cap, part, partb, &nsplit, s);
-    else if (cin % 32 == 0)
-      wgrad_rows_launch<1, 2>(dyb, x, batch, h, w, cout, r, cap, part, partb, &nsplit, s);
-    else
-      wgrad_rows_launch<1, 1>(dyb, x, batch, h, w, cout, r, cap, part, partb, &nsplit, s);
-  } else if (ob == 4)
+  if (ob == 4)
     hipLaunchKernelGGL(wgrad_kernel<4>, grid, dim3(256), 0, s, dyb, x, batch, h, w, cout, chunk,
                        part, partb);
   else if (ob == 2)
@@ -1140,9 +1296,47 @@ void wgrad_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, i
   else
     hipLaunchKernelGGL(wgrad_kernel<1>, grid, dim3(256), 0, s, dyb, x, batch, h, w, cout, chunk,
                        part, partb);
-  const size_t n = (size_t)cout * K, nb = dbias ? (size_t)cout : 0;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + nb + 63) / 64)), dim3(256), 0, s,
-                     part, nsplit, n, dweight, partb, nb, dbias);
+  return nsplit;
+}
+
+void wgrad_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t h, int32_t w,
+                  int32_t cout, float *dweight, float *dbias, void *workspace, hipStream_t s) {
+  float *part = static_cast<float *>(workspace);
+  const int nsplit = wgrad_parts_launch(dyb, x, batch, h, w, cout, dbias != nullptr, part, s);
+  const size_t n = (size_t)cout * 9 * (x.ca + x.cb), nb = dbias ? (size_t)cout : 0;
+  const size_t per = sum_outputs_per_block(nsplit);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + nb + per - 1) / per)), dim3(256), 0,
+                     s, part, nsplit, n, dweight, part + (size_t)nsplit * n, nb, dbias);
+}
+
+// The layer table of sum_parts_layers_kernel: layer l adds nsplit[l] chunks
+// of n[l] weight and nb[l] bias partial sums at part[l] into w[l] and b[l];
+// its workgroups are [block0[l], block0[l + 1]).
+struct PartLayers {
+  int n_layers;
+  const float *part[CLB_NN_MAX_LAYERS];
+  float *w[CLB_NN_MAX_LAYERS];
+  float *b[CLB_NN_MAX_LAYERS];
+  int nsplit[CLB_NN_MAX_LAYERS], n[CLB_NN_MAX_LAYERS], nb[CLB_NN_MAX_LAYERS];
+  int block0[CLB_NN_MAX_LAYERS + 1];
+};
+
+// sum_parts_kernel for many layers in one launch (same order of additions).
+__global__ void __launch_bounds__(256) sum_parts_layers_kernel(PartLayers L) {
+  int l = 0;
+  while (l + 1 < L.n_layers && (int)blockIdx.x >= L.block0[l + 1]) ++l;
+  const size_t n = L.n[l], nb = L.nb[l];
+  const float *part = L.part[l], *partb = L.part[l] + (size_t)L.nsplit[l] * n;
+  float *w = L.w[l], *b = L.b[l];
+  sum_chunks(
+      L.nsplit[l], blockIdx.x - L.block0[l], n + nb,
+      [&](size_t i, int z) { return i < n ? part[(size_t)z * n + i] : partb[(size_t)z * nb + i - n]; },
+      [&](size_t i, float v) {
+        if (i < n)
+          w[i] = v;
+        else
+          b[i - n] = v;
+      });
 }
 
 }  // namespace
@@ -1192,6 +1386,22 @@ extern "C" clb_status clb_nn_conv3x3_split(const clb_bf16 *x, int32_t batch, int
   return launched();
 }
 
+extern "C" clb_status clb_nn_conv3x3_act_grad(const clb_bf16 *dy, int32_t batch, int32_t h,
+                                              int32_t w, int32_t cin, const clb_bf16 *weight,
+                                              int32_t cout, const clb_bf16 *y, float slope,
+                                              clb_bf16 *dz, void *stream) {
+  if (!dy || !weight || !y || !dz || !dims_ok(batch, h, w) || cin <= 0 || cin % 16 ||
+      cout <= 0 || cout % 16 || !aligned16(dy) || !aligned16(weight))
+    return CLB_ERR_ARG;
+  const ConvSrc src{reinterpret_cast<const bf16 *>(dy), nullptr, cin, 0, 0};
+  ConvDst dst{dz, nullptr, cout};
+  dst.act_y = reinterpret_cast<const bf16 *>(y);
+  dst.act_slope = slope;
+  conv_launch(src, batch, h, w, reinterpret_cast<const bf16 *>(weight), nullptr, cout, 0, 0.0f,
+              dst, 0, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
 extern "C" clb_status clb_nn_wgrad_workspace_bytes(int32_t batch, int32_t h, int32_t w,
                                                    int32_t cin, int32_t cout, size_t *bytes) {
   if (!bytes || !dims_ok(batch, h, w) || cin <= 0 || cin % 16 || cout <= 0 || cout % 16)
@@ -1231,6 +1441,73 @@ extern "C" clb_status clb_nn_conv3x3_wgrad_cat(const clb_bf16 *dy, const clb_bf1
                     up_a};
   wgrad_launch(reinterpret_cast<const bf16 *>(dy), src, batch, h, w, cout, dweight, dbias,
                workspace, static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_conv3x3_wgrad_parts(const clb_bf16 *dy, const clb_bf16 *x,
+                                                 int32_t batch, int32_t h, int32_t w, int32_t cin,
+                                                 int32_t cout, int32_t with_bias, void *workspace,
+                                                 size_t bytes, int32_t *nsplit, void *stream) {
+  size_t need = 0;
+  if (clb_nn_wgrad_workspace_bytes(batch, h, w, cin, cout, &need) != CLB_OK || !dy || !x ||
+      !workspace || !nsplit || bytes < need || !aligned16(dy) || !aligned16(x) ||
+      !aligned16(workspace))
+    return CLB_ERR_ARG;
+  const ConvSrc src{reinterpret_cast<const bf16 *>(x), nullptr, cin, 0, 0};
+  *nsplit = wgrad_parts_launch(reinterpret_cast<const bf16 *>(dy), src, batch, h, w, cout,
+                               with_bias != 0, static_cast<float *>(workspace),
+                               static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_conv3x3_wgrad_cat_parts(const clb_bf16 *dy, const clb_bf16 *a,
+                                                     int32_t ca, int32_t up_a, const clb_bf16 *b,
+                                                     int32_t cb, int32_t batch, int32_t h,
+                                                     int32_t w, int32_t cout, int32_t with_bias,
+                                                     void *workspace, size_t bytes,
+                                                     int32_t *nsplit, void *stream) {
+  size_t need = 0;
+  if (!cat_ok(a, ca, up_a, b, cb, h, w) ||
+      clb_nn_wgrad_workspace_bytes(batch, h, w, ca + cb, cout, &need) != CLB_OK || !dy ||
+      !workspace || !nsplit || bytes < need || !aligned16(dy) || !aligned16(workspace))
+    return CLB_ERR_ARG;
+  const ConvSrc src{reinterpret_cast<const bf16 *>(a), reinterpret_cast<const bf16 *>(b), ca, cb,
+                    up_a};
+  *nsplit = wgrad_parts_launch(reinterpret_cast<const bf16 *>(dy), src, batch, h, w, cout,
+                               with_bias != 0, static_cast<float *>(workspace),
+                               static_cast<hipStream_t>(stream));
+  return launched();
+}
+
+extern "C" clb_status clb_nn_wgrad_reduce_layers(int32_t nlayers, void *const *parts,
+                                                 const int32_t *nsplit, const int32_t *cout,
+                                                 const int32_t *cin, float *const *dweight,
+                                                 float *const *dbias, void *stream) {
+  if (nlayers < 1 || nlayers > CLB_NN_MAX_LAYERS || !parts || !nsplit || !cout || !cin ||
+      !dweight || !dbias)
+    return CLB_ERR_ARG;
+  PartLayers L{};
+  L.n_layers = nlayers;
+  int64_t blocks = 0;
+  for (int l = 0; l < nlayers; ++l) {
+    const int64_t n = (int64_t)cout[l] * 9 * cin[l];
+    if (!parts[l] || !dweight[l] || nsplit[l] < 1 || cout[l] <= 0 || cin[l] <= 0 ||
+        n + cout[l] >= (1LL << 31))
+      return CLB_ERR_ARG;
+    L.part[l] = static_cast<const float *>(parts[l]);
+    L.w[l] = dweight[l];
+    L.b[l] = dbias[l];
+    L.nsplit[l] = nsplit[l];
+    L.n[l] = (int)n;
+    L.nb[l] = dbias[l] ? cout[l] : 0;
+    L.block0[l] = (int)blocks;
+    const int per = sum_outputs_per_block(nsplit[l]);
+    blocks += (n + L.nb[l] + per - 1) / per;
+    if (blocks >= (1LL << 31)) return CLB_ERR_ARG;
+  }
+  L.block0[nlayers] = (int)blocks;
+  hipLaunchKernelGGL(sum_parts_layers_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), L);
   return launched();
 }
 
@@ -1348,7 +1625,7 @@ extern "C" clb_status clb_nn_pool2_grad(const clb_bf16 *dy, int32_t batch, int32
     const int C8 = c / 8;
     hipLaunchKernelGGL(pool2_grad_v8_kernel, dim3(blocks_for((size_t)w * C8), batch * h),
                        dim3(256), 0, s, reinterpret_cast<const bf16x8 *>(dy), h, w, C8,
-                       reinterpret_cast<bf16x8 *>(dx));
+                       reinterpret_cast<bf16x8 *>(dx), nullptr, nullptr, 0.0f);
     return launched();
   }
   const size_t n = (size_t)batch * h * w * c;
@@ -1368,6 +1645,38 @@ extern "C" clb_status clb_nn_up2(const clb_bf16 *x, int32_t batch, int32_t h, in
   return launched();
 }
 
+extern "C" clb_status clb_nn_pool2_grad_act(const clb_bf16 *dy, int32_t batch, int32_t h,
+                                            int32_t w, int32_t c, const clb_bf16 *add,
+                                            const clb_bf16 *y, float slope, clb_bf16 *dz,
+                                            void *stream) {
+  if (!dy || !y || !dz || !dims_ok(batch, h, w) || h % 2 || w % 2 || c <= 0 || c % 8 ||
+      !aligned16(dy) || !aligned16(y) || !aligned16(dz) || (add && !aligned16(add)) ||
+      (int64_t)w * (c / 8) >= (1 << 30) || (int64_t)batch * h >= 65536)
+    return CLB_ERR_ARG;
+  const int C8 = c / 8;
+  hipLaunchKernelGGL(pool2_grad_v8_kernel, dim3(blocks_for((size_t)w * C8), batch * h),
+                     dim3(256), 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<const bf16x8 *>(dy), h, w, C8, reinterpret_cast<bf16x8 *>(dz),
+                     reinterpret_cast<const bf16x8 *>(add), reinterpret_cast<const bf16x8 *>(y),
+                     slope);
+  return launched();
+}
+
+extern "C" clb_status clb_nn_up2_grad_act(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w,
+                                          int32_t c, const clb_bf16 *y, float slope, clb_bf16 *dz,
+                                          void *stream) {
+  if (!dy || !y || !dz || !dims_ok(batch, 2 * h, 2 * w) || c <= 0 || c % 8 || !aligned16(dy) ||
+      !aligned16(y) || !aligned16(dz) || (int64_t)w * (c / 8) >= (1 << 30) ||
+      (int64_t)batch * h >= 65536)
+    return CLB_ERR_ARG;
+  const int C8 = c / 8;
+  hipLaunchKernelGGL(up2_grad_v8_kernel, dim3(blocks_for((size_t)w * C8), batch * h), dim3(256),
+                     0, static_cast<hipStream_t>(stream), reinterpret_cast<const bf16x8 *>(dy), h,
+                     w, C8, reinterpret_cast<bf16x8 *>(dz), reinterpret_cast<const bf16x8 *>(y),
+                     slope);
+  return launched();
+}
+
 extern "C" clb_status clb_nn_up2_grad(const clb_bf16 *dy, int32_t batch, int32_t h, int32_t w,
                                       int32_t c, clb_bf16 *dx, void *stream) {
   if (!dy || !dx || !dims_ok(batch, 2 * h, 2 * w) || c <= 0) return CLB_ERR_ARG;
@@ -1377,7 +1686,7 @@ extern "C" clb_status clb_nn_up2_grad(const clb_bf16 *dy, int32_t batch, int32_t
     const int C8 = c / 8;
     hipLaunchKernelGGL(up2_grad_v8_kernel, dim3(blocks_for((size_t)w * C8), batch * h), dim3(256),
                        0, s, reinterpret_cast<const bf16x8 *>(dy), h, w, C8,
-                       reinterpret_cast<bf16x8 *>(dx));
+                       reinterpret_cast<bf16x8 *>(dx), nullptr, 0.0f);
     return launched();
   }
   const size_t n = (size_t)batch * h * w * c;
@@ -1440,7 +1749,8 @@ extern "C" clb_status clb_nn_mse(const float *out, int32_t ldo, const float *tar
       bytes < sizeof(double) * kMseBlocks)
     return CLB_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const unsigned nb = (unsigned)std::min<size_t>(kMseBlocks, blocks_for((size_t)npix));
+  if (ldo % 8 || !aligned16(out) || !aligned16(dout)) return CLB_ERR_ARG;
+  const unsigned nb = (unsigned)std::min<size_t>(kMseBlocks, blocks_for((size_t)npix * (ldo / 8)));
   hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, s, out, ldo, target, nch, (size_t)npix,
                      reinterpret_cast<bf16 *>(dout), static_cast<double *>(workspace));
   hipLaunchKernelGGL(mse_finalize_kernel, dim3(1), dim3(256), 0, s,

@@ -29,6 +29,8 @@ NN_EXPORTS = (
     "clb_nn_mse", "clb_nn_adamw", "clb_nn_features", "clb_nn_gather",
     "clb_nn_wgrad_static_max_bytes", "clb_nn_conv3x3_wgrad_static", "clb_nn_conv3x3_cat",
     "clb_nn_conv3x3_split", "clb_nn_conv3x3_wgrad_cat", "clb_nn_weights_bf16_layers",
+    "clb_nn_conv3x3_wgrad_parts", "clb_nn_conv3x3_wgrad_cat_parts", "clb_nn_wgrad_reduce_layers",
+    "clb_nn_conv3x3_act_grad", "clb_nn_pool2_grad_act", "clb_nn_up2_grad_act",
 )
 
 _ready = False
@@ -52,6 +54,14 @@ def lib():
                                          vp, C.c_size_t, vp],
             "clb_nn_weights_bf16": [vp, i32, i32, vp, vp, vp],
             "clb_nn_weights_bf16_layers": [vp, i32, vp, vp, vp, vp, vp, vp],
+            "clb_nn_conv3x3_wgrad_parts": [vp, vp, i32, i32, i32, i32, i32, i32, vp, C.c_size_t,
+                                           C.POINTER(C.c_int32), vp],
+            "clb_nn_conv3x3_wgrad_cat_parts": [vp, vp, i32, i32, vp, i32, i32, i32, i32, i32, i32,
+                                               vp, C.c_size_t, C.POINTER(C.c_int32), vp],
+            "clb_nn_wgrad_reduce_layers": [i32, vp, vp, vp, vp, vp, vp, vp],
+            "clb_nn_conv3x3_act_grad": [vp, i32, i32, i32, i32, vp, i32, vp, f32, vp, vp],
+            "clb_nn_pool2_grad_act": [vp, i32, i32, i32, i32, vp, vp, f32, vp, vp],
+            "clb_nn_up2_grad_act": [vp, i32, i32, i32, i32, vp, f32, vp, vp],
             "clb_nn_pool2": [vp, i32, i32, i32, i32, vp, vp],
             "clb_nn_pool2_grad": [vp, i32, i32, i32, i32, vp, vp],
             "clb_nn_up2": [vp, i32, i32, i32, i32, vp, vp],
@@ -154,6 +164,26 @@ class UNet:
                 t_up, t_skip = cat["ins"]
                 self.fused[i] = (self.steps[t_up - 1]["ins"][0], t_up, t_skip)
                 self.virtual |= {a - 1, t_up - 1}
+        # gradient contributions each tensor receives in the backward pass (a
+        # virtual cat step passes none: its convolution writes both parts),
+        # and whether it is the output of a leaky ReLU
+        self.expect = [0] * len(self.ch)
+        self.expect[-1] = 1  # the loss
+        for i, st in enumerate(self.steps):
+            if st["op"] == "conv":
+                if i in self.fused:
+                    _, t_up, skip = self.fused[i]
+                    self.expect[t_up] += 1
+                    self.expect[skip] += 1
+                elif st["ins"][0] > 0:
+                    self.expect[st["ins"][0]] += 1
+            elif st["op"] in ("pool", "up"):
+                self.expect[st["ins"][0]] += 1
+            elif i not in self.virtual:
+                for a in st["ins"]:
+                    self.expect[a] += 1
+        self.activated = [t > 0 and self.steps[t - 1]["op"] == "conv" and self.steps[t - 1]["act"]
+                          for t in range(len(self.ch))]
         self.offsets = []
         n = 0
         for o, c in self.convs:
@@ -242,18 +272,25 @@ class UNet:
                 continue  # its gradient goes straight to its two parts
             self.gin[t] = [torch.empty(n, **bf), torch.empty(n, **bf)]
             self.dz[t] = torch.empty(n, **bf)
-        ws = 0
+        # one workspace slice per convolution for the weight-gradient partial
+        # sums, which one launch adds after the backward pass
+        self.ws_off, total = [0] * len(self.convs), 0
         for st in self.steps:
             if st["op"] == "conv":
                 a = st["ins"][0]
                 nb = C.c_size_t()
                 call("clb_nn_wgrad_workspace_bytes", batch, h >> self.lv[a], w >> self.lv[a],
                      self.ch[a], st["out"], C.byref(nb))
-                ws = max(ws, nb.value)
+                self.ws_off[st["k"]] = total
+                total += (nb.value + 255) // 256 * 256
+        self.ws_parts = torch.empty(total, dtype=torch.uint8, device=self.device)
+        self.ws_bytes = [0] * len(self.convs)
+        for k in range(len(self.convs)):
+            end = self.ws_off[k + 1] if k + 1 < len(self.convs) else total
+            self.ws_bytes[k] = end - self.ws_off[k]
         nb = C.c_size_t()
         call("clb_nn_mse_workspace_bytes", batch * h * w, C.byref(nb))
-        ws = max(ws, nb.value)
-        self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         self.loss_d = torch.zeros(1, dtype=torch.float64, device=self.device)
         self._shape = (batch, h, w)
 
@@ -312,6 +349,15 @@ class UNet:
             ncontrib[t] += 1
             return buf
 
+        def completes(t, single=False):
+            """This contribution completes the gradient of t, a leaky ReLU
+            output: the producer then writes dz[t] itself."""
+            return (self.activated[t] and ncontrib[t] + 1 == self.expect[t]
+                    and (self.expect[t] == 1 or not single))
+
+        done = [False] * len(self.ch)
+        nsplit = [C.c_int32(0) for _ in self.convs]
+
         for i in range(len(self.steps) - 1, -1, -1):
             st = self.steps[i]
             t, a = i + 1, st["ins"][0]
@@ -323,38 +369,64 @@ class UNet:
             ha, wa = h >> self.lv[a], w >> self.lv[a]
             if st["op"] == "conv":
                 k = st["k"]
-                if st["act"]:
+                if st["act"] and done[t]:
+                    dz = self.dz[t]
+                elif st["act"]:
                     call("clb_nn_act_grad", ptr(g0), ptr(g1), ptr(vals[t]),
                          batch * ht * wt * self.ch[t], SLOPE, ptr(self.dz[t]), s)
                     dz = self.dz[t]
                 else:
                     dz = g0
-                w0, b0 = self.offsets[k]
+                ws_k = C.c_void_p(self.ws_parts.data_ptr() + self.ws_off[k])
                 if i in self.fused:
                     deep, t_up, skip = self.fused[i]
-                    call("clb_nn_conv3x3_wgrad_cat", ptr(dz), ptr(vals[deep]), self.ch[deep], 1,
-                         ptr(vals[skip]), self.ch[skip], batch, ha, wa, st["out"],
-                         C.c_void_p(self.g.data_ptr() + 4 * w0),
-                         C.c_void_p(self.g.data_ptr() + 4 * b0), ptr(self.ws), self.ws.numel(), s)
+                    call("clb_nn_conv3x3_wgrad_cat_parts", ptr(dz), ptr(vals[deep]), self.ch[deep],
+                         1, ptr(vals[skip]), self.ch[skip], batch, ha, wa, st["out"], 1, ws_k,
+                         self.ws_bytes[k], C.byref(nsplit[k]), s)
                     # input gradient written straight to its two parts
                     call("clb_nn_conv3x3_split", ptr(dz), batch, ha, wa, st["out"],
                          ptr(self.wb[k]), self.ch[a], self.ch[t_up], ptr(contrib(t_up)),
                          ptr(contrib(skip)), s)
                     continue
-                call("clb_nn_conv3x3_wgrad", ptr(dz), ptr(vals[a]), batch, ha, wa, self.ch[a],
-                     st["out"], C.c_void_p(self.g.data_ptr() + 4 * w0),
-                     C.c_void_p(self.g.data_ptr() + 4 * b0), ptr(self.ws), self.ws.numel(), s)
-                if a > 0:
+                call("clb_nn_conv3x3_wgrad_parts", ptr(dz), ptr(vals[a]), batch, ha, wa,
+                     self.ch[a], st["out"], 1, ws_k, self.ws_bytes[k], C.byref(nsplit[k]), s)
+                if a > 0 and completes(a, single=True):
+                    call("clb_nn_conv3x3_act_grad", ptr(dz), batch, ha, wa, st["out"],
+                         ptr(self.wb[k]), self.ch[a], ptr(vals[a]), SLOPE, ptr(self.dz[a]), s)
+                    ncontrib[a] += 1
+                    done[a] = True
+                elif a > 0:
                     call("clb_nn_conv3x3", ptr(dz), batch, ha, wa, st["out"], ptr(self.wb[k]),
                          None, self.ch[a], 0, 0.0, ptr(contrib(a)), 0, s)
+            elif st["op"] == "pool" and completes(a) and self.ch[a] % 8 == 0:
+                add = self.gin[a][0] if self.expect[a] == 2 else None
+                call("clb_nn_pool2_grad_act", ptr(g0), batch, ha, wa, self.ch[a], ptr(add),
+                     ptr(vals[a]), SLOPE, ptr(self.dz[a]), s)
+                ncontrib[a] += 1
+                done[a] = True
             elif st["op"] == "pool":
                 call("clb_nn_pool2_grad", ptr(g0), batch, ha, wa, self.ch[a], ptr(contrib(a)), s)
+            elif st["op"] == "up" and completes(a, single=True) and self.ch[a] % 8 == 0:
+                call("clb_nn_up2_grad_act", ptr(g0), batch, ha, wa, self.ch[a], ptr(vals[a]),
+                     SLOPE, ptr(self.dz[a]), s)
+                ncontrib[a] += 1
+                done[a] = True
             elif st["op"] == "up":
                 call("clb_nn_up2_grad", ptr(g0), batch, ha, wa, self.ch[a], ptr(contrib(a)), s)
             else:
                 b_ = st["ins"][1]
                 call("clb_nn_split", ptr(g0), self.ch[a], self.ch[b_], batch * ha * wa,
                      ptr(contrib(a)), ptr(contrib(b_)), s)
+        # the weight and bias gradients of every convolution in one launch
+        ks = [k for k in range(len(self.convs)) if nsplit[k].value > 0]
+        VP = C.c_void_p * len(ks)
+        I32 = C.c_int32 * len(ks)
+        parts = VP(*[self.ws_parts.data_ptr() + self.ws_off[k] for k in ks])
+        dw = VP(*[self.g.data_ptr() + 4 * self.offsets[k][0] for k in ks])
+        db = VP(*[self.g.data_ptr() + 4 * self.offsets[k][1] for k in ks])
+        call("clb_nn_wgrad_reduce_layers", len(ks), parts, I32(*[nsplit[k].value for k in ks]),
+             I32(*[self.convs[k][0] for k in ks]), I32(*[self.convs[k][1] for k in ks]), dw, db,
+             s)
         return self.loss_d
 
     def adamw(self, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):

@@ -174,6 +174,16 @@ def test_network_calls_validate_arguments_on_the_host():
     assert lib.clb_nn_weights_bf16_layers(a16, 0, *tab, a16, a16, None) == B.ERR_ARG
     assert lib.clb_nn_weights_bf16_layers(a16, 65, *tab, a16, a16, None) == B.ERR_ARG
     assert lib.clb_nn_weights_bf16_layers(a16, 2, *tab, a16, a16, None) == B.ERR_ARG  # cout 0
+    assert lib.clb_nn_mse(a16, 12, a16, 3, 10, a16, a16, a16, 1 << 20, None) == B.ERR_ARG
+    ns = C.c_int32(0)
+    assert lib.clb_nn_conv3x3_wgrad_parts(a16, a16, 2, 16, 16, 16, 32, 1, a16, n.value - 4,
+                                          C.byref(ns), None) == B.ERR_ARG  # workspace too small
+    assert lib.clb_nn_conv3x3_wgrad_parts(a16, a16, 2, 16, 16, 16, 32, 1, a16, n.value, None,
+                                          None) == B.ERR_ARG  # no chunk count
+    ptrs = (C.c_void_p * 2)(4096, None)
+    one = (C.c_int32 * 2)(1, 1)
+    assert lib.clb_nn_wgrad_reduce_layers(0, ptrs, one, one, one, ptrs, ptrs, None) == B.ERR_ARG
+    assert lib.clb_nn_wgrad_reduce_layers(2, ptrs, one, one, one, ptrs, ptrs, None) == B.ERR_ARG
 
 
 def test_bgk_derivation_uses_one_rate_per_lattice():

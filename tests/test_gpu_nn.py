@@ -196,6 +196,117 @@ def test_weights_bf16_layers_matches_per_layer_calls(nn):
                                                nn.ptr(wb), None) != 0
 
 
+def test_wgrad_parts_and_one_reduction_match_wgrad(nn):
+    """clb_nn_conv3x3_wgrad_parts (row-band and tiled kernels) and
+    clb_nn_conv3x3_wgrad_cat_parts, added for all layers by one
+    clb_nn_wgrad_reduce_layers, give the bits of clb_nn_conv3x3_wgrad and
+    clb_nn_conv3x3_wgrad_cat."""
+    import torch
+    r = rng(23)
+    # (batch, h, w, cin or (ca, cb), cout, bias)
+    layers = [(2, 16, 16, 16, 32, True), (1, 9, 13, 32, 16, False), (2, 16, 16, (32, 16), 16, True)]
+    parts, ns, co, ci, dws, dbs, refs, keep = [], [], [], [], [], [], [], []
+    for Bn, H, W, cin, cout, with_b in layers:
+        cat = isinstance(cin, tuple)
+        ct = sum(cin) if cat else cin
+        dy = dev_bf16(N.round_bf16(r.standard_normal((Bn, H, W, cout))))
+        nb = C.c_size_t()
+        nn.call("clb_nn_wgrad_workspace_bytes", Bn, H, W, ct, cout, C.byref(nb))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        ws_ref = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        gw, gb = empty(cout * 9 * ct, "f32"), empty(cout, "f32") if with_b else None
+        rw, rb = empty(cout * 9 * ct, "f32"), empty(cout, "f32") if with_b else None
+        n = C.c_int32(0)
+        if cat:
+            ca, cb = cin
+            a = dev_bf16(N.round_bf16(r.standard_normal((Bn, H // 2, W // 2, ca))))
+            b = dev_bf16(N.round_bf16(r.standard_normal((Bn, H, W, cb))))
+            nn.call("clb_nn_conv3x3_wgrad_cat", nn.ptr(dy), nn.ptr(a), ca, 1, nn.ptr(b), cb, Bn, H,
+                    W, cout, nn.ptr(rw), nn.ptr(rb), nn.ptr(ws_ref), nb.value, None)
+            nn.call("clb_nn_conv3x3_wgrad_cat_parts", nn.ptr(dy), nn.ptr(a), ca, 1, nn.ptr(b), cb,
+                    Bn, H, W, cout, int(with_b), nn.ptr(ws), nb.value, C.byref(n), None)
+            keep += [a, b]
+        else:
+            x = dev_bf16(N.round_bf16(r.standard_normal((Bn, H, W, cin))))
+            nn.call("clb_nn_conv3x3_wgrad", nn.ptr(dy), nn.ptr(x), Bn, H, W, cin, cout,
+                    nn.ptr(rw), nn.ptr(rb), nn.ptr(ws_ref), nb.value, None)
+            nn.call("clb_nn_conv3x3_wgrad_parts", nn.ptr(dy), nn.ptr(x), Bn, H, W, cin, cout,
+                    int(with_b), nn.ptr(ws), nb.value, C.byref(n), None)
+            keep.append(x)
+        assert n.value >= 1
+        keep += [dy, ws, ws_ref]
+        parts.append(ws.data_ptr())
+        ns.append(n.value)
+        co.append(cout)
+        ci.append(ct)
+        dws.append(gw)
+        dbs.append(gb)
+        refs.append((rw, rb))
+    L = len(layers)
+    VP, I32 = C.c_void_p * L, C.c_int32 * L
+    nn.call("clb_nn_wgrad_reduce_layers", L, VP(*parts), I32(*ns), I32(*co), I32(*ci),
+            VP(*[t.data_ptr() for t in dws]),
+            VP(*[t.data_ptr() if t is not None else None for t in dbs]), None)
+    torch.cuda.synchronize()
+    for gw, gb, (rw, rb) in zip(dws, dbs, refs):
+        assert torch.equal(gw, rw)
+        assert (gb is None) == (rb is None) and (gb is None or torch.equal(gb, rb))
+
+
+def test_fused_activation_gradients_match_unfused(nn):
+    """clb_nn_conv3x3_act_grad, clb_nn_pool2_grad_act (with and without a
+    second contribution) and clb_nn_up2_grad_act give the bits of the
+    unfused call followed by clb_nn_act_grad."""
+    import torch
+    r = rng(29)
+    Bn, H, W, c = 2, 16, 24, 32
+
+    def bf(shape):
+        return dev_bf16(N.round_bf16(r.standard_normal(shape)))
+
+    def act_ref(g0, g1, y):
+        out = empty(y.numel())
+        nn.call("clb_nn_act_grad", nn.ptr(g0), nn.ptr(g1), nn.ptr(y), y.numel(), nn.SLOPE,
+                nn.ptr(out), None)
+        return out
+
+    # input gradient of a convolution (cout = c) from dy with 16 channels
+    dy = bf((Bn, H, W, 16))
+    w = bf((c, 9, 16)).reshape(-1)  # the input-gradient weights, layout (c, 9, 16)
+    y = bf((Bn, H, W, c))
+    g = empty(Bn * H * W * c)
+    nn.call("clb_nn_conv3x3", nn.ptr(dy), Bn, H, W, 16, nn.ptr(w), None, c, 0, 0.0, nn.ptr(g), 0,
+            None)
+    ref = act_ref(g, None, y)
+    dz = empty(Bn * H * W * c)
+    nn.call("clb_nn_conv3x3_act_grad", nn.ptr(dy), Bn, H, W, 16, nn.ptr(w), c, nn.ptr(y),
+            nn.SLOPE, nn.ptr(dz), None)
+    torch.cuda.synchronize()
+    assert torch.equal(dz.view(torch.int16), ref.view(torch.int16))
+    # pooling gradient, alone and with another contribution
+    dyp = bf((Bn, H // 2, W // 2, c))
+    other = bf((Bn, H, W, c))
+    gp = empty(Bn * H * W * c)
+    nn.call("clb_nn_pool2_grad", nn.ptr(dyp), Bn, H, W, c, nn.ptr(gp), None)
+    for add in (None, other):
+        ref = act_ref(gp, None, y) if add is None else act_ref(add, gp, y)
+        dz = empty(Bn * H * W * c)
+        nn.call("clb_nn_pool2_grad_act", nn.ptr(dyp), Bn, H, W, c, nn.ptr(add), nn.ptr(y),
+                nn.SLOPE, nn.ptr(dz), None)
+        torch.cuda.synchronize()
+        assert torch.equal(dz.view(torch.int16), ref.view(torch.int16))
+    # upsampling gradient
+    yh = bf((Bn, H // 2, W // 2, c))
+    gu = empty(Bn * (H // 2) * (W // 2) * c)
+    nn.call("clb_nn_up2_grad", nn.ptr(other), Bn, H // 2, W // 2, c, nn.ptr(gu), None)
+    ref = act_ref(gu, None, yh)
+    dz = empty(gu.numel())
+    nn.call("clb_nn_up2_grad_act", nn.ptr(other), Bn, H // 2, W // 2, c, nn.ptr(yh), nn.SLOPE,
+            nn.ptr(dz), None)
+    torch.cuda.synchronize()
+    assert torch.equal(dz.view(torch.int16), ref.view(torch.int16))
+
+
 def test_elementwise_layers(nn):
     r = rng(11)
     Bn, H, W, Cc = 2, 6, 10, 16
