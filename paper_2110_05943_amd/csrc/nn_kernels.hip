@@ -539,10 +539,10 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
   }
 }
 
-// Weight gradient over bands of image rows (W a multiple of 8, at most 256):
+// Weight gradient over bands of image rows (W a multiple of 8, at most 512):
 // a workgroup owns 16 OB output channels x 16 CB input channels for all nine
-// taps and runs over bands of R rows of one image (P = R W pixels, R =
-// min(H, 256 / W)).  Per band it loads dy[band, o tile] and the input rows
+// taps and runs over bands of R rows of one image (P = R W <= 512 pixels, R
+// as large as 64 KB of LDS allows).  Per band it loads dy[band, o tile] and the input rows
 // band - 1 .. band + R of its channel tile; each thread takes blocks of 8
 // pixels x 8 channels (eight 16-byte loads), transposes them in registers
 // (v_perm) and stores 8 pixel-contiguous 16-byte rows to LDS.  Every tap then
@@ -552,7 +552,7 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const bf16 *__restrict__ dy,
 // sums in wave order at the end.  Partial sums per chunk of bands go to
 // `part` (bias partial sums, for the first channel tile, to `partb`), laid
 // out as for wgrad_kernel.
-constexpr int kRowPix = 256;             // pixels per band at most
+constexpr int kRowPix = 512;             // pixels per band at most
 constexpr int kDyPitch = kRowPix + 8;    // LDS row of dy^T in bf16
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
@@ -1237,13 +1237,27 @@ bool cat_ok(const void *a, int32_t ca, int32_t up, const void *b, int32_t cb, in
          (!up || (h % 2 == 0 && w % 2 == 0)) && aligned16(a) && aligned16(b);
 }
 
+// LDS bytes of wgrad_rows_kernel<OB, CB> for bands of r rows of width w.
+size_t wgrad_rows_lds(int ob, int cb, int r, int w) {
+  return sizeof(bf16) * ((size_t)16 * ob * kDyPitch + (size_t)16 * cb * (r + 2) * (w + 16));
+}
+
 // Rows per band of the row-band weight gradient, or 0 where it does not
-// apply (the width must be a multiple of 8 and at most 256, the bands must
-// tile the image height, and a band must hold whole 32-pixel steps).
-int wgrad_rows(int32_t h, int32_t w) {
+// apply: the width must be a multiple of 8 and at most kRowPix, the bands
+// (as tall as kRowPix pixels and 64 KB of LDS allow) must tile the image
+// height, and a band must hold whole 32-pixel steps.
+int wgrad_rows(int32_t h, int32_t w, int ob, int cb) {
   if (w % 8 || w > kRowPix) return 0;
-  const int r = std::min<int>(h, kRowPix / w);
-  return (h % r == 0 && (r * w) % 32 == 0) ? r : 0;
+  // 512-pixel bands for wide images (fewer halo rows), 256 below (more bands)
+  int r = std::min<int>(h, (w >= 128 ? kRowPix : kRowPix / 2) / w);
+  while (r > 1 && wgrad_rows_lds(ob, cb, r, w) > 65536) r /= 2;
+  return (wgrad_rows_lds(ob, cb, r, w) <= 65536 && h % r == 0 && (r * w) % 32 == 0) ? r : 0;
+}
+
+// Output x input channel blocks (of 16) of a row-band weight-gradient workgroup.
+void wgrad_rows_blocks(int cin, int cout, int *ob, int *cb) {
+  *ob = cout % 32 == 0 ? 2 : 1;
+  *cb = (*ob == 1 && cin % 32 == 0) ? 2 : 1;
 }
 
 template <int OB, int CB>
@@ -1251,7 +1265,7 @@ void wgrad_rows_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t
                        int32_t cout, int r, int bpc, int nsplit, float *part, float *partb,
                        hipStream_t s) {
   const int cin = x.ca + x.cb;
-  const size_t lds = sizeof(bf16) * ((size_t)16 * OB * kDyPitch + (size_t)16 * CB * (r + 2) * (w + 16));
+  const size_t lds = wgrad_rows_lds(OB, CB, r, w);
   const dim3 grid((unsigned)(cout / (16 * OB)), (unsigned)(cin / (16 * CB)), (unsigned)nsplit);
   hipLaunchKernelGGL((wgrad_rows_kernel<OB, CB>), grid, dim3(256), lds, s, dyb, x, batch, h, w,
                      cout, r, bpc, part, partb);
@@ -1267,7 +1281,9 @@ int wgrad_parts_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t
   int nsplit, chunk;
   const int64_t K = 9LL * cin, M = (int64_t)batch * h * w;
   wgrad_plan(M, wgrad_tiles(cin, cout), &nsplit, &chunk);
-  const int r = wgrad_rows(h, w);
+  int rob, rcb;
+  wgrad_rows_blocks(cin, cout, &rob, &rcb);
+  const int r = wgrad_rows(h, w, rob, rcb);
   int bpc = 0;
   if (r) {  // bands of rows: at most nsplit chunks of whole bands
     const int nbands = batch * (h / r);
@@ -1277,9 +1293,9 @@ int wgrad_parts_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t
   }
   float *partb = with_bias ? part + (size_t)nsplit * cout * K : nullptr;
   if (r) {
-    if (cout % 32 == 0)
+    if (rob == 2)
       wgrad_rows_launch<2, 1>(dyb, x, batch, h, w, cout, r, bpc, nsplit, part, partb, s);
-    else if (cin % 32 == 0)
+    else if (rcb == 2)
       wgrad_rows_launch<1, 2>(dyb, x, batch, h, w, cout, r, bpc, nsplit, part, partb, s);
     else
       wgrad_rows_launch<1, 1>(dyb, x, batch, h, w, cout, r, bpc, nsplit, part, partb, s);
