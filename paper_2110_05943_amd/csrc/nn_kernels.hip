@@ -1285,9 +1285,12 @@ int wgrad_parts_launch(const bf16 *dyb, const ConvSrc &x, int32_t batch, int32_t
   wgrad_rows_blocks(cin, cout, &rob, &rcb);
   const int r = wgrad_rows(h, w, rob, rcb);
   int bpc = 0;
-  if (r) {  // bands of rows: at most nsplit chunks of whole bands
+  if (r) {  // bands of rows: chunks of whole bands, about 768 workgroups (the
+            // workgroup tiles are larger than wgrad_kernel's, so fewer chunks,
+            // and fewer partial sums to add, fill the GPU)
     const int nbands = batch * (h / r);
-    const int cap = std::min(nbands, nsplit);
+    const int tiles = (cout / (16 * rob)) * (cin / (16 * rcb));
+    const int cap = std::min(std::min(nbands, nsplit), std::max(1, (768 + tiles - 1) / tiles));
     bpc = (nbands + cap - 1) / cap;
     nsplit = (nbands + bpc - 1) / bpc;
   }
