@@ -220,6 +220,15 @@ clb_status clb_nn_mse(const float *out, int32_t ldo, const float *target, int32_
 clb_status clb_nn_adamw(float *p, const float *g, float *m, float *v, int64_t n, float lr,
                         float b1, float b2, float eps, float wd, int32_t t, void *stream);
 
+/* clb_nn_adamw followed, in the same launch, by the bfloat16 copies of
+ * clb_nn_weights_bf16_layers for the updated parameters (same layer table;
+ * the offsets must increase and every layer lie within the n parameters). */
+clb_status clb_nn_adamw_layers(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                               float b1, float b2, float eps, float wd, int32_t t,
+                               int32_t nlayers, const int32_t *cout, const int32_t *cin,
+                               const int64_t *offset, clb_bf16 *w_fwd, clb_bf16 *w_bwd,
+                               void *stream);
+
 /* Network input for `batch` samples picked by idx (device int32, indices into
  * the sample arrays): channel 0 = (eps - 0.625) * 5 from the porosity maps
  * eps_all (samples, h, w) FP32; channels 1..ngroups = groups_all[s, k]

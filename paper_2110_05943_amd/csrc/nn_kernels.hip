@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(1024) conv3x3_kgroups_kernel(
 // lane's 8 k are 16 aligned bytes).  The GEMM is that of conv3x3_kernel
 // (rows = pixels, columns = output channels, k = tap x channel in steps of
 // 32); wave w takes the pixel tiles 16 (w + 4 p), p < PT.
-template <int PT, int NT>
+template <int PT, int NT, bool WLDS>
 __global__ void __launch_bounds__(256) conv3x3_rows_kernel(
     ConvSrc x, int B, int H, int W, const bf16 *__restrict__ wt, const float *__restrict__ bias,
     int cout, int act, float slope, ConvDst dst, int y_fp32, int R, int PS) {
@@ -371,13 +371,17 @@ __global__ void __launch_bounds__(256) conv3x3_rows_kernel(
     const bf16x8 val = src_load(x, n, y0 - 1 + r, cc - 1, 8 * c8, H, W);
     *reinterpret_cast<bf16x8 *>(sin + (size_t)pix * PS + 8 * c8) = val;
   }
-  // the weight rows of this workgroup's output channels
-  const int kv = K / 8;
-  for (int v = threadIdx.x; v < 16 * NT * kv; v += 256) {
-    const int o = v / kv, k8 = v - o * kv;
-    bf16x8 val = {};
-    if (o < 16 * nt) val = *reinterpret_cast<const bf16x8 *>(wt + (size_t)(co0 + o) * K + 8 * k8);
-    *reinterpret_cast<bf16x8 *>(sw + o * KP + 8 * k8) = val;
+  // the weight rows of this workgroup's output channels (WLDS; else they are
+  // read from global memory, which leaves LDS to the input band)
+  if constexpr (WLDS) {
+    const int kv = K / 8;
+    for (int v = threadIdx.x; v < 16 * NT * kv; v += 256) {
+      const int o = v / kv, k8 = v - o * kv;
+      bf16x8 val = {};
+      if (o < 16 * nt)
+        val = *reinterpret_cast<const bf16x8 *>(wt + (size_t)(co0 + o) * K + 8 * k8);
+      *reinterpret_cast<bf16x8 *>(sw + o * KP + 8 * k8) = val;
+    }
   }
   __syncthreads();
   f4 acc[PT][NT];
@@ -406,8 +410,10 @@ __global__ void __launch_bounds__(256) conv3x3_rows_kernel(
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (t < nt) {
-        const bf16x8 b = kok ? *reinterpret_cast<const bf16x8 *>(sw + (16 * t + row) * KP + k)
-                             : zero;
+        bf16x8 b = zero;
+        if (kok)
+          b = WLDS ? *reinterpret_cast<const bf16x8 *>(sw + (16 * t + row) * KP + k)
+                   : *reinterpret_cast<const bf16x8 *>(wt + (size_t)(co0 + 16 * t + row) * K + k);
 #pragma unroll
         for (int p = 0; p < PT; ++p) acc[p][t] = mfma16(a[p], b, acc[p][t]);
       }
@@ -1082,6 +1088,44 @@ __global__ void __launch_bounds__(256) adamw_kernel(float *__restrict__ p,
   p[i] = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
 }
 
+// AdamW (adamw_kernel) followed, for the elements that are convolution
+// weights of the layer table L (offsets ascending), by the two bfloat16
+// copies of weights_layers_kernel.
+__global__ void __launch_bounds__(256) adamw_layers_kernel(
+    float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+    float *__restrict__ v, size_t n, float lr, float b1, float b2, float eps, float wd, float c1,
+    float c2, WeightLayers L, bf16 *__restrict__ wf, bf16 *__restrict__ wb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / c1, vh = vi / c2;
+  const float pi = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+  p[i] = pi;
+  // the last layer that starts at or before i
+  int lo = 0, hi = L.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((size_t)L.offset[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const size_t base = (size_t)L.offset[lo];
+  if (i < base) return;
+  const int cout = L.cout[lo], cin = L.cin[lo];
+  const size_t j = i - base;
+  if (j >= (size_t)cout * 9 * cin) return;  // a bias or a gap
+  const int o = (int)(j / (9 * cin)), r = (int)(j - (size_t)o * 9 * cin), t = r / cin,
+            c = r - t * cin;
+  const bf16 b = (bf16)pi;
+  wf[i] = b;
+  wb[base + ((size_t)c * 9 + (8 - t)) * cout + o] = b;
+}
+
 __global__ void __launch_bounds__(256) features_kernel(const float *__restrict__ eps_all,
                                                        const float *__restrict__ groups,
                                                        int ngroups, const int32_t *__restrict__ idx,
@@ -1161,8 +1205,9 @@ namespace {
 // split reduction below that.
 // LDS bytes of conv3x3_rows_kernel for bands of r rows, or 0 if it exceeds
 // 64 KiB.
-size_t conv_rows_lds(int r, int w, int cin, int ps, int nt) {
-  const size_t b = sizeof(bf16) * ((size_t)(r + 2) * (w + 2) * ps + (size_t)16 * nt * (9 * cin + 8));
+size_t conv_rows_lds(int r, int w, int cin, int ps, int nt, bool wlds) {
+  const size_t b = sizeof(bf16) * ((size_t)(r + 2) * (w + 2) * ps +
+                                   (wlds ? (size_t)16 * nt * (9 * cin + 8) : 0));
   return b <= 65536 ? b : 0;
 }
 
@@ -1182,14 +1227,24 @@ void conv_launch(const ConvSrc &x, int32_t batch, int32_t h, int32_t w, const bf
     if (pix % w || h % (pix / w)) continue;
     const int r = pix / w;
     const int ps = cin;  // pixel stride in LDS (padding it measured no faster)
-    const size_t lds = conv_rows_lds(r, w, cin, ps, nt);
+    // band and weights within 64 KB of LDS; for 16 output channels the
+    // weights are read from global memory instead where the two exceed 48 KB
+    // (three workgroups then fit a CU instead of two; with more output
+    // channels that measured slower)
+    const size_t with_w = conv_rows_lds(r, w, cin, ps, nt, true);
     const int64_t wgs = (int64_t)batch * (h / r) * cot;
-    if (!lds || wgs < 256) continue;
+    if (!with_w || wgs < 256) continue;
+    const bool wlds = nt > 1 || with_w <= 49152;
+    const size_t lds = conv_rows_lds(r, w, cin, ps, nt, wlds);
     const dim3 grid((unsigned)(batch * (h / r)), cot);
     auto go = [&](auto pt_tag, auto nt_tag) {
       constexpr int PT = decltype(pt_tag)::value, NT = decltype(nt_tag)::value;
-      hipLaunchKernelGGL((conv3x3_rows_kernel<PT, NT>), grid, dim3(256), lds, s, x, batch, h, w,
-                         wb, bias, cout, act, slope, dst, y_fp32, r, ps);
+      if (wlds)
+        hipLaunchKernelGGL((conv3x3_rows_kernel<PT, NT, true>), grid, dim3(256), lds, s, x, batch,
+                           h, w, wb, bias, cout, act, slope, dst, y_fp32, r, ps);
+      else
+        hipLaunchKernelGGL((conv3x3_rows_kernel<PT, NT, false>), grid, dim3(256), lds, s, x,
+                           batch, h, w, wb, bias, cout, act, slope, dst, y_fp32, r, ps);
     };
     auto pick = [&](auto pt_tag) {
       if (nt == 1)
@@ -1786,6 +1841,33 @@ extern "C" clb_status clb_nn_adamw(float *p, const float *g, float *m, float *v,
   hipLaunchKernelGGL(adamw_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0,
                      static_cast<hipStream_t>(stream), p, g, m, v, (size_t)n, lr, b1, b2, eps, wd,
                      c1, c2);
+  return launched();
+}
+
+extern "C" clb_status clb_nn_adamw_layers(float *p, const float *g, float *m, float *v,
+                                          int64_t n, float lr, float b1, float b2, float eps,
+                                          float wd, int32_t t, int32_t nlayers,
+                                          const int32_t *cout, const int32_t *cin,
+                                          const int64_t *offset, clb_bf16 *w_fwd,
+                                          clb_bf16 *w_bwd, void *stream) {
+  if (!p || !g || !m || !v || n <= 0 || t < 1 || !w_fwd || !w_bwd || !cout || !cin || !offset ||
+      nlayers < 1 || nlayers > CLB_NN_MAX_LAYERS)
+    return CLB_ERR_ARG;
+  WeightLayers L{};
+  L.n = nlayers;
+  for (int l = 0; l < nlayers; ++l) {
+    if (cout[l] <= 0 || cin[l] <= 0 || offset[l] < 0 || (l && offset[l] <= offset[l - 1]) ||
+        offset[l] + (int64_t)cout[l] * 9 * cin[l] > n)
+      return CLB_ERR_ARG;
+    L.cout[l] = cout[l];
+    L.cin[l] = cin[l];
+    L.offset[l] = offset[l];
+  }
+  const float c1 = (float)(1.0 - std::pow((double)b1, t));
+  const float c2 = (float)(1.0 - std::pow((double)b2, t));
+  hipLaunchKernelGGL(adamw_layers_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), p, g, m, v, (size_t)n, lr, b1, b2, eps, wd,
+                     c1, c2, L, reinterpret_cast<bf16 *>(w_fwd), reinterpret_cast<bf16 *>(w_bwd));
   return launched();
 }
 

@@ -31,6 +31,7 @@ NN_EXPORTS = (
     "clb_nn_conv3x3_split", "clb_nn_conv3x3_wgrad_cat", "clb_nn_weights_bf16_layers",
     "clb_nn_conv3x3_wgrad_parts", "clb_nn_conv3x3_wgrad_cat_parts", "clb_nn_wgrad_reduce_layers",
     "clb_nn_conv3x3_act_grad", "clb_nn_pool2_grad_act", "clb_nn_up2_grad_act",
+    "clb_nn_adamw_layers",
 )
 
 _ready = False
@@ -72,6 +73,8 @@ def lib():
             "clb_nn_mse_workspace_bytes": [i64, sz],
             "clb_nn_mse": [vp, i32, vp, i32, i64, vp, vp, vp, C.c_size_t, vp],
             "clb_nn_adamw": [vp, vp, vp, vp, i64, f32, f32, f32, f32, f32, i32, vp],
+            "clb_nn_adamw_layers": [vp, vp, vp, vp, i64, f32, f32, f32, f32, f32, i32, i32, vp,
+                                    vp, vp, vp, vp, vp],
             "clb_nn_features": [vp, vp, i32, vp, i32, i32, i32, vp, vp],
             "clb_nn_gather": [vp, i32, vp, i32, i64, vp, vp],
             "clb_set_state_device": [vp, i32, vp, i64, f64, f64],
@@ -430,7 +433,12 @@ class UNet:
         return self.loss_d
 
     def adamw(self, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+        """One AdamW step on the flat parameters, refreshing the bfloat16
+        weight copies in the same launch."""
         self.t += 1
-        call("clb_nn_adamw", ptr(self.p), ptr(self.g), ptr(self.m), ptr(self.v), self.nparams,
-             lr, b1, b2, eps, wd, self.t, C.c_void_p(self.stream.cuda_stream))
-        self._refresh_bf16()
+        co, ci, off = self._layer_tab
+        call("clb_nn_adamw_layers", ptr(self.p), ptr(self.g), ptr(self.m), ptr(self.v),
+             self.nparams, lr, b1, b2, eps, wd, self.t, len(self.convs),
+             co.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+             off.ctypes.data_as(C.c_void_p), ptr(self.wf_flat), ptr(self.wb_flat),
+             C.c_void_p(self.stream.cuda_stream))

@@ -175,6 +175,11 @@ def test_network_calls_validate_arguments_on_the_host():
     assert lib.clb_nn_weights_bf16_layers(a16, 65, *tab, a16, a16, None) == B.ERR_ARG
     assert lib.clb_nn_weights_bf16_layers(a16, 2, *tab, a16, a16, None) == B.ERR_ARG  # cout 0
     assert lib.clb_nn_mse(a16, 12, a16, 3, 10, a16, a16, a16, 1 << 20, None) == B.ERR_ARG
+    desc = (np.array([16, 16], dtype=np.int32), np.array([16, 16], dtype=np.int32),
+            np.array([2320, 0], dtype=np.int64))  # offsets must increase
+    dtab = [t.ctypes.data_as(vp) for t in desc]
+    assert lib.clb_nn_adamw_layers(a16, a16, a16, a16, 10000, 1e-3, 0.9, 0.999, 1e-8, 0.0, 1, 2,
+                                   *dtab, a16, a16, None) == B.ERR_ARG
     ns = C.c_int32(0)
     assert lib.clb_nn_conv3x3_wgrad_parts(a16, a16, 2, 16, 16, 16, 32, 1, a16, n.value - 4,
                                           C.byref(ns), None) == B.ERR_ARG  # workspace too small

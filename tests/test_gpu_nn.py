@@ -307,6 +307,41 @@ def test_fused_activation_gradients_match_unfused(nn):
     assert torch.equal(dz.view(torch.int16), ref.view(torch.int16))
 
 
+def test_adamw_layers_matches_adamw_and_weight_copies(nn):
+    """clb_nn_adamw_layers gives the bits of clb_nn_adamw followed by
+    clb_nn_weights_bf16_layers, and leaves the bfloat16 elements outside the
+    layers' weights alone."""
+    import torch
+    r = rng(37)
+    layers = [(16, 16), (32, 16), (16, 48)]
+    offs, n = [], 0
+    for o, c in layers:
+        offs.append(n)
+        n += o * 9 * c + o
+    n += 40  # parameters after the last layer
+    p0, g = r.standard_normal(n).astype(np.float32), r.standard_normal(n).astype(np.float32)
+    m0, v0 = r.standard_normal(n).astype(np.float32), np.abs(r.standard_normal(n)).astype(np.float32)
+    co = np.array([o for o, _ in layers], dtype=np.int32)
+    ci = np.array([c for _, c in layers], dtype=np.int32)
+    off = np.array(offs, dtype=np.int64)
+    tab = [t.ctypes.data_as(C.c_void_p) for t in (co, ci, off)]
+    a = [dev_f32(x) for x in (p0, g, m0, v0)]
+    b = [dev_f32(x) for x in (p0, g, m0, v0)]
+    sentinel = torch.full((n,), 3.0, dtype=torch.bfloat16, device="cuda")
+    wf_a, wb_a, wf_b, wb_b = (sentinel.clone() for _ in range(4))
+    args = (1e-3, 0.9, 0.999, 1e-8, 0.01, 3)
+    nn.call("clb_nn_adamw", *[nn.ptr(x) for x in a], n, *args, None)
+    nn.call("clb_nn_weights_bf16_layers", nn.ptr(a[0]), len(layers), *tab, nn.ptr(wf_a),
+            nn.ptr(wb_a), None)
+    nn.call("clb_nn_adamw_layers", *[nn.ptr(x) for x in b], n, *args, len(layers), *tab,
+            nn.ptr(wf_b), nn.ptr(wb_b), None)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert torch.equal(wf_a.view(torch.int16), wf_b.view(torch.int16))
+    assert torch.equal(wb_a.view(torch.int16), wb_b.view(torch.int16))
+
+
 def test_elementwise_layers(nn):
     r = rng(11)
     Bn, H, W, Cc = 2, 6, 10, 16
