@@ -199,8 +199,14 @@ clb_status clb_create(const clb_params *p, int32_t count, void *d_workspace, siz
                       void *hip_stream, clb_ctx **out);
 
 /* Enqueue n time steps of every active domain on the stream (asynchronous).
- * The last step also records u, v, T for clb_residual.  A kernel fault is
- * reported here or by the next synchronizing call (CLB_ERR_HIP). */
+ * One time step (Section 2) is, per node: the populations streamed in (pull
+ * form of Eqs. 18 and 35), the macroscopic values and the implicit velocity
+ * (Eqs. 20-23 and 36, force of Eq. 4), the boundary reconstruction of wall,
+ * inlet and outlet nodes, the D2Q9 cascaded collision with the porous shift
+ * (Eqs. 11-17, A1) and the D2Q5 collision with the heat-capacity ratio
+ * (Eqs. 28-33, A2).  The last step also records u, v, T for clb_residual.  A
+ * kernel fault is reported here or by the next synchronizing call
+ * (CLB_ERR_HIP). */
 clb_status clb_step(clb_ctx *ctx, int64_t n);
 
 /* Macroscopic fields of one domain at the current time (Eqs. 20-23, 36;
@@ -209,10 +215,11 @@ clb_status clb_step(clb_ctx *ctx, int64_t n);
 clb_status clb_macros(clb_ctx *ctx, int32_t cavity, double *rho, double *u, double *v,
                       double *T);
 
-/* Mean Nusselt number on one side (CLB_WEST..CLB_NORTH): second-order
- * one-sided wall gradient, trapezoid mean over the wall nodes, L and dT of the
- * domain.  nu_local (nullable) receives one value per wall node.  FP64.
- * Synchronizes. */
+/* Mean Nusselt number on one side (CLB_WEST..CLB_NORTH), the heat-transfer
+ * measure of Section 3.2 (the wall-normal temperature gradient scaled by L /
+ * dT, averaged over the wall): second-order one-sided wall gradient,
+ * trapezoid mean over the wall nodes, L and dT of the domain.  nu_local
+ * (nullable) receives one value per wall node.  FP64.  Synchronizes. */
 clb_status clb_nusselt(clb_ctx *ctx, int32_t cavity, int32_t side, double *nu_mean,
                        double *nu_local);
 
