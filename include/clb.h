@@ -330,18 +330,22 @@ clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_
 clb_status clb_set_steps_per_launch(clb_ctx *ctx, int32_t steps);
 
 /* The launch mode: steps per launch (1 or 2) and the width of the two-step
- * tiles in nodes (64 or 128; 128 at creation when every domain is at least
- * that wide, else 64; clb_autotune may change it).  Either pointer may be
- * NULL. */
+ * tiles in nodes: 64 or 128 when every domain uses that width, 0 when each
+ * domain has its own (128 for the domains at least that wide, else 64; a
+ * pair of steps then runs as one launch per width).  At creation: 128 when
+ * every domain is at least that wide, else 64; clb_autotune may change it.
+ * Either pointer may be NULL. */
 clb_status clb_get_steps_per_launch(clb_ctx *ctx, int32_t *steps, int32_t *tile_x);
 
 /* Time the step kernel over the candidate launch shapes on the live state
  * (which the timing runs advance) and keep the fastest; with two steps per
- * launch in effect, also time the two-step kernel with 64-wide tiles and,
- * when some domain is at least 128 wide, 128-wide tiles, and keep the
- * faster.  When cache_path is non-NULL the choice is read from / appended to
- * that text file (one line per context key: key, tile_x, tile_y, blocks and,
- * when timed, the two-step width), keyed by storage and domain sizes.
+ * launch in effect, also time the two-step kernel with 64-wide tiles for
+ * every domain, 128-wide tiles for every domain (when some domain is at
+ * least 128 wide) and per-domain widths (when the widths are mixed), and keep
+ * the fastest.  When cache_path is non-NULL the choice is read from /
+ * appended to that text file (one line per context key: key, tile_x, tile_y,
+ * blocks and, when timed, the two-step width: 64, 128, or 1 for per-domain),
+ * keyed by storage and domain sizes.
  * Synchronizes. */
 clb_status clb_autotune(clb_ctx *ctx, const char *cache_path);
 

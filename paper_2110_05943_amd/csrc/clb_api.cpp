@@ -266,8 +266,8 @@ Layout make_layout(const clb_params *p, int count) {
   L.desc = take(sizeof(CavDesc) * count);
   L.tiles_all = take(sizeof(Tile) * L.max_tiles);
   L.tiles_active = take(sizeof(Tile) * (L.max_tiles + 8));
-  L.tiles2 = take(sizeof(Tile) * (L.max_tiles2 + 8));
-  L.counts = take(sizeof(int32_t) * 5);
+  L.tiles2 = take(sizeof(Tile) * 2 * (L.max_tiles2 + 8));  // a 64- and a 128-wide list
+  L.counts = take(sizeof(int32_t) * 6);
   L.partials = take(sizeof(double) * clb::kRed * L.max_tiles);
   L.gpart = take(sizeof(double) * clb::kRed * L.max_tiles);
   L.results = take(sizeof(double) * clb::kRed * count);
@@ -319,12 +319,16 @@ struct clb_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
   CavDesc *d_desc = nullptr;
-  Tile *d_tiles_all = nullptr, *d_tiles_active = nullptr, *d_tiles2 = nullptr;
-  // Grid of the two-step kernel: the XCD-ordered list length over all
-  // domains; the list itself holds the active domains (its length in
-  // counts[4], which the kernel reads, so graphs survive retirement).
-  int32_t ntiles2 = 0;
-  int tile2_x = clb::kFusedX;  // two-step tile width: 128 when every domain is that wide
+  Tile *d_tiles_all = nullptr, *d_tiles_active = nullptr;
+  // Two-step tile lists, [0] of 64-wide and [1] of 128-wide tiles.  Their
+  // grids (ntiles2) are the XCD-ordered list lengths over all domains of that
+  // width; the lists hold the active domains (lengths in counts[4 + i], which
+  // the kernel reads, so graphs survive retirement).
+  Tile *d_tiles2[2] = {nullptr, nullptr};
+  int32_t ntiles2[2] = {0, 0};
+  // two-step tile width: 0 = per domain (128 for domains at least 128 wide,
+  // else 64), or 64 / 128 for every domain
+  int tile2_mode = 0;
   int32_t *d_counts = nullptr;
   double *d_partials = nullptr, *d_gpart = nullptr, *d_results = nullptr, *d_nu = nullptr,
          *d_nu_local = nullptr, *d_nu_part = nullptr;
@@ -496,41 +500,50 @@ clb_status upload_tiles(clb_ctx *c) {
 // computed by both tiles with identical results.
 int tile2_origin(int i, int tile, int n) { return n >= tile ? std::min(i * tile, n - tile) : 0; }
 
-// The two-step tile list: every tile of every active domain, laid out for the
-// XCDs like the active list, with its length in counts[4].
+// Width of domain k's two-step tiles.
+int tile2_width(const clb_ctx *c, int k) {
+  if (c->tile2_mode) return c->tile2_mode;
+  return c->p[k].nx >= clb::kFusedXWide ? clb::kFusedXWide : clb::kFusedX;
+}
+
+// The two-step tile lists, one per tile width: every tile of every active
+// domain of that width, laid out for the XCDs like the active list, with the
+// lengths in counts[4] (64-wide) and counts[5] (128-wide).
 clb_status upload_tiles2(clb_ctx *c) {
-  std::vector<Tile> order;
-  size_t all = 0;
-  for (int k = 0; k < c->count; ++k) {
-    const int nx = c->p[k].nx, ny = c->p[k].ny;
-    const size_t per = (size_t)((nx + c->tile2_x - 1) / c->tile2_x) *
-                       ((ny + clb::kFusedY - 1) / clb::kFusedY);
-    all += per;
-    if (!c->active[k]) continue;
-    const int w = c->tile2_x, h = clb::kFusedY;
-    const int tx = (nx + w - 1) / w;
-    const int ty = (ny + h - 1) / h;
-    for (int j = 0; j < ty; ++j)
-      for (int i = 0; i < tx; ++i) {
-        const int x0 = tile2_origin(i, w, nx), y0 = tile2_origin(j, h, ny);
-        // interior: the region [x0 - 1, x0 + w] x [y0 - 1, y0 + h] lies in
-        // [1, nx - 2] x [1, ny - 2], so its pulls stay inside the domain
-        const bool interior = x0 >= 2 && x0 + w <= nx - 2 && y0 >= 2 && y0 + h <= ny - 2;
-        order.push_back(Tile{k, x0, y0, interior ? 0 : 1});
-      }
+  for (int wi = 0; wi < 2; ++wi) {
+    const int w = wi ? clb::kFusedXWide : clb::kFusedX, h = clb::kFusedY;
+    std::vector<Tile> order;
+    size_t all = 0;
+    for (int k = 0; k < c->count; ++k) {
+      if (tile2_width(c, k) != w) continue;
+      const int nx = c->p[k].nx, ny = c->p[k].ny;
+      const int tx = (nx + w - 1) / w;
+      const int ty = (ny + h - 1) / h;
+      all += (size_t)tx * ty;
+      if (!c->active[k]) continue;
+      for (int j = 0; j < ty; ++j)
+        for (int i = 0; i < tx; ++i) {
+          const int x0 = tile2_origin(i, w, nx), y0 = tile2_origin(j, h, ny);
+          // interior: the region [x0 - 1, x0 + w] x [y0 - 1, y0 + h] lies in
+          // [1, nx - 2] x [1, ny - 2], so its pulls stay inside the domain
+          const bool interior = x0 >= 2 && x0 + w <= nx - 2 && y0 >= 2 && y0 + h <= ny - 2;
+          order.push_back(Tile{k, x0, y0, interior ? 0 : 1});
+        }
+    }
+    const size_t n = order.size(), m = (n + kXcds - 1) / kXcds;
+    std::vector<Tile> list(m * kXcds, Tile{-1, 0, 0, 0});
+    for (size_t b = 0; b < m * kXcds; ++b) {
+      const size_t t = (b % kXcds) * m + b / kXcds;
+      if (t < n) list[b] = order[t];
+    }
+    c->ntiles2[wi] = (int32_t)((all + kXcds - 1) / kXcds * kXcds);
+    const int32_t n2 = (int32_t)list.size();
+    if (!list.empty())
+      HIPCHK(hipMemcpyAsync(c->d_tiles2[wi], list.data(), sizeof(Tile) * list.size(),
+                            hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_counts + 4 + wi, &n2, sizeof(n2), hipMemcpyHostToDevice,
+                          c->stream));
   }
-  const size_t n = order.size(), m = (n + kXcds - 1) / kXcds;
-  std::vector<Tile> list(m * kXcds, Tile{-1, 0, 0, 0});
-  for (size_t b = 0; b < m * kXcds; ++b) {
-    const size_t t = (b % kXcds) * m + b / kXcds;
-    if (t < n) list[b] = order[t];
-  }
-  c->ntiles2 = (int32_t)((all + kXcds - 1) / kXcds * kXcds);
-  const int32_t n2 = (int32_t)list.size();
-  if (!list.empty())
-    HIPCHK(hipMemcpyAsync(c->d_tiles2, list.data(), sizeof(Tile) * list.size(),
-                          hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->d_counts + 4, &n2, sizeof(n2), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return CLB_OK;
 }
@@ -563,10 +576,19 @@ clb_status launch_one(clb_ctx *c, int write_snap, hipStream_t s) {
   return CLB_OK;
 }
 
+// The two-step launches of one pair of steps (one per tile width in use).
+hipError_t launch_two_lists(clb_ctx *c, int parity, int write_snap, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int wi = 0; wi < 2 && e == hipSuccess; ++wi)
+    if (c->ntiles2[wi] > 0)
+      e = clb::launch_step2(c->d_desc, c->d_tiles2[wi], c->ntiles2[wi], c->d_counts,
+                            c->d_counts + 4 + wi, parity, write_snap, c->storage, c->raw,
+                            c->rows, wi ? clb::kFusedXWide : clb::kFusedX, s);
+  return e;
+}
+
 clb_status launch_two(clb_ctx *c, int write_snap, hipStream_t s) {
-  const hipError_t e =
-      clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts, c->parity, write_snap,
-                        c->storage, c->raw, c->rows, c->tile2_x, s);
+  const hipError_t e = launch_two_lists(c, c->parity, write_snap, s);
   if (e != hipSuccess) return hip_fail(e, "two-step kernel launch");
   return CLB_OK;
 }
@@ -579,8 +601,7 @@ clb_status capture_graph(clb_ctx *c, int p0) {
   const bool two = fused_now(c);
   const int launches = two ? kGraphSteps / 2 : kGraphSteps;
   for (int k = 0; k < launches && err == hipSuccess; ++k)
-    err = two ? clb::launch_step2(c->d_desc, c->d_tiles2, c->ntiles2, c->d_counts, (p0 + k) & 1,
-                                  0, c->storage, c->raw, c->rows, c->tile2_x, c->cap_stream)
+    err = two ? launch_two_lists(c, (p0 + k) & 1, 0, c->cap_stream)
               : clb::launch_step(c->d_desc, c->d_tiles_active, c->d_counts, grid_tiles(c),
                                  (p0 + k) & 1, 0, c->storage, c->raw, c->rows, c->shape,
                                  c->cap_stream);
@@ -624,10 +645,12 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   // cavity, -4.5% on a batch of small domains)
   c->fused = p[0].storage != CLB_STORE_F16;
   // 128-wide two-step tiles (fewer partly used cache lines at the tile
-  // edges) when no domain would leave most of such a tile idle
-  c->tile2_x = clb::kFusedXWide;
+  // edges) when no domain would leave most of such a tile idle, else 64-wide
+  // ones for every domain (per-domain widths, two launches per pair of steps,
+  // measured slower on the 256-cavity batch; clb_autotune times them)
+  c->tile2_mode = clb::kFusedXWide;
   for (int k = 0; k < count; ++k)
-    if (p[k].nx < clb::kFusedXWide) c->tile2_x = clb::kFusedX;
+    if (p[k].nx < clb::kFusedXWide) c->tile2_mode = clb::kFusedX;
   c->p.assign(p, p + count);
   for (auto &q : c->p) {  // host arrays are not kept
     c->rows |= has_rows(q);
@@ -641,7 +664,8 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->d_desc = reinterpret_cast<CavDesc *>(c->ws + lay.desc);
   c->d_tiles_all = reinterpret_cast<Tile *>(c->ws + lay.tiles_all);
   c->d_tiles_active = reinterpret_cast<Tile *>(c->ws + lay.tiles_active);
-  c->d_tiles2 = reinterpret_cast<Tile *>(c->ws + lay.tiles2);
+  c->d_tiles2[0] = reinterpret_cast<Tile *>(c->ws + lay.tiles2);
+  c->d_tiles2[1] = c->d_tiles2[0] + lay.max_tiles2 + 8;
   c->d_counts = reinterpret_cast<int32_t *>(c->ws + lay.counts);
   c->d_partials = reinterpret_cast<double *>(c->ws + lay.partials);
   c->d_gpart = reinterpret_cast<double *>(c->ws + lay.gpart);
@@ -1147,17 +1171,24 @@ extern "C" clb_status clb_set_steps_per_launch(clb_ctx *c, int32_t k) {
 extern "C" clb_status clb_get_steps_per_launch(clb_ctx *c, int32_t *steps, int32_t *tile_x) {
   if (!c) return CLB_ERR_ARG;
   if (steps) *steps = c->fused ? 2 : 1;
-  if (tile_x) *tile_x = c->tile2_x;
+  if (tile_x) {
+    bool w64 = false, w128 = false;
+    for (int k = 0; k < c->count; ++k) (tile2_width(c, k) == clb::kFusedX ? w64 : w128) = true;
+    *tile_x = w64 && w128 ? 0 : (w128 ? clb::kFusedXWide : clb::kFusedX);
+  }
   return CLB_OK;
 }
 
 namespace {
-// Switch the two-step tiles to width w (64 or 128): rebuild the list and drop
-// the graphs that captured the old one.
+// The autotune cache's code for two-step tiles chosen per domain.
+constexpr int kTile2PerDomain = 1;
+
+// Switch the two-step tiles to width w (64 or 128 for every domain, 0 per
+// domain): rebuild the lists and drop the graphs that captured the old ones.
 clb_status set_tile2_width(clb_ctx *c, int w) {
-  if (w != clb::kFusedX && w != clb::kFusedXWide) return CLB_ERR_ARG;
+  if (w != 0 && w != clb::kFusedX && w != clb::kFusedXWide) return CLB_ERR_ARG;
   drop_graphs(c);
-  c->tile2_x = w;
+  c->tile2_mode = w;
   return upload_tiles2(c);
 }
 }  // namespace
@@ -1203,7 +1234,7 @@ extern "C" clb_status clb_autotune(clb_ctx *c, const char *cache_path) {
     if (found.blocks >= 0) {
       const clb_status s = clb_set_launch(c, found.tile_x, found.tile_y, found.blocks);
       if (s != CLB_OK || found_w == 0) return s;
-      return set_tile2_width(c, found_w);
+      return set_tile2_width(c, found_w == kTile2PerDomain ? 0 : found_w);
     }
   }
   const int shapes[][2] = {{0, 0},   {64, 1},  {64, 2},  {64, 4},  {64, 8}, {128, 1},
@@ -1246,16 +1277,19 @@ extern "C" clb_status clb_autotune(clb_ctx *c, const char *cache_path) {
   }
   clb_status s = clb_set_launch(c, best.tile_x, best.tile_y, best.blocks);
   if (s != CLB_OK) return s;
-  // The two-step tile width, when pairs of steps run per launch: 64, and 128
-  // if some domain is that wide, timed the same way (each launch advances two
-  // steps).
+  // The two-step tile width, when pairs of steps run per launch: 64 for every
+  // domain; 128 for every domain if some domain is that wide; per domain if
+  // the widths are mixed; timed the same way (each pair of steps advances two
+  // steps).  The cache records 64, 128, or kTile2PerDomain.
   int best_w = 0;
+  bool have_w = false;
   if (fused_now(c)) {
-    bool wide = false;
-    for (const auto &p : c->p) wide = wide || p.nx >= clb::kFusedXWide;
+    bool wide = false, narrow = false;
+    for (const auto &p : c->p) (p.nx >= clb::kFusedXWide ? wide : narrow) = true;
     float best2_ms = 1e30f;
-    for (int w : {clb::kFusedX, clb::kFusedXWide}) {
+    for (int w : {clb::kFusedX, clb::kFusedXWide, 0}) {
       if (w == clb::kFusedXWide && !wide) continue;
+      if (w == 0 && !(wide && narrow)) continue;
       s = set_tile2_width(c, w);
       if (s != CLB_OK) return s;
       for (int r = 0; r < 1 + std::max(2, reps / 2); ++r) {
@@ -1272,6 +1306,7 @@ extern "C" clb_status clb_autotune(clb_ctx *c, const char *cache_path) {
       if (ms < best2_ms) {
         best2_ms = ms;
         best_w = w;
+        have_w = true;
       }
     }
     s = set_tile2_width(c, best_w);
@@ -1283,7 +1318,7 @@ extern "C" clb_status clb_autotune(clb_ctx *c, const char *cache_path) {
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
     o << key << " " << best.tile_x << " " << best.tile_y << " " << best.blocks;
-    if (best_w) o << " " << best_w;
+    if (have_w) o << " " << (best_w ? best_w : kTile2PerDomain);
     o << "\n";
   }
   return CLB_OK;

@@ -112,12 +112,14 @@ hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
 // mode), tile_x = kFusedX (64) or kFusedXWide (128; the kernel masks the
 // nodes of a domain narrower than the tile); the list holds the tiles of the
 // active domains and may hold padding entries (cav = -1).  ntiles is the grid
-// (workgroups); the kernel reads the list length from counts[4].
-// write_snap records (u, v, theta) of the second step for the residual.
+// (workgroups); the kernel reads the list length from *len (a device int).
+// A context may run two such launches per pair of steps, one per tile width,
+// over disjoint sets of domains.  write_snap records (u, v, theta) of the
+// second step for the residual.
 constexpr int kFusedX = 64, kFusedXWide = 128, kFusedY = 8;
 hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
-                        int parity, int write_snap, int storage, int raw, int rows, int tile_x,
-                        hipStream_t s);
+                        const int32_t *len, int parity, int write_snap, int storage, int raw,
+                        int rows, int tile_x, hipStream_t s);
 hipError_t launch_init(const CavDesc *descs, int32_t cav, int nx, int ny, int parity,
                        const float *uvth /* 3 dense planes or null */, float th_uniform,
                        int storage, hipStream_t s);

@@ -874,19 +874,22 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) s
 // updates; each ring is recomputed by the neighbouring tiles.  The region is
 // in unwrapped coordinates: the ring of a tile at a periodic side holds the
 // wrapped neighbours, and ring nodes outside a walled side are neither
-// computed nor read (boundary nodes gather inward).  counts[4] holds the
-// length of the tile list (the tiles of the active domains; the grid may be
-// longer), counts[2 + parity] the index of the first step, and the kernel
-// passes step + 2 on.  write_snap records (u, v, theta) of the second step.
+// computed nor read (boundary nodes gather inward).  *len holds the length
+// of the tile list (the tiles of the active domains; the grid may be longer),
+// counts[2 + parity] the index of the first step, and the kernel passes
+// step + 2 on (the launches of the 64- and the 128-wide tiles of one pair of
+// steps read and write the same values).  write_snap records (u, v, theta) of
+// the second step.
 template <typename P, int TX, bool RAW, bool ROWS>
 __global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict__ descs,
                                                        const Tile *__restrict__ tiles,
-                                                       int32_t *__restrict__ counts, int parity,
-                                                       int write_snap) {
+                                                       int32_t *__restrict__ counts,
+                                                       const int32_t *__restrict__ len,
+                                                       int parity, int write_snap) {
   using R = typename P::R;
   constexpr int kRegionW = Region<TX>::W, kRegion = Region<TX>::N;
   __shared__ __attribute__((aligned(16))) char lds[RegionPlanes<P, TX>::kBytes];
-  const int ntiles = counts[4];  // the list of the active domains
+  const int ntiles = *len;  // the list of the active domains
   const uint32_t step = (uint32_t)counts[2 + parity];
   if (blockIdx.x == 0 && threadIdx.x == 0) counts[3 - parity] = (int32_t)(step + 2);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -1270,31 +1273,33 @@ hipError_t launch_step(const CavDesc *descs, const Tile *tiles, int32_t *counts,
 namespace {
 template <typename P, int TX>
 void launch_step2_tx(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
-                     int parity, int write_snap, int raw, int rows, hipStream_t s) {
+                     const int32_t *len, int parity, int write_snap, int raw, int rows,
+                     hipStream_t s) {
   const dim3 grid(ntiles), block(TX * 4);
   if (raw && rows)
     hipLaunchKernelGGL((step2_kernel<P, TX, true, true>), grid, block, 0, s, descs, tiles, counts,
-                       parity, write_snap);
+                       len, parity, write_snap);
   else if (raw)
     hipLaunchKernelGGL((step2_kernel<P, TX, true, false>), grid, block, 0, s, descs, tiles,
-                       counts, parity, write_snap);
+                       counts, len, parity, write_snap);
   else if (rows)
     hipLaunchKernelGGL((step2_kernel<P, TX, false, true>), grid, block, 0, s, descs, tiles,
-                       counts, parity, write_snap);
+                       counts, len, parity, write_snap);
   else
     hipLaunchKernelGGL((step2_kernel<P, TX, false, false>), grid, block, 0, s, descs, tiles,
-                       counts, parity, write_snap);
+                       counts, len, parity, write_snap);
 }
 
 template <typename P>
 hipError_t launch_step2_p(const CavDesc *descs, const Tile *tiles, int32_t ntiles,
-                          int32_t *counts, int parity, int write_snap, int raw, int rows,
-                          int tile_x, hipStream_t s) {
+                          int32_t *counts, const int32_t *len, int parity, int write_snap,
+                          int raw, int rows, int tile_x, hipStream_t s) {
   if (tile_x == kFusedXWide)
-    launch_step2_tx<P, kFusedXWide>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
-                                    s);
+    launch_step2_tx<P, kFusedXWide>(descs, tiles, ntiles, counts, len, parity, write_snap, raw,
+                                    rows, s);
   else if (tile_x == kFusedX)
-    launch_step2_tx<P, kFusedX>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows, s);
+    launch_step2_tx<P, kFusedX>(descs, tiles, ntiles, counts, len, parity, write_snap, raw, rows,
+                                s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1302,21 +1307,21 @@ hipError_t launch_step2_p(const CavDesc *descs, const Tile *tiles, int32_t ntile
 }  // namespace
 
 hipError_t launch_step2(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
-                        int parity, int write_snap, int storage, int raw, int rows, int tile_x,
-                        hipStream_t s) {
+                        const int32_t *len, int parity, int write_snap, int storage, int raw,
+                        int rows, int tile_x, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (storage == 0)  // FP32 planes, FP64 arithmetic
-    return launch_step2_p<StoreF32>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
-                                    tile_x, s);
+    return launch_step2_p<StoreF32>(descs, tiles, ntiles, counts, len, parity, write_snap, raw,
+                                    rows, tile_x, s);
   if (storage == 3)  // FP32 planes, FP32 arithmetic
-    return launch_step2_p<StoreF32C>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
-                                     tile_x, s);
+    return launch_step2_p<StoreF32C>(descs, tiles, ntiles, counts, len, parity, write_snap, raw,
+                                     rows, tile_x, s);
   if (storage == 1)  // FP16 planes
-    return launch_step2_p<StoreF16>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
-                                    tile_x, s);
+    return launch_step2_p<StoreF16>(descs, tiles, ntiles, counts, len, parity, write_snap, raw,
+                                    rows, tile_x, s);
   if (storage == 2)  // FP16 flow, FP32 temperature planes
-    return launch_step2_p<StoreMix>(descs, tiles, ntiles, counts, parity, write_snap, raw, rows,
-                                    tile_x, s);
+    return launch_step2_p<StoreMix>(descs, tiles, ntiles, counts, len, parity, write_snap, raw,
+                                    rows, tile_x, s);
   return hipErrorInvalidValue;
 }
 

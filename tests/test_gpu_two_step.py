@@ -207,9 +207,10 @@ def test_steps_per_launch_argument(B):
 
 def test_wide_tiles_forced_on_a_narrow_domain(B, tmp_path):
     """clb_create picks 64-wide two-step tiles when a domain is narrower
-    than 128; a cached tuning choice can still impose 128-wide tiles on such
-    a context.  The narrow domain then sits in one masked 128 x 8 tile per
-    row band; the results must equal single steps bit for bit."""
+    than 128; a cached tuning choice can impose 128-wide tiles on every
+    domain (the narrow domain then sits in one masked 128 x 8 tile per row
+    band) or per-domain widths (two launches per pair of steps, reported as
+    width 0).  The results must equal single steps bit for bit."""
     cases = [cavity(40, ny=24, Ra=1e4, sigma=1.1), cavity(260, ny=40, Ra=1e5, Da=1e-3, phi=0.5)]
     Ts = [inputs.cavity_initial_T(c["nx"], seed=3 + k, ny=c["ny"]) for k, c in enumerate(cases)]
     nodes = sum(c["nx"] * c["ny"] for c in cases)
@@ -219,14 +220,21 @@ def test_wide_tiles_forced_on_a_narrow_domain(B, tmp_path):
     assert a.get_steps_per_launch() == (2, 64)
     a.autotune(str(cache))
     assert a.get_steps_per_launch() == (2, 128) and a.steps_done == 0
+    cache2 = tmp_path / "tune2.txt"
+    cache2.write_text("storage=0;n=2;nodes=%d;first=40x24 0 0 0 1\n" % nodes)
+    c = B.Solver(cases)
+    c.autotune(str(cache2))
+    assert c.get_steps_per_launch() == (2, 0) and c.steps_done == 0
     b = B.Solver(cases)
     b.set_steps_per_launch(1)
-    for s in (a, b):
+    for s in (a, b, c):
         for k, T in enumerate(Ts):
             s.set_state(k, T)
         s.step(101)
     for k in range(len(cases)):
-        ma, mb = a.macros(k), b.macros(k)
-        log("forced 128-wide tiles, domain %d: bit-identical %s" % (
-            k, all(np.array_equal(ma[q], mb[q]) for q in ma)))
-        assert all(np.array_equal(ma[q], mb[q]) for q in ma)
+        mb = b.macros(k)
+        for name, s in (("forced 128-wide", a), ("per-domain", c)):
+            ms = s.macros(k)
+            same = all(np.array_equal(ms[q], mb[q]) for q in ms)
+            log("%s tiles, domain %d: bit-identical %s" % (name, k, same))
+            assert same
