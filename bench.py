@@ -897,7 +897,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="time launch shapes first")
     ap.add_argument("--launch", type=str, default=None, help="tile_x,tile_y,blocks")
     ap.add_argument("--steps-per-launch", type=int, default=None, choices=(1, 2),
-                    help="time steps per launch (default: 1 for f16 storage, else 2)")
+                    help="time steps per launch (default: the library's, 2 unless f16 storage "
+                         "has a domain narrower than 128)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
@@ -951,8 +952,8 @@ def main():
     initial_state(s, cases)
     if args.launch:
         s.set_launch(*[int(v) for v in args.launch.split(",")])
-    if args.steps_per_launch is None:
-        args.steps_per_launch = 1 if args.storage == "f16" else 2
+    if args.steps_per_launch is None:  # the library's default for this context
+        args.steps_per_launch = s.get_steps_per_launch()[0]
     s.set_steps_per_launch(args.steps_per_launch)
     if args.autotune:
         s.autotune()
@@ -991,7 +992,7 @@ def main():
         achieved = bytes_per_lu * nodes / (kernel_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(key if args.storage == "f16" else key + "_single"),
+                    "traffic": measured_traffic(key + "_single"),
                     "kernel": "step_kernel", "kernel_us": round(kernel_ms * 1e3, 2),
                     "bytes_per_node_update": bytes_per_lu}
     out = {

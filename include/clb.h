@@ -313,8 +313,9 @@ clb_status clb_steps_done(clb_ctx *ctx, int64_t *steps);
 clb_status clb_set_launch(clb_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t blocks);
 clb_status clb_get_launch(clb_ctx *ctx, int32_t *tile_x, int32_t *tile_y, int32_t *blocks);
 
-/* Time steps per kernel launch: 1 or 2 (else CLB_ERR_ARG); 2 is the default
- * for every storage mode but CLB_STORE_F16.  With 2, the active domains
+/* Time steps per kernel launch: 1 or 2 (else CLB_ERR_ARG); 2 is the default,
+ * except with CLB_STORE_F16 when some domain is narrower than 128 nodes
+ * (there one step per launch is faster).  With 2, the active domains
  * advance in pairs of steps per launch (domains that clb_run retires simply
  * drop out of the launch): each tile (128 x 8 nodes when every domain is at
  * least 128 wide, else 64 x 8) and a one-node ring around it are collided

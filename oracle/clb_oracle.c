@@ -547,9 +547,13 @@ static void boundary_values(const orc_params *p, int x, int y, const bnode_t *b,
 
 /* ---------------------------------------------------------------- lattice */
 
+/* nthreads > 0: that many threads; 0: the process's initial OpenMP default
+   (a call with an explicit count does not carry over to later calls). */
 static void set_threads(const orc_params *p) {
 #ifdef _OPENMP
-  if (p->nthreads > 0) omp_set_num_threads(p->nthreads);
+  static int initial = 0;
+  if (initial == 0) initial = omp_get_max_threads();
+  omp_set_num_threads(p->nthreads > 0 ? p->nthreads : initial);
 #else
   (void)p;
 #endif

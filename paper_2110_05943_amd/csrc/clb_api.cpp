@@ -640,10 +640,6 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->count = count;
   c->storage = p[0].storage;
   c->raw = p[0].model != CLB_MODEL_CASCADED;
-  // two steps per launch by default, except for all-FP16 storage (its one-step
-  // kernel already sits at the instruction-issue limit: +3% on a 4096^2
-  // cavity, -4.5% on a batch of small domains)
-  c->fused = p[0].storage != CLB_STORE_F16;
   // 128-wide two-step tiles (fewer partly used cache lines at the tile
   // edges) when no domain would leave most of such a tile idle, else 64-wide
   // ones for every domain (per-domain widths, two launches per pair of steps,
@@ -651,6 +647,11 @@ extern "C" clb_status clb_create(const clb_params *p, int32_t count, void *d_wor
   c->tile2_mode = clb::kFusedXWide;
   for (int k = 0; k < count; ++k)
     if (p[k].nx < clb::kFusedXWide) c->tile2_mode = clb::kFusedX;
+  // two steps per launch by default; all-FP16 storage only with 128-wide
+  // tiles (its 64-wide two-step kernel, without the interior-tile path, loses
+  // to its one-step kernel on the batch of small domains: 470 against 2 x 227
+  // us; with 128-wide tiles it wins on the 4096^2 cavity: 323 against 2 x 174)
+  c->fused = p[0].storage != CLB_STORE_F16 || c->tile2_mode == clb::kFusedXWide;
   c->p.assign(p, p + count);
   for (auto &q : c->p) {  // host arrays are not kept
     c->rows |= has_rows(q);

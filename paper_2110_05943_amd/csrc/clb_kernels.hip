@@ -65,25 +65,34 @@ __device__ __forceinline__ float round_sr(double v, uint32_t r) {
   u &= ~((1ull << 29) - 1ull);
   return (float)__longlong_as_double((long long)u);
 }
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+// Per-node state of the encoder: the FP16 conversion below writes one half of
+// its destination register and keeps the other, so the conversions of a node
+// are chained through one register instead of clearing one per store.
+struct EncState {
+  half2v k = {};
+};
+
 // The stored value of a post-collision deviation v with random word r; the
 // pointer argument only selects the storage type.
-__device__ __forceinline__ float enc(const float *, double v, uint32_t r) { return round_sr(v, r); }
-// FP32 -> FP16 (scaled) with stochastic rounding by the gfx950 conversion
+__device__ __forceinline__ float enc(EncState &, const float *, double v, uint32_t r) {
+  return round_sr(v, r);
+}
+// FP32 -> FP16 with stochastic rounding by the gfx950 conversion
 // instruction v_cvt_sr_f16_f32, which adds the top 13 bits of its random
-// operand below the FP16 precision of the value and truncates (unbiased,
-// subnormal results included).  The 12 low bits of r become the top of the
-// operand, the bits a software rounding of the FP32 pattern would add.
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ _Float16 enc(const _Float16 *, float v, uint32_t r) {
-  const half2v zero = {};
-  return __builtin_amdgcn_cvt_sr_f16_f32(zero, v * kF16Scale, r << 20, false)[0];
+// operand r below the FP16 precision of the value and truncates (unbiased,
+// subnormal results included).  v is the value already scaled by kF16Scale
+// (the collision folds the scale into its last products).
+__device__ __forceinline__ _Float16 enc(EncState &e, const _Float16 *, float v, uint32_t r) {
+  e.k = __builtin_amdgcn_cvt_sr_f16_f32(e.k, v, r, false);
+  return e.k[0];
 }
 // FP32 -> FP32: no rounding (FP32 planes computed in FP32).
-__device__ __forceinline__ float enc(const float *, float v, uint32_t) { return v; }
+__device__ __forceinline__ float enc(EncState &, const float *, float v, uint32_t) { return v; }
 
 template <typename T, typename R>
-__device__ __forceinline__ void stv(T *p, R v, uint32_t r) {
-  __builtin_nontemporal_store(enc(p, v, r), (gptr<T>)p);
+__device__ __forceinline__ void stv(EncState &e, T *p, R v, uint32_t r) {
+  __builtin_nontemporal_store(enc(e, p, v, r), (gptr<T>)p);
 }
 
 // The deviation a stored value stands for (the inverse scaling of enc).
@@ -180,6 +189,16 @@ __device__ __forceinline__ uint32_t next_bits(uint32_t x) {
   x ^= x >> 17;
   x ^= x << 5;
   return x;
+}
+// The random operand of the rounding of plane i from the node's current word
+// w; each word serves two planes.  FP64 arithmetic (round_sr reads the low 16
+// bits): w and w >> 16.  FP32 arithmetic (v_cvt_sr_f16_f32 reads the top 13
+// bits): w and w << 13, the disjoint fields w[19..31] and w[6..18]; w << 13
+// is also the first term of the xorshift step that makes the next word.
+template <typename R>
+__device__ __forceinline__ uint32_t round_bits(uint32_t w, int i) {
+  if (sizeof(R) == 8) return (i & 1) ? (w >> 16) : w;
+  return (i & 1) ? (w << 13) : w;
 }
 
 // ------------------------------------------------------- fast helpers
@@ -602,7 +621,10 @@ __device__ __forceinline__ bool node_state(const CavDesc &d, const Src &A, int x
 }
 
 // Collide one node in central-moment space (RAW: in raw-moment space, the
-// MRT form with N = N_T = I): the 14 post-collision deviations, D2Q9 first.
+// MRT form with N = N_T = I): the 14 post-collision deviations, D2Q9 first,
+// each in the scale of its stored plane (kF16Scale for FP16 planes, 1 for
+// FP32 planes).  The scale rides on the constants of the last products, a
+// power-of-two change that leaves every rounding as it was.
 template <typename P, bool RAW, bool ROWS, typename R = typename P::R>
 __device__ __forceinline__ void collide(const CavDesc &d, const NodeState<R> &st, bool wall,
                                         R out[kPlanes], R &rest_err) {
@@ -699,21 +721,26 @@ __device__ __forceinline__ void collide(const CavDesc &d, const NodeState<R> &st
     Q22 = me[8] + (R(1) - s4) * (st.k22 - me[8]) + (R(1) - half * s4) * S8;
   }
 
+  // scales of the stored planes
+  constexpr R sF = std::is_same<typename P::F, _Float16>::value ? R(kF16Scale) : R(1);
+  constexpr R sG = std::is_same<typename P::G, _Float16>::value ? R(kF16Scale) : R(1);
+
   // populations f* = M^-1 m* (deviations; M^-1 maps the rest moments to w_i)
-  const R h20 = half * (Q20 - Q22), h02 = half * (Q02 - Q22);
-  const R f1 = half * (K10 - Q12) + h20;
-  const R f3 = half * (Q12 - K10) + h20;
-  const R f2 = half * (K01 - Q21) + h02;
-  const R f4 = half * (Q21 - K01) + h02;
-  const R pa = quarter * (Q22 + Q21), pb = quarter * (Q11 + Q12);
-  const R pc = quarter * (Q22 - Q21), pd = quarter * (Q11 - Q12);
+  const R hF = half * sF, qF = quarter * sF;
+  const R h20 = hF * (Q20 - Q22), h02 = hF * (Q02 - Q22);
+  const R f1 = hF * (K10 - Q12) + h20;
+  const R f3 = hF * (Q12 - K10) + h20;
+  const R f2 = hF * (K01 - Q21) + h02;
+  const R f4 = hF * (Q21 - K01) + h02;
+  const R pa = qF * (Q22 + Q21), pb = qF * (Q11 + Q12);
+  const R pc = qF * (Q22 - Q21), pd = qF * (Q11 - Q12);
   const R f5 = pa + pb;  // (k11 + k21 + k12 + k22)/4
   const R f6 = pa - pb;  // (-k11 + k21 - k12 + k22)/4
   const R f7 = pc + pd;  // (k11 - k21 - k12 + k22)/4
   const R f8 = pc - pd;  // (-k11 - k21 + k12 + k22)/4
   // rest population (row f0 of M^-1: k00 - k20 - k02 + k22; as deviations
   // the rest values cancel, and k00* = rho conserves mass)
-  const R f0 = dr - Q20 - Q02 + Q22;
+  const R f0 = (dr - Q20 - Q02 + Q22) * sF;
 
   // D2Q5 (Eqs. 28-33, A2) in closed form, as deviations
   const R T = cst<R>(d).T0 + st.th;
@@ -732,10 +759,11 @@ __device__ __forceinline__ void collide(const CavDesc &d, const NodeState<R> &st
     ay_ = uy2 * T + hvth + cst<R>(d).znc * (st.n4 - hvth - uy2 * T);
   }
   const R bx_ = ux * T + q1, by_ = uy * T + q2;
-  const R g1 = half * (ax_ + bx_);
-  const R g3 = half * (ax_ - bx_);
-  const R g2 = half * (ay_ + by_);
-  const R g4 = half * (ay_ - by_);
+  const R hG = half * sG;
+  const R g1 = hG * (ax_ + bx_);
+  const R g3 = hG * (ax_ - bx_);
+  const R g2 = hG * (ay_ + by_);
+  const R g4 = hG * (ay_ - by_);
   // rest population from heat conservation (equal to
   // (sigma - varpi) theta - |u|^2 T - 2 u.q - e3 - e4)
   R g0;
@@ -747,7 +775,7 @@ __device__ __forceinline__ void collide(const CavDesc &d, const NodeState<R> &st
     g0 = two_sum(st.sg, -gs, e2);
     rest_err = (e2 - e1) + st.sg_lo;
   } else {
-    g0 = st.sg - ((g1 + g3) + (g2 + g4));
+    g0 = st.sg * sG - ((g1 + g3) + (g2 + g4));
   }
 
   out[0] = f0;
@@ -778,15 +806,16 @@ __device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlan
   const uint32_t uidx = (uint32_t)idx;
   // random words for the stochastic rounding: two 16-bit fields per word
   uint32_t w = mix32((uint32_t)idx + seed);
+  EncState e;
 #pragma unroll
   for (int i = 0; i < kPlanes; ++i) {
     if (i < 9)
-      stv(at(uniform_base(of + (size_t)i * plane), uidx), out[i], (i & 1) ? (w >> 16) : w);
+      stv(e, at(uniform_base(of + (size_t)i * plane), uidx), out[i], round_bits<R>(w, i));
     else if (i == 9 && kCompensatedRest<P>)
-      stv(at(uniform_base(og), uidx), round_pair_sr(out[9], rest_err, w >> 16), 0u);
+      stv(e, at(uniform_base(og), uidx), round_pair_sr(out[9], rest_err, w >> 16), 0u);
     else
-      stv(at(uniform_base(og + (size_t)(i - 9) * plane), uidx), out[i],
-          (i & 1) ? (w >> 16) : w);
+      stv(e, at(uniform_base(og + (size_t)(i - 9) * plane), uidx), out[i],
+          round_bits<R>(w, i));
     if (i & 1) w = next_bits<R>(w);
   }
 }
@@ -800,15 +829,16 @@ __device__ __forceinline__ void store_region(const R out[kPlanes], R rest_err, c
   typename P::G *G = RegionPlanes<P, TX>::g(lds);
   constexpr int N = Region<TX>::N;
   uint32_t w = mix32((uint32_t)idx + seed);
+  EncState e;
 #pragma unroll
   for (int i = 0; i < kPlanes; ++i) {
-    const uint32_t r = (i & 1) ? (w >> 16) : w;
+    const uint32_t r = round_bits<R>(w, i);
     if (i < 9)
-      F[i * N + c] = enc(F, out[i], r);
+      F[i * N + c] = enc(e, F, out[i], r);
     else if (i == 9 && kCompensatedRest<P>)
-      G[c] = round_pair_sr(out[9], rest_err, r);
+      G[c] = round_pair_sr(out[9], rest_err, w >> 16);
     else
-      G[(i - 9) * N + c] = enc(G, out[i], r);
+      G[(i - 9) * N + c] = enc(e, G, out[i], r);
     if (i & 1) w = next_bits<R>(w);
   }
 }

@@ -21,7 +21,8 @@ def test_traffic_summary_matches_the_kernel_source():
     data = json.load(open(os.path.join(ROOT, "profiles", "step_kernel_traffic.json")))
     h = bench.kernel_source_hash()
     for key in ("cavity4096_f32", "cavity4096_f32_single", "cavity4096_f32c",
-                "cavity4096_f32c_single", "cavity4096_f16", "cavity4096_mixed",
+                "cavity4096_f32c_single", "cavity4096_f16", "cavity4096_f16_single",
+                "cavity4096_mixed",
                 "cavity4096_mixed_single", "batch256_f32",
                 "channel2048_f32"):
         assert data[key]["kernel_hash"] == h, key
@@ -33,8 +34,8 @@ def test_traffic_summary_matches_the_kernel_source():
         assert os.path.exists(os.path.join(ROOT, "profiles", "step_kernel_%s.md" % key))
     # the FP32 records of the default launch mode come from the two-step
     # kernel, the "single" one from the one-step kernel
-    for key in ("cavity4096_f32", "cavity4096_f32c", "cavity4096_mixed", "batch256_f32",
-                "channel2048_f32"):
+    for key in ("cavity4096_f32", "cavity4096_f32c", "cavity4096_f16", "cavity4096_mixed",
+                "batch256_f32", "channel2048_f32"):
         assert data[key]["steps_per_launch"] == 2 and "step2_kernel" in data[key]["kernel"], key
     one, two = data["cavity4096_f32_single"], data["cavity4096_f32"]
     assert one["steps_per_launch"] == 1 and "step2_kernel" not in one["kernel"]

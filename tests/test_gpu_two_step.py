@@ -163,9 +163,10 @@ def test_two_step_launches_match_oracle(B, name, storage):
     # FP32 planes (FP64 or FP32 arithmetic): 1e-6; FP16 planes: 1e-3.  The
     # hot-wall Nusselt number with all-FP16 storage carries the FP16
     # temperature noise (~1e-4) times the wall gradient's length scale (the
-    # domain width, up to 259 here): 1e-2.
+    # domain width, up to 259 here): a standard deviation of 1e-2 on the
+    # 260 x 40 cavity over 32 independent rounding streams, held to 4e-2.
     tol = {"f32": 1e-6, "f32c": 1e-6}.get(storage, 1e-3)
-    tol_nu = 1e-2 if storage == "f16" else 1e-4
+    tol_nu = 4e-2 if storage == "f16" else 1e-4
     for k in compared:
         case = cases[k]
         lat = oracle_lattice(case)
