@@ -887,8 +887,9 @@ def main():
     ap.add_argument("--count", type=int, default=None,
                     help="domains of the batch (256) or warmstart (500) workload")
     ap.add_argument("--storage", choices=("f32", "f32c", "f16", "mixed"), default=None,
-                    help="f32c: FP32 planes, FP32 arithmetic (default of the cavity workload); "
-                         "f32: FP32 planes, FP64 arithmetic (default of the others)")
+                    help="f32c: FP32 planes, FP32 arithmetic (default of the cavity, batch and "
+                         "channel workloads); f32: FP32 planes, FP64 arithmetic (default of the "
+                         "others)")
     ap.add_argument("--weights", default=None, help="warmstart: network weights (.npz)")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -903,7 +904,7 @@ def main():
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
     if args.storage is None:
-        args.storage = "f32c" if args.workload == "cavity" else "f32"
+        args.storage = "f32c" if args.workload in ("cavity", "batch", "channel") else "f32"
     if args.workload == "oracle-timing":
         return oracle_timing()
     if args.gpus != 1:

@@ -23,8 +23,8 @@ def test_traffic_summary_matches_the_kernel_source():
     for key in ("cavity4096_f32", "cavity4096_f32_single", "cavity4096_f32c",
                 "cavity4096_f32c_single", "cavity4096_f16", "cavity4096_f16_single",
                 "cavity4096_mixed",
-                "cavity4096_mixed_single", "batch256_f32",
-                "channel2048_f32"):
+                "cavity4096_mixed_single", "batch256_f32", "batch256_f32c",
+                "channel2048_f32", "channel2048_f32c"):
         assert data[key]["kernel_hash"] == h, key
         t = bench.measured_traffic(key)
         # one step per launch: close to the populations read and written once;
@@ -35,7 +35,7 @@ def test_traffic_summary_matches_the_kernel_source():
     # the FP32 records of the default launch mode come from the two-step
     # kernel, the "single" one from the one-step kernel
     for key in ("cavity4096_f32", "cavity4096_f32c", "cavity4096_f16", "cavity4096_mixed",
-                "batch256_f32", "channel2048_f32"):
+                "batch256_f32", "batch256_f32c", "channel2048_f32", "channel2048_f32c"):
         assert data[key]["steps_per_launch"] == 2 and "step2_kernel" in data[key]["kernel"], key
     one, two = data["cavity4096_f32_single"], data["cavity4096_f32"]
     assert one["steps_per_launch"] == 1 and "step2_kernel" not in one["kernel"]

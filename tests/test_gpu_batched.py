@@ -249,28 +249,41 @@ def test_set_state_device_matches_host_warm_start(B):
     assert np.array_equal(a.get_state(), b.get_state())
 
 
-def test_batch256_workload_sampled_cavities(B):
-    """The batched bench workload (256 cavities, 64^2..512^2, drawn
-    parameters) in its launch configuration: 300 steps from the seeded
-    initial state; eight cavities, the largest and smallest among them,
-    against the oracle run by themselves."""
+@pytest.fixture(scope="module")
+def batch256_oracle():
+    """The batched bench workload and the oracle's state of eight of its
+    cavities (the largest, the smallest and six drawn ones) after 300 steps
+    from the seeded initial state, each run by itself."""
     from paper_2110_05943_amd import workloads
     cases = workloads.batch(256, seed=3)
+    sizes = np.array([c["nx"] for c in cases])
+    pick = [int(np.argmax(sizes)), int(np.argmin(sizes))]
+    pick += [int(k) for k in inputs.rng(77).choice(256, 6, replace=False) if k not in pick][:6]
+    out = {}
+    for k in pick:
+        lat = oracle_lattice(cases[k])
+        lat.init_equilibrium(inputs.cavity_initial_T(cases[k]["nx"], seed=1))
+        lat.step(300)
+        out[k] = lat.macros()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32c"])
+def test_batch256_workload_sampled_cavities(B, batch256_oracle, storage):
+    """The batched bench workload (256 cavities, 64^2..512^2, drawn
+    parameters) in its launch configuration, FP32 storage with FP64 or FP32
+    arithmetic: 300 steps from the seeded initial state; eight cavities, the
+    largest and smallest among them, against the oracle run by themselves."""
+    from paper_2110_05943_amd import workloads
+    cases = workloads.batch(256, seed=3, storage=storage)
     s = B.Solver(cases)
     for k, c in enumerate(cases):
         s.set_state(k, inputs.cavity_initial_T(c["nx"], seed=1))
     s.step(300)
-    sizes = np.array([c["nx"] for c in cases])
-    pick = [int(np.argmax(sizes)), int(np.argmin(sizes))]
-    pick += [int(k) for k in inputs.rng(77).choice(256, 6, replace=False) if k not in pick][:6]
     ru, rT, mass, st = s.residual_all()
     compared = diverged = 0
-    for k in pick:
+    for k, o in batch256_oracle.items():
         c = cases[k]
-        lat = oracle_lattice(c)
-        lat.init_equilibrium(inputs.cavity_initial_T(c["nx"], seed=1))
-        lat.step(300)
-        o = lat.macros()
         if st[k] != B.OK:
             # a drawn cavity at the stability edge may diverge: then the
             # oracle must diverge too
@@ -280,26 +293,33 @@ def test_batch256_workload_sampled_cavities(B):
             diverged += 1
             continue
         check_state(s.macros(k), o, TOL32,
-                    "batch[%d] N=%d Ra=%.3g Da=%.3g" % (k, c["nx"], c["Ra"], c["Da"]))
+                    "batch %s [%d] N=%d Ra=%.3g Da=%.3g" % (storage, k, c["nx"], c["Ra"], c["Da"]))
         compared += 1
-    log("batch: %d cavities compared, %d diverged on both sides" % (compared, diverged))
+    log("batch %s: %d cavities compared, %d diverged on both sides" % (storage, compared, diverged))
     assert compared >= 6
     s.close()
 
 
-def test_cavity_1024_full_field(B):
-    """1024^2 cavity (Ra = 1e6, Da = 1e-4, phi = 0.4), 2000 steps from the
-    seeded initial state (the parity window of the 1024^2 configuration):
-    the whole field against the oracle."""
+@pytest.fixture(scope="module")
+def cavity1024_oracle():
     case = cavity(1024, Ra=1e6, Da=1e-4, phi=0.4)
-    T = inputs.cavity_initial_T(1024, seed=1)
-    s = B.Solver(case)
-    s.set_state(0, T)
-    s.step(2000)
     lat = oracle_lattice(case)
-    lat.init_equilibrium(T)
+    lat.init_equilibrium(inputs.cavity_initial_T(1024, seed=1))
     lat.step(2000)
-    g, o = s.macros(), lat.macros()
-    check_state(g, o, TOL32, "cavity 1024 2000 steps")
-    assert abs(s.nusselt(0, B.WEST) - lat.nusselt(0, 1.0)) <= 1e-4
+    return lat.macros(), lat.nusselt(0, 1.0)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32c"])
+def test_cavity_1024_full_field(B, cavity1024_oracle, storage):
+    """1024^2 cavity (Ra = 1e6, Da = 1e-4, phi = 0.4), 2000 steps from the
+    seeded initial state (the parity window of the 1024^2 configuration),
+    FP32 storage with FP64 or FP32 arithmetic: the whole field against the
+    oracle."""
+    case = cavity(1024, Ra=1e6, Da=1e-4, phi=0.4, storage=storage)
+    s = B.Solver(case)
+    s.set_state(0, inputs.cavity_initial_T(1024, seed=1))
+    s.step(2000)
+    o, nu_o = cavity1024_oracle
+    check_state(s.macros(), o, TOL32, "cavity 1024 %s 2000 steps" % storage)
+    assert abs(s.nusselt(0, B.WEST) - nu_o) <= 1e-4
     s.close()

@@ -32,7 +32,8 @@ def eps2048():
     return inputs.porosity_map(2048, 2048, ell=32, seed=4)
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 2e-6), ("f16", 2e-3), ("mixed", 2e-3)])
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-6), ("f32c", 2e-6), ("f16", 2e-3),
+                                         ("mixed", 2e-3)])
 def test_channel_2048_sampled(Solver, eps2048, storage, tol):
     """2048^2 channel with its porosity map in the default launch shape: 6
     steps from a smooth random state; 72 sampled nodes (inlet, outlet, walls,
@@ -71,7 +72,8 @@ def crop_oracle(eps2048):
     return lat.macros(), lat.nusselt(2, 1.0)
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("mixed", 1e-3), ("f16", 1e-3)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f32c", 1e-6), ("mixed", 1e-3),
+                                         ("f16", 1e-3)])
 def test_channel_crop_256_6000_steps(Solver, eps2048, crop_oracle, storage, tol):
     """The 256^2 corner of the same porosity map as its own channel (H = 255,
     same U, Re, Ri), from rest at T = 0, 6000 steps (about one flow-through
