@@ -384,6 +384,15 @@ struct GlobalSrc {
   }
 };
 
+// Threads of a two-step workgroup: four per tile column, so that the tile
+// takes two passes of the second step.  The 64-wide kernel with FP32 planes
+// and FP32 arithmetic takes eight: its 37 KB of LDS and 55 VGPRs then hold
+// eight waves per SIMD instead of four (5% faster on the 256-cavity batch;
+// slower for the other storage modes and for 128-wide tiles, whose LDS
+// allows only two workgroups per CU).
+template <typename P, int TX>
+constexpr int kThreads2 = (TX == kFusedX && std::is_same<P, StoreF32C>::value) ? 8 * TX : 4 * TX;
+
 // The LDS region of a two-step tile TX x kFusedY: the tile plus a one-node ring.
 template <int TX>
 struct Region {
@@ -895,8 +904,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) s
 // ------------------------------------------------------- two-step kernel
 
 // Two time steps of every tile of a two-step tile list (TX x kFusedY nodes,
-// TX = 64 or 128, 4 TX threads: four waves per SIMD either way, as LDS
-// allows) in one launch, any storage policy P.  Step one collides the tile
+// TX = 64 or 128, kThreads2<P, TX> threads) in one launch, any storage
+// policy P.  Step one collides the tile
 // and a one-node ring around it from the source buffer into LDS, in the
 // storage types of P and with the values a stored step would hold (the same
 // stochastic rounding); step two collides the tile again from LDS and stores
@@ -911,7 +920,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) s
 // steps read and write the same values).  write_snap records (u, v, theta) of
 // the second step.
 template <typename P, int TX, bool RAW, bool ROWS>
-__global__ void __launch_bounds__(TX * 4) step2_kernel(const CavDesc *__restrict__ descs,
+__global__ void __launch_bounds__((kThreads2<P, TX>)) step2_kernel(const CavDesc *__restrict__ descs,
                                                        const Tile *__restrict__ tiles,
                                                        int32_t *__restrict__ counts,
                                                        const int32_t *__restrict__ len,
@@ -1305,7 +1314,7 @@ template <typename P, int TX>
 void launch_step2_tx(const CavDesc *descs, const Tile *tiles, int32_t ntiles, int32_t *counts,
                      const int32_t *len, int parity, int write_snap, int raw, int rows,
                      hipStream_t s) {
-  const dim3 grid(ntiles), block(TX * 4);
+  const dim3 grid(ntiles), block(kThreads2<P, TX>);
   if (raw && rows)
     hipLaunchKernelGGL((step2_kernel<P, TX, true, true>), grid, block, 0, s, descs, tiles, counts,
                        len, parity, write_snap);
