@@ -206,6 +206,22 @@ def test_steps_per_launch_argument(B):
             s.set_steps_per_launch(3)
 
 
+def test_default_launch_mode(B):
+    """At creation: two steps per launch, on 128-wide tiles when every domain
+    is at least 128 wide, else on 64-wide ones; all-FP16 storage takes two
+    steps per launch only with 128-wide tiles, else one."""
+    wide, mixed = [(260, 40)], [(40, 24), (260, 40)]
+    for st in ("f32", "f32c", "mixed", "f16"):
+        s = B.Solver([cavity(nx, ny=ny, storage=st) for nx, ny in wide])
+        assert s.get_steps_per_launch() == (2, 128), st
+        s.close()
+        s = B.Solver([cavity(nx, ny=ny, storage=st) for nx, ny in mixed])
+        assert s.get_steps_per_launch()[0] == (1 if st == "f16" else 2), st
+        if st != "f16":
+            assert s.get_steps_per_launch() == (2, 64), st
+        s.close()
+
+
 def test_wide_tiles_forced_on_a_narrow_domain(B, tmp_path):
     """clb_create picks 64-wide two-step tiles when a domain is narrower
     than 128; a cached tuning choice can impose 128-wide tiles on every
