@@ -813,15 +813,18 @@ __device__ __forceinline__ void store_planes(const CavDesc &d, const R out[kPlan
   typename P::F *of = const_cast<typename P::F *>(fplanes<P>(buf));
   typename P::G *og = const_cast<typename P::G *>(gplanes<P>(buf, plane));
   const uint32_t uidx = (uint32_t)idx;
-  // random words for the stochastic rounding: two 16-bit fields per word
+  // random words for the stochastic rounding: two fields per word (the
+  // compensated rest population, the only rounding of that policy, takes the
+  // node's first word)
   uint32_t w = mix32((uint32_t)idx + seed);
+  const uint32_t w0 = w;
   EncState e;
 #pragma unroll
   for (int i = 0; i < kPlanes; ++i) {
     if (i < 9)
       stv(e, at(uniform_base(of + (size_t)i * plane), uidx), out[i], round_bits<R>(w, i));
     else if (i == 9 && kCompensatedRest<P>)
-      stv(e, at(uniform_base(og), uidx), round_pair_sr(out[9], rest_err, w >> 16), 0u);
+      stv(e, at(uniform_base(og), uidx), round_pair_sr(out[9], rest_err, w0 >> 16), 0u);
     else
       stv(e, at(uniform_base(og + (size_t)(i - 9) * plane), uidx), out[i],
           round_bits<R>(w, i));
@@ -838,6 +841,7 @@ __device__ __forceinline__ void store_region(const R out[kPlanes], R rest_err, c
   typename P::G *G = RegionPlanes<P, TX>::g(lds);
   constexpr int N = Region<TX>::N;
   uint32_t w = mix32((uint32_t)idx + seed);
+  const uint32_t w0 = w;
   EncState e;
 #pragma unroll
   for (int i = 0; i < kPlanes; ++i) {
@@ -845,7 +849,7 @@ __device__ __forceinline__ void store_region(const R out[kPlanes], R rest_err, c
     if (i < 9)
       F[i * N + c] = enc(e, F, out[i], r);
     else if (i == 9 && kCompensatedRest<P>)
-      G[c] = round_pair_sr(out[9], rest_err, w >> 16);
+      G[c] = round_pair_sr(out[9], rest_err, w0 >> 16);
     else
       G[(i - 9) * N + c] = enc(e, G, out[i], r);
     if (i & 1) w = next_bits<R>(w);
