@@ -9,7 +9,9 @@ and must lie within 2% of the paper's "Present" column.  The nine Da = 1e-6
 cases are run from the conduction profile for a fixed number of steps and
 logged: on the paper's 256^2 grid the method's steady values lie 1-9% above
 the paper's (a grid study of those cases is `bench.py --workload
-table1-grid`); the test bounds them loosely.
+table1-grid`); the test bounds them loosely.  The nine Da = 1e-2 cases also
+run with FP32 arithmetic (the benchmark's precision mode) against FP64
+arithmetic.
 """
 import sys
 
@@ -69,6 +71,32 @@ def test_table1_resolved_darcy_numbers_within_two_percent(B):
     assert np.all(r["status"] == B.OK), r["status"]
     assert max(devs) <= 0.02
     s.close()
+
+
+@pytest.mark.timeout(600)
+def test_table1_fp32_arithmetic_steady_states(B):
+    """The nine Da = 1e-2 cavities of Table 1 (128^2) with FP32 storage and
+    FP32 arithmetic (compensated heat sums) and with FP64 arithmetic, 1e6
+    steps from rest (past the steady state of every one; a retirement test
+    would stop the two at different points of the slowest thermal mode):
+    the steady Nusselt numbers of the two agree within 1e-5 and lie within
+    1% of the paper's."""
+    ref = rows((1e-2,))
+    nus = {}
+    for st in ("f32", "f32c"):
+        cases = [cavity(GRID[Da], Ra=Ra, Da=Da, phi=phi, Pr=1.0, storage=st)
+                 for Da, Ra, phi, _ in ref]
+        s = B.Solver(cases)
+        for k, c in enumerate(cases):
+            s.set_state(k, inputs.cavity_initial_T(c["nx"], seed=1))
+        s.step(1_000_000)
+        nus[st] = np.array([s.nusselt(k, B.WEST) for k in range(len(cases))])
+        s.close()
+    for k, (Da, Ra, phi, paper) in enumerate(ref):
+        log("Da=%g Ra=%g phi=%.1f: Nu FP64 arithmetic %.6f, FP32 arithmetic %.6f, paper %.4f"
+            % (Da, Ra, phi, nus["f32"][k], nus["f32c"][k], paper))
+    assert np.max(np.abs(nus["f32c"] - nus["f32"])) <= 1e-5
+    assert np.max(np.abs(nus["f32c"] / np.array([p for *_, p in ref]) - 1)) <= 0.01
 
 
 @pytest.mark.timeout(600)
