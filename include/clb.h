@@ -68,10 +68,14 @@ enum { CLB_WEST = 0, CLB_EAST = 1, CLB_SOUTH = 2, CLB_NORTH = 3 };
  *   CLB_STORE_F16:   14 FP16 planes (56 B), FP32 arithmetic;
  *   CLB_STORE_MIXED: 9 FP16 flow planes and 5 FP32 temperature planes (76 B),
  *                    FP32 arithmetic;
- *   CLB_STORE_F32C:  14 FP32 planes (112 B), FP32 arithmetic; the D2Q5
- *                    rest population's last subtraction is formed in FP64
- *                    and rounded stochastically (the one stored value whose
- *                    round-to-nearest bias the thermal field accumulates). */
+ *   CLB_STORE_F32C:  14 FP32 planes (112 B), FP32 arithmetic (FP64 only in
+ *                    the reductions); the node's heat sum (Eq. 36) and the
+ *                    D2Q5 rest population carry the exact errors of their
+ *                    FP32 additions (compensated sums), and the rest
+ *                    population, the one stored value whose round-to-nearest
+ *                    bias the thermal field would accumulate, is rounded
+ *                    stochastically from its compensated value; the other
+ *                    planes round to nearest. */
 enum { CLB_STORE_F32 = 0, CLB_STORE_F16 = 1, CLB_STORE_MIXED = 2, CLB_STORE_F32C = 3 };
 
 /* Collision operator of a domain.
